@@ -1,0 +1,242 @@
+"""Benchmark of the local-expansion-move hot path on one MI355X.
+
+A step is one complete plain-method run on the 450x375 synthetic pair
+(12 planar + 2 quadric segments, 2% occlusion holes, disparity [0,60],
+guided-filter radius 20, cell grids 5/15/25 px, 10 iterations, 1 propagation
++ 7 randomisation candidates per region and level): set-up of the guide
+statistics, random init and per-pixel costs, then every group step of
+Alg. 2 (fused cost kernel, device graph terms, host max-flow, label update).
+Inputs are resident in device memory before the timed region starts.
+
+Prints one JSON line.  ``value`` is cost evaluations (phi_p for one pixel
+under one candidate label, including the per-pixel initial costs) per second
+of whole-job wall time, in Gpix*labels/s.  ``roofline`` reports the fused
+cost kernel: algorithmic bytes per launch over its HIP-event duration on its
+launch stream.  ``cpu_baseline`` times the FP64 oracle on a bounded sample of
+the same workload on the host cores and extrapolates to the same unit.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = "lowres-450x375"
+METRIC = "slanted-patch cost evals/s (Gpix*labels/s); time to plain-method final energy"
+HBM_PEAK_GBPS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_unary_lowres-450x375_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1603_08328_amd", "csrc", "lexp_kernels.hip")
+
+
+def _kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def _traffic_from_profile():
+    """HBM bytes per fused-cost launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    vals = {}
+    with open(TRAFFIC_SUMMARY) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != _kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_gpu(steps: int, warmup: int, seed: int = 0):
+    import torch
+
+    import paper_1603_08328_amd.lexp as L
+    from synth import make_workload_pair, params_for, workload
+
+    wl = workload(WORKLOAD)
+    prm = params_for(WORKLOAD)
+    pair = make_workload_pair(WORKLOAD)
+    dev = torch.device("cuda:0")
+    left = torch.from_numpy(pair.left).to(dev)
+    right = torch.from_numpy(pair.right).to(dev)
+    h, w = pair.left.shape[:2]
+    labels = torch.zeros((h, w, 4), dtype=torch.float32, device=dev)
+    cost = torch.zeros((h, w), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def one_step(timing):
+        ctx = L.lexp_create(prm, left, right, stream)
+        L.lexp_set_timing(ctx, timing)
+        e, t = L.lexp_optimize(ctx, wl["grids"], wl["iterations"], seed, labels, cost, stream)
+        st = L.lexp_get_stats(ctx)
+        ctx.close()
+        return e, t, st
+
+    for _ in range(warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = [one_step(True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    evals = sum(r[2]["unary_evals"] for r in results) + steps * h * w  # + per-pixel initial costs
+    kms = sum(r[2]["unary_kernel_ms"] for r in results)
+    kbytes = sum(r[2]["unary_alg_bytes"] for r in results)
+    launches = sum(r[2]["unary_launches"] for r in results)
+    e_final = float(results[-1][0][-1])
+    return dict(elapsed=elapsed, evals=evals, kernel_ms=kms, kernel_bytes=kbytes, launches=launches,
+                energy=[float(x) for x in results[-1][0]], times=[float(x) for x in results[-1][1]],
+                final_energy=e_final, stats=results[-1][2], final_labels=labels.cpu().numpy())
+
+
+def run_cpu_baseline():
+    """The oracle on a bounded sample of the same workload: initial per-pixel
+    costs of the regions of the first 16/8/4 cells of group 0 at grid levels
+    5/15/25 px, and the 8 proposer steps of those cells at iteration 0 (cells
+    in parallel on all host threads).  The per-eval times of the two parts are
+    weighted by the full run's counts to give evals/s in the metric's unit."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import Oracle
+    from synth import make_workload_pair, params_for, workload
+
+    wl = workload(WORKLOAD)
+    prm = params_for(WORKLOAD)
+    pair = make_workload_pair(WORKLOAD)
+    ora = Oracle(prm, pair.left, pair.right)
+    threads = Oracle.num_threads()
+    h, w = pair.left.shape[:2]
+    labels = ora.init_labels(0)
+    costs = np.zeros((h, w))
+    n_cells = {5: 16, 15: 8, 25: 4}
+    t_a5 = 0.0
+    n_a5 = 0
+    t_exp = {}
+    n_exp = {}
+    for level, (cell, kp, kr) in enumerate(wl["grids"]):
+        nci = -(-w // cell)
+        cells = [(i, 0) for i in range(0, nci, 4)][: n_cells[cell]]
+        rects = [((i - 1) * cell, (j - 1) * cell, (i + 2) * cell, (j + 2) * cell) for i, j in cells]
+        mask = np.zeros((h, w), np.uint8)
+        for u0, v0, u1, v1 in rects:
+            mask[max(v0, 0):v1, max(u0, 0):u1] = 1
+        t0 = time.perf_counter()
+        c = ora.pixel_costs(labels, mask)
+        t_a5 += time.perf_counter() - t0
+        n_a5 += int(mask.sum())
+        m = mask.astype(bool)
+        costs[m] = c[m]
+
+        def run_cell(q):
+            i, j = cells[q]
+            for step in range(kp + kr):
+                a = ora.propose(labels, 0, 0, level, cell, i, j, step, kp, prm["disp_max"] / 2, 1.0)
+                ora.expand(labels, costs, rects[q], a)
+
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(run_cell, range(len(cells))))
+        t_exp[cell] = time.perf_counter() - t0
+        n_exp[cell] = sum((min(u1, w) - max(u0, 0)) * (min(v1, h) - max(v0, 0)) for u0, v0, u1, v1 in rects) \
+            * (kp + kr)
+    # full-run counts per level (evaluations of every expansion) and of the init
+    full = {}
+    for level, (cell, kp, kr) in enumerate(wl["grids"]):
+        nci, ncj = -(-w // cell), -(-h // cell)
+        tot = 0
+        for j in range(ncj):
+            for i in range(nci):
+                u0, v0, u1, v1 = max((i - 1) * cell, 0), max((j - 1) * cell, 0), min((i + 2) * cell, w), \
+                    min((j + 2) * cell, h)
+                tot += (u1 - u0) * (v1 - v0)
+        full[cell] = tot * (kp + kr) * wl["iterations"]
+    full_evals = h * w + sum(full.values())
+    full_time = h * w * (t_a5 / n_a5) + sum(full[c] * t_exp[c] / n_exp[c] for c in full)
+    sample_time = t_a5 + sum(t_exp.values())
+    return dict(value=full_evals / full_time / 1e9, cores=threads, sample_s=sample_time,
+                sample=(f"oracle FP64: initial costs of {n_a5} px and 8 proposer steps of the first 16/8/4 "
+                        f"cells of group 0 at levels 5/15/25 px ({sum(n_exp.values())} evals); per-eval times "
+                        f"weighted by the full run's counts ({full_evals} evals)"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (for counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path runs on a single "
+              "MI355X; see the design notes for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration_mib:
+        import torch
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+    g = run_gpu(args.steps, args.warmup)
+    ms = g["elapsed"] / args.steps * 1e3
+    value = g["evals"] / g["elapsed"] / 1e9
+    achieved = g["kernel_bytes"] / (g["kernel_ms"] / 1e3) / 1e9 if g["kernel_ms"] > 0 else 0.0
+    traffic = _traffic_from_profile()
+    cpu = None
+    if not args.no_cpu_baseline:
+        c = run_cpu_baseline()
+        cpu = {"value": c["value"], "unit": "Gpix*labels/s", "cores": c["cores"], "kind": "oracle",
+               "sample": c["sample"], "sample_seconds": round(c["sample_s"], 2)}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Gpix*labels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "450x375 synthetic pair, 12 planar + 2 quadric segments, 2% holes, "
+                               "disparity [0,60], guided-filter radius 20, cells 5/15/25, 10 iterations, "
+                               "{K_prop,K_rand}={1,7}",
+                   "evals_per_step": g["evals"] // args.steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": "k_unary<0> (fused raw cost + guided filter)",
+                     "launches_per_step": g["launches"] // args.steps,
+                     "avg_launch_us": g["kernel_ms"] / max(g["launches"], 1) * 1e3,
+                     "alg_bytes_per_launch": g["kernel_bytes"] / max(g["launches"], 1)},
+        "cpu_baseline": cpu,
+        "time_to_final_energy_s": g["times"][-1],
+        "final_energy": g["final_energy"],
+        "energy_trace": [round(x, 3) for x in g["energy"]],
+        "kernel_evals_per_s": (g["evals"] / (g["kernel_ms"] / 1e3) / 1e9) if g["kernel_ms"] > 0 else None,
+        "host_cut_ms_per_step": g["stats"]["host_cut_ms"],
+        "host_wait_ms_per_step": g["stats"]["host_wait_ms"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+/*
+ * lexp.h -- C ABI of the MI355X local-expansion-move stereo library.
+ *
+ * Method: Taniai, Matsushita, Sato, Naemura, "Continuous 3D Label Stereo
+ * Matching using Local Expansion Moves" (TPAMI; arXiv 1603.08328).
+ *
+ * Conventions shared by every call
+ *   - Images are HxWx3 float32, row-major HWC, values in [0, 255]; u is the
+ *     column and v the row, both 0-based.
+ *   - A label is a disparity plane d(u, v) = a*u + b*v + c (Eq. (1)).  Label
+ *     fields on the device are HxWx4 float32 (a, b, c, unused).
+ *   - A rectangle is half-open [u0, u1) x [v0, v1); every call clips it to the
+ *     image.  A rectangle that clips to nothing is a no-op item.
+ *   - "device" pointers are HIP device memory owned by the caller (PyTorch
+ *     tensors in the Python binding); "host" pointers are read before return.
+ *   - hip_stream is a hipStream_t (NULL = legacy default stream).  Calls are
+ *     stream-ordered unless stated otherwise.  One context is used from one
+ *     host thread at a time; calls on one context are not re-entrant.
+ *   - Every call returns a status: LEXP_OK (0) or a negative error code.
+ *     Nothing is modified when a call fails its argument validation.
+ *     lexp_last_error() returns a message for the calling thread's last
+ *     failure; it stays valid until the next call on that thread.
+ *
+ * Units of the binary problem: the terms of one expansion are rounded up to
+ * integer multiples of LEXP_QUANTUM (2^-20) of the energy; energy changes
+ * reported as int64 are in those units.
+ */
+#ifndef LEXP_H
+#define LEXP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lexp_status;
+#define LEXP_OK 0
+#define LEXP_EINVAL (-1)  /* invalid argument: null pointer, size, range, overlap, non-finite label */
+#define LEXP_ENOMEM (-2)  /* device or host allocation failed */
+#define LEXP_EDEVICE (-3) /* HIP runtime error (message holds the HIP error string) */
+#define LEXP_ESTATE (-4)  /* the context is unusable after an earlier device error */
+
+#define LEXP_QUANTUM_LOG2 20
+
+typedef struct lexp_ctx lexp_ctx;
+
+typedef struct {
+  float a, b, c;
+} lexp_plane;
+
+typedef struct {
+  int32_t u0, v0, u1, v1;
+} lexp_rect;
+
+/* Parameters of the energy (Sec. 3.2) and of the guided filter.
+ *   alpha, tau_col, tau_grad : raw cost weights and truncations, Eq. (9)
+ *   gf_radius                : radius r of the regression window W'_k of
+ *                              Eq. (7), (2r+1)^2 pixels; 1 <= r <= 32
+ *   gf_eps                   : e of Eq. (7) (0.01^2 in the paper)
+ *   lambda, tau_dis, w_floor,
+ *   gamma                    : smoothness weight, truncation, lower bound
+ *                              epsilon and contrast gamma, Eqs. (5),(10),(11)
+ *   neighbours               : 8 or 4
+ *   host_threads             : threads of the host min-cut pool (0 = all cores, at most 64)
+ */
+typedef struct {
+  int32_t width, height;
+  double disp_max;
+  double alpha, tau_col, tau_grad;
+  int32_t gf_radius;
+  double gf_eps;
+  double lambda, tau_dis, w_floor, gamma;
+  int32_t neighbours;
+  int32_t host_threads;
+} lexp_params;
+
+/* Grid levels of the optimisation procedure (Alg. 2): cell size in pixels and
+ * the proposer counts of Alg. 1 per level. */
+typedef struct {
+  int32_t n_levels; /* 1..4 */
+  int32_t cell[4];
+  int32_t k_prop[4];
+  int32_t k_rand[4];
+  int32_t iterations;
+} lexp_schedule;
+
+/* Counters of the hot kernel, accumulated while timing is enabled. */
+typedef struct {
+  int64_t unary_launches;   /* launches of the fused cost kernel */
+  int64_t unary_items;      /* (region, label) items evaluated */
+  int64_t unary_evals;      /* phi_p evaluations (sum of clipped |R|) */
+  double unary_kernel_ms;   /* sum of kernel durations (HIP events on the launch stream) */
+  double unary_alg_bytes;   /* algorithmic bytes: sum over items of 16|M| + 16|M| + 36|R+| + 4|R| */
+  int64_t expand_calls;     /* group steps (one batch of disjoint expansions) */
+  double host_cut_ms;       /* host max-flow time (wall, summed over steps) */
+  double host_wait_ms;      /* time the host waited for device terms */
+} lexp_stats;
+
+/* Creates a context for one stereo pair and runs the label-independent set-up
+ * on the device: packed images (R, G, B, x-gradient of the BT.601 gray value
+ * by [-0.5 0 0.5], replicated borders), guide statistics of Eq. (7) (mean of
+ * I = I_L/255 and (Sigma_k + eU)^-1 over W'_k, computed in FP64, stored FP32)
+ * and the contrast weights w_pq of Eq. (11) for the forward neighbours (FP64).
+ * left_hwc / right_hwc: device, HxWx3 float32; they may be freed after return
+ * (the call synchronises hip_stream).  The context owns its device scratch. */
+lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const float* right_hwc,
+                        void* hip_stream, lexp_ctx** out);
+
+/* Frees the context and its device scratch.  NULL is accepted. */
+lexp_status lexp_destroy(lexp_ctx* ctx);
+
+const char* lexp_last_error(void);
+
+/* Unary term phi_p(alpha) of Eq. (6) for n (region, label) items, computed as
+ * Sec. 3.5 describes: the raw cost rho_alpha of Eqs. (8),(9),(18) over the
+ * filtering region M (the region dilated by 2r, Eq. (20)), aggregated by the
+ * box form of the guided filter of Eq. (7) (Eq. (19)).  Windows clipped by
+ * the image border are count-normalised; a sample outside the right image
+ * costs (1-alpha)*tau_col + alpha*tau_grad.
+ *   rects, labels, offsets: host arrays [n].
+ *   out_cost: device float32; item i writes |clip(rects[i])| values,
+ *             row-major over the clipped rectangle, at out_cost[offsets[i]].
+ * Asynchronous on hip_stream. */
+lexp_status lexp_unary_cost(lexp_ctx* ctx, int32_t n, const lexp_rect* rects, const lexp_plane* labels,
+                            const int64_t* offsets, float* out_cost, void* hip_stream);
+
+/* Linear coefficients (a_k[0..2], b_k) of the guided filter of Eq. (7) for the
+ * cost slice of each item, over R+ = clip(rect dilated by r), row-major, 4
+ * float32 per pixel at out_ab[4 * offsets[i]].  Inspection and tests. */
+lexp_status lexp_guided_coeffs(lexp_ctx* ctx, int32_t n, const lexp_rect* rects, const lexp_plane* labels,
+                               const int64_t* offsets, float* out_ab, void* hip_stream);
+
+/* Per-pixel unary phi_p(f_p) of Eq. (6) with every pixel's own label (each
+ * pixel is a 1x1 region): the state after the random initialisation of
+ * Alg. 2.  labels: device HxWx4; out_cost: device HxW float32. */
+lexp_status lexp_pixel_costs(lexp_ctx* ctx, const float* labels, float* out_cost, void* hip_stream);
+
+/* One local alpha-expansion per region (Eq. (13) restricted to the region,
+ * binary problem of Lemma 2, solved exactly by a host Boykov-Kolmogorov
+ * max-flow; among minimisers, the one that takes alpha at the fewest pixels).
+ * Regions must be pairwise separated by at least one pixel (no 8-neighbour
+ * contact), else LEXP_EINVAL and nothing is modified (Lemma 3 independence).
+ *   rects, alpha, offsets: host [n]; alpha_cost: device, phi(alpha) laid out
+ *   as lexp_unary_cost writes it; labels (device HxWx4) and cur_cost (device
+ *   HxW, phi_p(f_p)) are updated in place; delta_Eq (host [n], may be NULL):
+ *   energy change in LEXP_QUANTUM units (<= 0); n_changed (host [n], may be
+ *   NULL): pixels that took alpha.  Synchronises hip_stream. */
+lexp_status lexp_expand_region(lexp_ctx* ctx, int32_t n, const lexp_rect* rects, const lexp_plane* alpha,
+                               const float* alpha_cost, const int64_t* offsets, float* labels, float* cur_cost,
+                               int64_t* delta_Eq, int32_t* n_changed, void* hip_stream);
+
+/* The device-built binary problem of lexp_expand_region without solving it:
+ * per pixel of each region (row-major at 5 * offsets[i]) the int32 terms
+ * (U_p, w_0..w_3): E(x) = sum U_p x_p + sum_d w_d (1 - x_p) x_{p + fwd_d},
+ * forward directions (1,0), (0,1), (1,1), (-1,1).  out_terms: device. */
+lexp_status lexp_graph_terms(lexp_ctx* ctx, int32_t n, const lexp_rect* rects, const lexp_plane* alpha,
+                             const float* alpha_cost, const int64_t* offsets, const float* labels,
+                             const float* cur_cost, int32_t* out_terms, void* hip_stream);
+
+/* Smoothness term of Eq. (10) times lambda, for neighbours p and q, evaluated
+ * by the device code path (FP64).  Synchronous. */
+lexp_status lexp_pairwise(lexp_ctx* ctx, int32_t pu, int32_t pv, int32_t qu, int32_t qv, lexp_plane fp,
+                          lexp_plane fq, double* out);
+
+/* Energy of Eq. (5) (FP64): sum of cur_cost plus lambda * sum of Eq. (10)
+ * over unordered neighbour pairs.  labels: device HxWx4, cur_cost: device HxW.
+ * Any output pointer may be NULL.  Synchronises hip_stream. */
+lexp_status lexp_energy(lexp_ctx* ctx, const float* labels, const float* cur_cost, double* total,
+                        double* unary, double* pairwise, void* hip_stream);
+
+/* Random initialisation of Alg. 2 (plane through (p, z0), z0 ~ U[0, disp_max],
+ * normal uniform on the upper hemisphere) from a counter-based generator
+ * keyed by (seed, pixel).  labels: device HxWx4. */
+lexp_status lexp_init_labels(lexp_ctx* ctx, uint64_t seed, float* labels, void* hip_stream);
+
+/* Runs the optimisation procedure of Alg. 2 with Alg. 1 per cell and the
+ * grouping of Eq. (15): random init, per-pixel costs, then for every
+ * iteration, grid level and group, K_prop propagation and K_rand
+ * randomisation steps for all cells of the group together.
+ *   labels (device HxWx4) and cur_cost (device HxW) receive the result.
+ *   energy_trace (host, iterations+1 values, may be NULL): Eq. (5) after the
+ *   init and after each iteration.  time_trace (same size, may be NULL):
+ *   seconds since the call started at those points.  Synchronous. */
+lexp_status lexp_optimize(lexp_ctx* ctx, const lexp_schedule* schedule, uint64_t seed, float* labels,
+                          float* cur_cost, double* energy_trace, double* time_trace, void* hip_stream);
+
+/* Timing of the fused cost kernel (HIP events around each launch on its
+ * stream) and host phases.  enable != 0 turns it on; reset clears counters. */
+lexp_status lexp_set_timing(lexp_ctx* ctx, int32_t enable);
+lexp_status lexp_get_stats(lexp_ctx* ctx, lexp_stats* out);
+lexp_status lexp_reset_stats(lexp_ctx* ctx);
+
+/* Copies of the set-up buffers for inspection (device destinations, any may
+ * be NULL): left4/right4 HxWx4 (R, G, B, x-gradient), guide HxWx9
+ * (mu_0..2, inv00, inv01, inv02, inv11, inv12, inv22), weights HxWx4 float64
+ * (w_pq for the forward neighbours, 0 outside the image). */
+lexp_status lexp_debug_guide(lexp_ctx* ctx, float* left4, float* right4, float* guide, double* weights,
+                             void* hip_stream);
+
+/* ---- host-side pieces, usable without a device ---------------------------- */
+
+/* Exact minimisation of E(x) = sum U_p x_p + sum_d w_d (1 - x_p) x_{p+fwd_d}
+ * on a w x h grid by the library's Boykov-Kolmogorov max-flow; returns in x
+ * the minimiser with the fewest ones.  U: [w*h], w4: [w*h*4] (w_d >= 0),
+ * neighbours 8 or 4, x: [w*h].  Host memory. */
+lexp_status lexp_solve_binary(int32_t w, int32_t h, int32_t neighbours, const int64_t* U, const int64_t* w4,
+                              uint8_t* x);
+
+/* Counter-based random numbers: SplitMix64 output function applied along the
+ * key chain h0 = sm64(seed), h_{i+1} = sm64(h_i ^ fields[i]). */
+uint64_t lexp_rng_key(uint64_t seed, const uint64_t* fields, int32_t n_fields);
+
+/* Random initial labels (host, HxWx3 float32); same values lexp_init_labels
+ * writes to the device. */
+lexp_status lexp_init_labels_host(int32_t width, int32_t height, double disp_max, uint64_t seed,
+                                  float* labels_hw3);
+
+/* Candidate label of one alpha_ij-expansion step (Alg. 1): random pixel r of
+ * the clipped centre cell (ci, cj) of a grid with cells of `cell` pixels;
+ * alpha = f_r for step < k_prop, otherwise f_r perturbed (Sec. 3.4) with
+ * sizes (r_d, r_n) halved once per refinement step already taken.
+ * labels_hw3: host HxWx3 float32. */
+lexp_status lexp_propose(int32_t width, int32_t height, const float* labels_hw3, uint64_t seed,
+                         int32_t iteration, int32_t level, int32_t cell, int32_t ci, int32_t cj, int32_t step,
+                         int32_t k_prop, double r_d, double r_n, lexp_plane* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LEXP_H */

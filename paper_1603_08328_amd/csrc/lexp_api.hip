@@ -1,0 +1,871 @@
+// C ABI of the local-expansion-move library: context, argument validation,
+// kernel launches, one batch of disjoint local expansions, and the
+// optimisation procedure (Alg. 2 with Alg. 1 per cell).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "lexp.h"
+#include "lexp_device.h"
+#include "lexp_host.h"
+
+using lexp::DevParams;
+using lexp::Item;
+using lexp::Tile;
+
+namespace {
+
+thread_local std::string g_err;
+
+lexp_status fail(lexp_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(LEXP_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// grow-only device buffer
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t n) {
+    if (n <= cap) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    hipError_t e = hipMalloc((void**)&p, std::max<size_t>(n, 1) * sizeof(T));
+    if (e == hipSuccess) cap = n;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+// grow-only pinned host buffer
+template <class T>
+struct PinBuf {
+  T* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t n) {
+    if (n <= cap) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    hipError_t e = hipHostMalloc((void**)&p, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault);
+    if (e == hipSuccess) cap = n;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+constexpr int kMaxTileRows = 128;  // bounds the length of the running sums
+
+struct TileCaps {
+  int wp = 1, tw = 1, ws = 1;
+};
+
+}  // namespace
+
+struct lexp_ctx {
+  lexp_params prm{};
+  DevParams dp{};
+  int W = 0, H = 0, r = 0;
+  int tw_lim = 1;           // widest R tile column strip
+  size_t lds_limit = 65536; // dynamic LDS per workgroup
+  float4* left4 = nullptr;
+  float4* right4 = nullptr;
+  float* guide = nullptr;
+  double* wts = nullptr;
+  DevBuf<Item> d_items;
+  DevBuf<Tile> d_tiles;
+  DevBuf<float> d_phi;
+  DevBuf<int> d_terms;
+  DevBuf<uint8_t> d_x;
+  DevBuf<int> d_flag;
+  DevBuf<double> d_partial;
+  DevBuf<float4> d_labels_tmp;
+  PinBuf<Item> h_items;
+  PinBuf<Tile> h_tiles;
+  PinBuf<int> h_terms;
+  PinBuf<uint8_t> h_x;
+  PinBuf<int> h_flag;
+  PinBuf<double> h_partial;
+  PinBuf<float> h_labels4;
+  hipEvent_t staging_done = nullptr;  // host staging buffers may be rewritten once this has completed
+  std::unique_ptr<lexp::ThreadPool> pool;
+  std::vector<std::unique_ptr<lexp::BKSolver>> solvers;
+  bool timing = false;
+  lexp_stats stats{};
+  std::vector<hipEvent_t> ev_free;
+  struct Pending { hipEvent_t a, b; double bytes; };
+  std::vector<Pending> ev_pending;
+};
+
+namespace {
+
+bool finite_plane(const lexp_plane& p) { return std::isfinite(p.a) && std::isfinite(p.b) && std::isfinite(p.c); }
+
+void clip_rect(const lexp_ctx* c, const lexp_rect& r, int* u0, int* v0, int* u1, int* v1) {
+  *u0 = std::max(r.u0, 0);
+  *v0 = std::max(r.v0, 0);
+  *u1 = std::min(r.u1, c->W);
+  *v1 = std::min(r.v1, c->H);
+  if (*u1 < *u0) *u1 = *u0;
+  if (*v1 < *v0) *v1 = *v0;
+}
+
+int64_t clipped_area(const lexp_ctx* c, int u0, int v0, int u1, int v1, int m) {
+  const int a0 = std::max(u0 - m, 0), b0 = std::max(v0 - m, 0);
+  const int a1 = std::min(u1 + m, c->W), b1 = std::min(v1 + m, c->H);
+  return (int64_t)std::max(a1 - a0, 0) * std::max(b1 - b0, 0);
+}
+
+// Algorithmic bytes of one item: right-image band and left tile over M (16 B
+// each per pixel), guide statistics over R+ (36 B), phi over R (4 B).
+double item_alg_bytes(const lexp_ctx* c, const Item& it) {
+  const int u1 = it.ru0 + it.rw, v1 = it.rv0 + it.rh;
+  const double m = (double)clipped_area(c, it.ru0, it.rv0, u1, v1, 2 * c->r);
+  const double p = (double)clipped_area(c, it.ru0, it.rv0, u1, v1, c->r);
+  return 32.0 * m + 36.0 * p + 4.0 * (double)it.rw * it.rh;
+}
+
+int max_tile_width(int r, size_t budget) {
+  const int ring = 2 * r + 1 + lexp::kChunk;
+  for (int tw = 256 - 2 * r; tw >= 1; --tw)
+    if (lexp::unary_lds_bytes(ring, tw + 2 * r, tw, std::max(tw + 4 * r, tw + 2 * r)) <= budget) return tw;
+  return 0;
+}
+
+// Splits items into column strips (LDS-bounded width) and row strips.
+void plan_tiles(const lexp_ctx* c, const Item* items, int n, std::vector<Tile>& tiles, TileCaps& caps) {
+  tiles.clear();
+  caps = TileCaps{};
+  for (int i = 0; i < n; ++i) {
+    const Item& it = items[i];
+    if (it.rw <= 0 || it.rh <= 0) continue;
+    const int ncs = (it.rw + c->tw_lim - 1) / c->tw_lim;
+    const int nrs = (it.rh + kMaxTileRows - 1) / kMaxTileRows;
+    for (int rs = 0; rs < nrs; ++rs) {
+      const int tv0 = it.rv0 + (int)((int64_t)it.rh * rs / nrs);
+      const int tv1 = it.rv0 + (int)((int64_t)it.rh * (rs + 1) / nrs);
+      for (int cs = 0; cs < ncs; ++cs) {
+        const int tu0 = it.ru0 + (int)((int64_t)it.rw * cs / ncs);
+        const int tu1 = it.ru0 + (int)((int64_t)it.rw * (cs + 1) / ncs);
+        Tile t{};
+        t.item = i;
+        t.tu0 = tu0; t.tv0 = tv0; t.tu1 = tu1; t.tv1 = tv1;
+        t.flags = (cs == 0 ? lexp::kFirstCol : 0) | (cs == ncs - 1 ? lexp::kLastCol : 0) |
+                  (rs == 0 ? lexp::kFirstRow : 0) | (rs == nrs - 1 ? lexp::kLastRow : 0);
+        tiles.push_back(t);
+        const int wp = std::min(tu1 + c->r, c->W) - std::max(tu0 - c->r, 0);
+        const int wm = std::min(tu1 + 2 * c->r, c->W) - std::max(tu0 - 2 * c->r, 0);
+        caps.wp = std::max(caps.wp, wp);
+        caps.tw = std::max(caps.tw, tu1 - tu0);
+        caps.ws = std::max(caps.ws, std::max(wm, wp));
+      }
+    }
+  }
+}
+
+hipEvent_t take_event(lexp_ctx* c) {
+  if (!c->ev_free.empty()) {
+    hipEvent_t e = c->ev_free.back();
+    c->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Folds completed kernel timings into the counters (synchronises the events).
+void collect_timing(lexp_ctx* c) {
+  for (auto& p : c->ev_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->stats.unary_kernel_ms += ms;
+    }
+    c->ev_free.push_back(p.a);
+    c->ev_free.push_back(p.b);
+  }
+  c->ev_pending.clear();
+}
+
+template <int MODE>
+lexp_status launch_unary(lexp_ctx* c, const Item* d_items, const Tile* d_tiles, int n_tiles, const TileCaps& caps,
+                         const float4* label_field, float* out, hipStream_t s, double alg_bytes, int64_t evals,
+                         int64_t n_items) {
+  if (n_tiles <= 0) return LEXP_OK;
+  const int ring = 2 * c->r + 1 + lexp::kChunk;
+  const size_t lds = lexp::unary_lds_bytes(ring, caps.wp, caps.tw, caps.ws);
+  if (lds > c->lds_limit || caps.wp > 256 || caps.tw > 256)
+    return fail(LEXP_EINVAL, "tile exceeds kernel limits (lds %zu > %zu or width)", lds, c->lds_limit);
+  const int grid = ((n_tiles + 7) / 8) * 8;
+  // timing covers the region-cost launches (MODE 0), the hot loop of the method
+  const bool timed = c->timing && MODE == 0;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (timed) {
+    ea = take_event(c);
+    eb = take_event(c);
+    if (ea && eb) HIP_TRY(hipEventRecord(ea, s));
+  }
+  hipLaunchKernelGGL(lexp::k_unary<MODE>, dim3(grid), dim3(256), lds, s, c->dp, c->left4, c->right4, c->guide,
+                     d_items, d_tiles, n_tiles, label_field, out, ring, caps.wp, caps.tw, caps.ws);
+  HIP_TRY(hipGetLastError());
+  if (timed && ea && eb) {
+    HIP_TRY(hipEventRecord(eb, s));
+    c->ev_pending.push_back({ea, eb, alg_bytes});
+    c->stats.unary_launches += 1;
+    c->stats.unary_alg_bytes += alg_bytes;
+    c->stats.unary_evals += evals;
+    c->stats.unary_items += n_items;
+  }
+  return LEXP_OK;
+}
+
+lexp_status wait_staging(lexp_ctx* c) {
+  HIP_TRY(hipEventSynchronize(c->staging_done));
+  return LEXP_OK;
+}
+
+// Builds the item table for (rects, labels) on the host staging buffer.
+lexp_status stage_items(lexp_ctx* c, int n, const lexp_rect* rects, const lexp_plane* labels, const int64_t* offsets,
+                        const int64_t* aux) {
+  HIP_TRY(c->h_items.ensure((size_t)n));
+  for (int i = 0; i < n; ++i) {
+    int u0, v0, u1, v1;
+    clip_rect(c, rects[i], &u0, &v0, &u1, &v1);
+    Item& it = c->h_items.p[i];
+    it.ru0 = u0; it.rv0 = v0; it.rw = u1 - u0; it.rh = v1 - v0;
+    it.a = labels[i].a; it.b = labels[i].b; it.c = labels[i].c; it.pad = 0.f;
+    it.out_off = offsets ? offsets[i] : 0;
+    it.aux_off = aux ? aux[i] : 0;
+  }
+  return LEXP_OK;
+}
+
+lexp_status validate_items(lexp_ctx* c, int32_t n, const lexp_rect* rects, const lexp_plane* labels,
+                           const int64_t* offsets) {
+  if (!c) return fail(LEXP_EINVAL, "null context");
+  if (n < 0) return fail(LEXP_EINVAL, "negative item count");
+  if (n > 0 && (!rects || !labels || !offsets)) return fail(LEXP_EINVAL, "null item array");
+  for (int i = 0; i < n; ++i) {
+    if (!finite_plane(labels[i])) return fail(LEXP_EINVAL, "label %d is not finite", i);
+    if (offsets[i] < 0) return fail(LEXP_EINVAL, "negative offset %d", i);
+  }
+  return LEXP_OK;
+}
+
+// Rejects regions that overlap or touch (8-neighbour contact).
+lexp_status check_separated(lexp_ctx* c, int n, const Item* items) {
+  std::vector<int32_t> owner((size_t)c->W * c->H, -1);
+  for (int i = 0; i < n; ++i) {
+    const Item& it = items[i];
+    if (it.rw <= 0 || it.rh <= 0) continue;
+    const int a0 = std::max(it.ru0 - 1, 0), a1 = std::min(it.ru0 + it.rw + 1, c->W);
+    const int b0 = std::max(it.rv0 - 1, 0), b1 = std::min(it.rv0 + it.rh + 1, c->H);
+    for (int v = it.rv0; v < it.rv0 + it.rh; ++v)
+      for (int u = it.ru0; u < it.ru0 + it.rw; ++u) {
+        int32_t& o = owner[(size_t)v * c->W + u];
+        if (o >= 0) return fail(LEXP_EINVAL, "regions %d and %d overlap", o, i);
+        o = i;
+      }
+    for (int v = b0; v < b1; ++v)
+      for (int u = a0; u < a1; ++u) {
+        const int32_t o = owner[(size_t)v * c->W + u];
+        if (o >= 0 && o != i) return fail(LEXP_EINVAL, "regions %d and %d touch", o, i);
+      }
+  }
+  return LEXP_OK;
+}
+
+// Binary energy of a cut in quantum units.
+int64_t cut_energy(int w, int h, int nf, const int* terms, const uint8_t* x) {
+  static const int DU[4] = {1, 0, 1, -1}, DV[4] = {0, 1, 1, 1};
+  int64_t e = 0;
+  for (int i = 0; i < w * h; ++i) {
+    if (x[i]) e += terms[(size_t)i * 5];
+    else {
+      const int u = i % w, v = i / w;
+      for (int d = 0; d < nf; ++d) {
+        const int nu = u + DU[d], nv = v + DV[d];
+        if (nu < 0 || nu >= w || nv < 0 || nv >= h) continue;
+        if (x[nv * w + nu]) e += terms[(size_t)i * 5 + 1 + d];
+      }
+    }
+  }
+  return e;
+}
+
+// Graph terms on the device, host max-flow per item, label update on the
+// device.  Items are staged in c->h_items (aux_off = compact pixel offset,
+// total pixels n_px).  mirror (optional): host HxWx3 labels to update.
+lexp_status expand_batch(lexp_ctx* c, int n, int64_t n_px, const float* alpha_cost, float* labels, float* cur_cost,
+                         int64_t* delta_Eq, int32_t* n_changed, float* mirror, int64_t* total_dE, hipStream_t s,
+                         bool items_on_device) {
+  if (n <= 0) return LEXP_OK;
+  if (!items_on_device) {
+    HIP_TRY(c->d_items.ensure((size_t)n));
+    HIP_TRY(hipMemcpyAsync(c->d_items.p, c->h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(c->d_terms.ensure((size_t)n_px * 5));
+  HIP_TRY(c->d_x.ensure((size_t)n_px));
+  HIP_TRY(c->h_terms.ensure((size_t)n_px * 5));
+  HIP_TRY(c->h_x.ensure((size_t)n_px));
+  HIP_TRY(c->d_flag.ensure(1));
+  HIP_TRY(c->h_flag.ensure(1));
+  int max_px = 1;
+  for (int i = 0; i < n; ++i) max_px = std::max(max_px, c->h_items.p[i].rw * c->h_items.p[i].rh);
+  HIP_TRY(hipMemsetAsync(c->d_flag.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(lexp::k_graph_terms, dim3((max_px + 255) / 256, n), dim3(256), 0, s, c->dp, c->d_items.p,
+                     (const float4*)labels, cur_cost, alpha_cost, c->wts, c->d_terms.p, c->d_flag.p);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(c->h_terms.p, c->d_terms.p, sizeof(int) * 5 * n_px, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(c->h_flag.p, c->d_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  const auto t0 = std::chrono::steady_clock::now();
+  HIP_TRY(hipStreamSynchronize(s));
+  const auto t1 = std::chrono::steady_clock::now();
+  if (c->h_flag.p[0]) return fail(LEXP_EINVAL, "binary-problem term exceeds 2^30 quanta (parameters too large)");
+  const int nf = c->dp.nf;
+  std::vector<int64_t> de(n, 0);
+  std::vector<int32_t> nc(n, 0);
+  const Item* items = c->h_items.p;
+  c->pool->parallel_for(n, [&](int i, int worker) {
+    const Item& it = items[i];
+    if (it.rw <= 0 || it.rh <= 0) return;
+    const int* t = c->h_terms.p + (size_t)it.aux_off * 5;
+    uint8_t* x = c->h_x.p + it.aux_off;
+    lexp::BKSolver& bk = *c->solvers[worker];
+    bk.load<int32_t>(it.rw, it.rh, nf, t, 5, t + 1, 5);
+    bk.solve(x);
+    de[i] = cut_energy(it.rw, it.rh, nf, t, x);
+    int32_t cnt = 0;
+    for (int q = 0; q < it.rw * it.rh; ++q) {
+      if (!x[q]) continue;
+      ++cnt;
+      if (mirror) {
+        float* m = mirror + ((size_t)(it.rv0 + q / it.rw) * c->W + (it.ru0 + q % it.rw)) * 3;
+        m[0] = it.a; m[1] = it.b; m[2] = it.c;
+      }
+    }
+    nc[i] = cnt;
+  });
+  const auto t2 = std::chrono::steady_clock::now();
+  HIP_TRY(hipMemcpyAsync(c->d_x.p, c->h_x.p, (size_t)n_px, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(lexp::k_apply, dim3((max_px + 255) / 256, n), dim3(256), 0, s, c->W, c->d_items.p, c->d_x.p,
+                     alpha_cost, (float4*)labels, cur_cost);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(c->staging_done, s));
+  int64_t sum = 0;
+  for (int i = 0; i < n; ++i) {
+    if (delta_Eq) delta_Eq[i] = de[i];
+    if (n_changed) n_changed[i] = nc[i];
+    sum += de[i];
+  }
+  if (total_dE) *total_dE += sum;
+  c->stats.expand_calls += 1;
+  c->stats.host_wait_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+  c->stats.host_cut_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
+  return LEXP_OK;
+}
+
+lexp_status energy_impl(lexp_ctx* c, const float* labels, const float* cur_cost, double* total, double* unary,
+                        double* pair, hipStream_t s) {
+  const int n = c->W * c->H;
+  const int nb = (n + 255) / 256;
+  HIP_TRY(c->d_partial.ensure((size_t)nb * 2));
+  HIP_TRY(c->h_partial.ensure((size_t)nb * 2));
+  hipLaunchKernelGGL(lexp::k_energy, dim3(nb), dim3(256), 0, s, c->dp, (const float4*)labels, cur_cost, c->wts,
+                     c->d_partial.p);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(c->h_partial.p, c->d_partial.p, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double eu = 0.0, ep = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    eu += c->h_partial.p[2 * b];
+    ep += c->h_partial.p[2 * b + 1];
+  }
+  if (total) *total = eu + ep;
+  if (unary) *unary = eu;
+  if (pair) *pair = ep;
+  return LEXP_OK;
+}
+
+lexp_status pixel_costs_impl(lexp_ctx* c, const float* labels, float* out, hipStream_t s) {
+  TileCaps caps;
+  caps.tw = 1;
+  caps.wp = std::min(2 * c->r + 1, c->W);
+  caps.ws = std::max(std::min(4 * c->r + 1, c->W), caps.wp);
+  return launch_unary<2>(c, nullptr, nullptr, c->W * c->H, caps, (const float4*)labels, out, s, 0.0,
+                         (int64_t)c->W * c->H, (int64_t)c->W * c->H);
+}
+
+// Host labels (HxWx3) -> device field (HxWx4).
+lexp_status upload_labels(lexp_ctx* c, const float* hw3, float* dev4, hipStream_t s) {
+  const size_t n = (size_t)c->W * c->H;
+  HIP_TRY(c->h_labels4.ensure(n * 4));
+  for (size_t i = 0; i < n; ++i) {
+    c->h_labels4.p[4 * i + 0] = hw3[3 * i + 0];
+    c->h_labels4.p[4 * i + 1] = hw3[3 * i + 1];
+    c->h_labels4.p[4 * i + 2] = hw3[3 * i + 2];
+    c->h_labels4.p[4 * i + 3] = 0.f;
+  }
+  HIP_TRY(hipMemcpyAsync(dev4, c->h_labels4.p, sizeof(float) * 4 * n, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return LEXP_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// ABI
+// ===========================================================================
+extern "C" {
+
+const char* lexp_last_error(void) { return g_err.c_str(); }
+
+lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const float* right_hwc, void* hip_stream,
+                        lexp_ctx** out) {
+  if (!params || !left_hwc || !right_hwc || !out) return fail(LEXP_EINVAL, "null argument");
+  const lexp_params& p = *params;
+  if (p.width <= 0 || p.height <= 0 || (int64_t)p.width * p.height > (1ll << 30))
+    return fail(LEXP_EINVAL, "bad image size %dx%d", p.width, p.height);
+  if (p.gf_radius < 1 || p.gf_radius > 32) return fail(LEXP_EINVAL, "gf_radius %d outside [1, 32]", p.gf_radius);
+  if (p.neighbours != 4 && p.neighbours != 8) return fail(LEXP_EINVAL, "neighbours must be 4 or 8");
+  if (!(p.gf_eps > 0.0) || !(p.gamma > 0.0) || !(p.lambda >= 0.0) || !(p.tau_dis >= 0.0) || !(p.w_floor >= 0.0) ||
+      !(p.tau_col >= 0.0) || !(p.tau_grad >= 0.0) || !(p.alpha >= 0.0 && p.alpha <= 1.0) ||
+      !std::isfinite(p.disp_max))
+    return fail(LEXP_EINVAL, "parameter out of range");
+  if (p.lambda * p.tau_dis > 64.0 || p.tau_col > 1e4 || p.tau_grad > 1e4)
+    return fail(LEXP_EINVAL, "lambda*tau_dis or truncations too large for 32-bit binary terms");
+  if (p.host_threads < 0 || p.host_threads > 64) return fail(LEXP_EINVAL, "host_threads outside [0, 64]");
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::unique_ptr<lexp_ctx> c(new lexp_ctx());
+  c->prm = p;
+  c->W = p.width;
+  c->H = p.height;
+  c->r = p.gf_radius;
+  DevParams& d = c->dp;
+  d.W = c->W; d.H = c->H; d.r = c->r; d.nf = p.neighbours == 8 ? 4 : 2;
+  d.oma = (float)(1.0 - p.alpha);
+  d.al = (float)p.alpha;
+  d.tc = (float)p.tau_col;
+  d.tg = (float)p.tau_grad;
+  d.rho_max = (float)((1.0 - p.alpha) * p.tau_col + p.alpha * p.tau_grad);
+  d.lam = p.lambda; d.tau_dis = p.tau_dis; d.w_floor = p.w_floor;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  int lds = 0;
+  HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  c->lds_limit = (size_t)std::max(lds, 16384);
+  // two workgroups per CU when the tile allows it, else one
+  c->tw_lim = max_tile_width(c->r, c->lds_limit / 2);
+  if (c->tw_lim < 1) c->tw_lim = max_tile_width(c->r, c->lds_limit);
+  if (c->tw_lim < 1) return fail(LEXP_EINVAL, "gf_radius %d needs more LDS than the device has", c->r);
+  const size_t n = (size_t)c->W * c->H;
+  HIP_TRY(hipMalloc((void**)&c->left4, n * sizeof(float4)));
+  HIP_TRY(hipMalloc((void**)&c->right4, n * sizeof(float4)));
+  HIP_TRY(hipMalloc((void**)&c->guide, n * 9 * sizeof(float)));
+  HIP_TRY(hipMalloc((void**)&c->wts, n * 4 * sizeof(double)));
+  double* tmp = nullptr;
+  HIP_TRY(hipMalloc((void**)&tmp, n * 9 * sizeof(double)));
+  const int nb = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(lexp::k_pack, dim3(nb), dim3(256), 0, s, left_hwc, c->left4, c->W, c->H);
+  hipLaunchKernelGGL(lexp::k_pack, dim3(nb), dim3(256), 0, s, right_hwc, c->right4, c->W, c->H);
+  hipLaunchKernelGGL(lexp::k_guide_h, dim3(nb), dim3(256), 0, s, c->left4, tmp, c->W, c->H, c->r);
+  hipLaunchKernelGGL(lexp::k_guide_v, dim3(nb), dim3(256), 0, s, tmp, c->guide, c->W, c->H, c->r, p.gf_eps);
+  hipLaunchKernelGGL(lexp::k_weights, dim3(nb), dim3(256), 0, s, left_hwc, c->wts, c->W, c->H, p.gamma);
+  hipError_t e = hipGetLastError();
+  hipError_t e2 = hipStreamSynchronize(s);
+  (void)hipFree(tmp);
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(LEXP_EDEVICE, "set-up kernels: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  HIP_TRY(hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(c->staging_done, s));
+  int nt = p.host_threads;
+  if (nt == 0) nt = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 64u);
+  c->pool.reset(new lexp::ThreadPool(nt));
+  for (int i = 0; i < c->pool->size(); ++i) c->solvers.emplace_back(new lexp::BKSolver());
+  *out = c.release();
+  return LEXP_OK;
+}
+
+lexp_status lexp_destroy(lexp_ctx* c) {
+  if (!c) return LEXP_OK;
+  (void)hipDeviceSynchronize();
+  collect_timing(c);
+  for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
+  if (c->staging_done) (void)hipEventDestroy(c->staging_done);
+  (void)hipFree(c->left4);
+  (void)hipFree(c->right4);
+  (void)hipFree(c->guide);
+  (void)hipFree(c->wts);
+  c->d_items.release(); c->d_tiles.release(); c->d_phi.release(); c->d_terms.release(); c->d_x.release();
+  c->d_flag.release(); c->d_partial.release(); c->d_labels_tmp.release();
+  c->h_items.release(); c->h_tiles.release(); c->h_terms.release(); c->h_x.release(); c->h_flag.release();
+  c->h_partial.release(); c->h_labels4.release();
+  delete c;
+  return LEXP_OK;
+}
+
+lexp_status lexp_unary_cost(lexp_ctx* c, int32_t n, const lexp_rect* rects, const lexp_plane* labels,
+                            const int64_t* offsets, float* out_cost, void* hip_stream) {
+  lexp_status st = validate_items(c, n, rects, labels, offsets);
+  if (st) return st;
+  if (n > 0 && !out_cost) return fail(LEXP_EINVAL, "null output");
+  if (n == 0) return LEXP_OK;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if ((st = wait_staging(c))) return st;
+  if ((st = stage_items(c, n, rects, labels, offsets, nullptr))) return st;
+  std::vector<Tile> tiles;
+  TileCaps caps;
+  plan_tiles(c, c->h_items.p, n, tiles, caps);
+  HIP_TRY(c->h_tiles.ensure(tiles.size()));
+  std::copy(tiles.begin(), tiles.end(), c->h_tiles.p);
+  HIP_TRY(c->d_items.ensure((size_t)n));
+  HIP_TRY(c->d_tiles.ensure(tiles.size()));
+  HIP_TRY(hipMemcpyAsync(c->d_items.p, c->h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
+  if (!tiles.empty())
+    HIP_TRY(hipMemcpyAsync(c->d_tiles.p, c->h_tiles.p, sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, s));
+  double bytes = 0.0;
+  int64_t evals = 0;
+  for (int i = 0; i < n; ++i) {
+    bytes += item_alg_bytes(c, c->h_items.p[i]);
+    evals += (int64_t)c->h_items.p[i].rw * c->h_items.p[i].rh;
+  }
+  st = launch_unary<0>(c, c->d_items.p, c->d_tiles.p, (int)tiles.size(), caps, nullptr, out_cost, s, bytes, evals, n);
+  if (st) return st;
+  HIP_TRY(hipEventRecord(c->staging_done, s));
+  return LEXP_OK;
+}
+
+lexp_status lexp_guided_coeffs(lexp_ctx* c, int32_t n, const lexp_rect* rects, const lexp_plane* labels,
+                               const int64_t* offsets, float* out_ab, void* hip_stream) {
+  lexp_status st = validate_items(c, n, rects, labels, offsets);
+  if (st) return st;
+  if (n > 0 && !out_ab) return fail(LEXP_EINVAL, "null output");
+  if (n == 0) return LEXP_OK;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if ((st = wait_staging(c))) return st;
+  if ((st = stage_items(c, n, rects, labels, offsets, nullptr))) return st;
+  std::vector<Tile> tiles;
+  TileCaps caps;
+  plan_tiles(c, c->h_items.p, n, tiles, caps);
+  HIP_TRY(c->h_tiles.ensure(tiles.size()));
+  std::copy(tiles.begin(), tiles.end(), c->h_tiles.p);
+  HIP_TRY(c->d_items.ensure((size_t)n));
+  HIP_TRY(c->d_tiles.ensure(tiles.size()));
+  HIP_TRY(hipMemcpyAsync(c->d_items.p, c->h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
+  if (!tiles.empty())
+    HIP_TRY(hipMemcpyAsync(c->d_tiles.p, c->h_tiles.p, sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, s));
+  st = launch_unary<1>(c, c->d_items.p, c->d_tiles.p, (int)tiles.size(), caps, nullptr, out_ab, s, 0.0, 0, n);
+  if (st) return st;
+  HIP_TRY(hipEventRecord(c->staging_done, s));
+  return LEXP_OK;
+}
+
+lexp_status lexp_pixel_costs(lexp_ctx* c, const float* labels, float* out_cost, void* hip_stream) {
+  if (!c || !labels || !out_cost) return fail(LEXP_EINVAL, "null argument");
+  return pixel_costs_impl(c, labels, out_cost, (hipStream_t)hip_stream);
+}
+
+static lexp_status prepare_expand(lexp_ctx* c, int32_t n, const lexp_rect* rects, const lexp_plane* alpha,
+                                  const float* alpha_cost, const int64_t* offsets, const float* labels,
+                                  const float* cur_cost, int64_t* n_px) {
+  lexp_status st = validate_items(c, n, rects, alpha, offsets);
+  if (st) return st;
+  if (n > 0 && (!alpha_cost || !labels || !cur_cost)) return fail(LEXP_EINVAL, "null device buffer");
+  if ((st = wait_staging(c))) return st;
+  if ((st = stage_items(c, n, rects, alpha, offsets, nullptr))) return st;
+  int64_t acc = 0;
+  for (int i = 0; i < n; ++i) {
+    c->h_items.p[i].aux_off = acc;
+    acc += (int64_t)c->h_items.p[i].rw * c->h_items.p[i].rh;
+  }
+  *n_px = acc;
+  return check_separated(c, n, c->h_items.p);
+}
+
+lexp_status lexp_expand_region(lexp_ctx* c, int32_t n, const lexp_rect* rects, const lexp_plane* alpha,
+                               const float* alpha_cost, const int64_t* offsets, float* labels, float* cur_cost,
+                               int64_t* delta_Eq, int32_t* n_changed, void* hip_stream) {
+  int64_t n_px = 0;
+  lexp_status st = prepare_expand(c, n, rects, alpha, alpha_cost, offsets, labels, cur_cost, &n_px);
+  if (st) return st;
+  if (n == 0) return LEXP_OK;
+  hipStream_t s = (hipStream_t)hip_stream;
+  st = expand_batch(c, n, n_px, alpha_cost, labels, cur_cost, delta_Eq, n_changed, nullptr, nullptr, s, false);
+  if (st) return st;
+  HIP_TRY(hipStreamSynchronize(s));
+  return LEXP_OK;
+}
+
+lexp_status lexp_graph_terms(lexp_ctx* c, int32_t n, const lexp_rect* rects, const lexp_plane* alpha,
+                             const float* alpha_cost, const int64_t* offsets, const float* labels,
+                             const float* cur_cost, int32_t* out_terms, void* hip_stream) {
+  int64_t n_px = 0;
+  lexp_status st = prepare_expand(c, n, rects, alpha, alpha_cost, offsets, labels, cur_cost, &n_px);
+  if (st) return st;
+  if (n > 0 && !out_terms) return fail(LEXP_EINVAL, "null output");
+  if (n == 0) return LEXP_OK;
+  hipStream_t s = (hipStream_t)hip_stream;
+  for (int i = 0; i < n; ++i) c->h_items.p[i].aux_off = offsets[i];
+  int max_px = 1;
+  for (int i = 0; i < n; ++i) max_px = std::max(max_px, c->h_items.p[i].rw * c->h_items.p[i].rh);
+  HIP_TRY(c->d_items.ensure((size_t)n));
+  HIP_TRY(c->d_flag.ensure(1));
+  HIP_TRY(hipMemcpyAsync(c->d_items.p, c->h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(c->d_flag.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(lexp::k_graph_terms, dim3((max_px + 255) / 256, n), dim3(256), 0, s, c->dp, c->d_items.p,
+                     (const float4*)labels, cur_cost, alpha_cost, c->wts, out_terms, c->d_flag.p);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(c->staging_done, s));
+  return LEXP_OK;
+}
+
+lexp_status lexp_pairwise(lexp_ctx* c, int32_t pu, int32_t pv, int32_t qu, int32_t qv, lexp_plane fp, lexp_plane fq,
+                          double* out) {
+  if (!c || !out) return fail(LEXP_EINVAL, "null argument");
+  if (pu < 0 || pv < 0 || qu < 0 || qv < 0 || pu >= c->W || qu >= c->W || pv >= c->H || qv >= c->H)
+    return fail(LEXP_EINVAL, "pixel outside the image");
+  if (std::abs(pu - qu) > 1 || std::abs(pv - qv) > 1 || (pu == qu && pv == qv))
+    return fail(LEXP_EINVAL, "p and q are not 8-neighbours");
+  if (!finite_plane(fp) || !finite_plane(fq)) return fail(LEXP_EINVAL, "label not finite");
+  HIP_TRY(c->d_partial.ensure(2));
+  hipLaunchKernelGGL(lexp::k_pair1, dim3(1), dim3(1), 0, 0, c->dp, c->wts, pu, pv, qu, qv,
+                     make_float4(fp.a, fp.b, fp.c, 0.f), make_float4(fq.a, fq.b, fq.c, 0.f), c->d_partial.p);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpy(out, c->d_partial.p, sizeof(double), hipMemcpyDeviceToHost));
+  return LEXP_OK;
+}
+
+lexp_status lexp_energy(lexp_ctx* c, const float* labels, const float* cur_cost, double* total, double* unary,
+                        double* pairwise, void* hip_stream) {
+  if (!c || !labels || !cur_cost) return fail(LEXP_EINVAL, "null argument");
+  return energy_impl(c, labels, cur_cost, total, unary, pairwise, (hipStream_t)hip_stream);
+}
+
+lexp_status lexp_init_labels(lexp_ctx* c, uint64_t seed, float* labels, void* hip_stream) {
+  if (!c || !labels) return fail(LEXP_EINVAL, "null argument");
+  std::vector<float> h((size_t)c->W * c->H * 3);
+  lexp_status st = lexp_init_labels_host(c->W, c->H, c->prm.disp_max, seed, h.data());
+  if (st) return st;
+  if ((st = wait_staging(c))) return st;
+  return upload_labels(c, h.data(), labels, (hipStream_t)hip_stream);
+}
+
+lexp_status lexp_optimize(lexp_ctx* c, const lexp_schedule* sch, uint64_t seed, float* labels, float* cur_cost,
+                          double* energy_trace, double* time_trace, void* hip_stream) {
+  if (!c || !sch || !labels || !cur_cost) return fail(LEXP_EINVAL, "null argument");
+  if (sch->n_levels < 1 || sch->n_levels > 4 || sch->iterations < 0) return fail(LEXP_EINVAL, "bad schedule");
+  for (int h = 0; h < sch->n_levels; ++h)
+    if (sch->cell[h] < 1 || sch->k_prop[h] < 0 || sch->k_rand[h] < 0 || sch->k_prop[h] + sch->k_rand[h] > 64)
+      return fail(LEXP_EINVAL, "bad grid level %d", h);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const auto t_start = std::chrono::steady_clock::now();
+  auto now_s = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(); };
+  const int W = c->W, H = c->H;
+  lexp_status st = wait_staging(c);
+  if (st) return st;
+
+  // Per (level, group): cells, clipped regions, compact offsets and tiles.
+  struct Group {
+    std::vector<int> ci, cj;
+    std::vector<Item> items;
+    int64_t n_px = 0;
+    size_t tile_off = 0, n_tiles = 0;
+    TileCaps caps;
+    double bytes = 0.0;
+  };
+  std::vector<Group> groups((size_t)sch->n_levels * 16);
+  std::vector<Tile> all_tiles;
+  int64_t max_px = 0;
+  size_t max_items = 0;
+  for (int h = 0; h < sch->n_levels; ++h) {
+    const int cell = sch->cell[h];
+    const int nci = (W + cell - 1) / cell, ncj = (H + cell - 1) / cell;
+    for (int k = 0; k < 16; ++k) {
+      Group& g = groups[(size_t)h * 16 + k];
+      for (int j = k / 4; j < ncj; j += 4)
+        for (int i = k % 4; i < nci; i += 4) {
+          lexp_rect rr{(i - 1) * cell, (j - 1) * cell, (i + 2) * cell, (j + 2) * cell};
+          int u0, v0, u1, v1;
+          clip_rect(c, rr, &u0, &v0, &u1, &v1);
+          Item it{};
+          it.ru0 = u0; it.rv0 = v0; it.rw = u1 - u0; it.rh = v1 - v0;
+          it.out_off = g.n_px;
+          it.aux_off = g.n_px;
+          g.n_px += (int64_t)it.rw * it.rh;
+          g.ci.push_back(i);
+          g.cj.push_back(j);
+          g.items.push_back(it);
+          g.bytes += item_alg_bytes(c, it);
+        }
+      std::vector<Tile> t;
+      plan_tiles(c, g.items.data(), (int)g.items.size(), t, g.caps);
+      g.tile_off = all_tiles.size();
+      g.n_tiles = t.size();
+      all_tiles.insert(all_tiles.end(), t.begin(), t.end());
+      max_px = std::max(max_px, g.n_px);
+      max_items = std::max(max_items, g.items.size());
+    }
+  }
+  HIP_TRY(c->d_tiles.ensure(all_tiles.size()));
+  HIP_TRY(c->h_tiles.ensure(all_tiles.size()));
+  std::copy(all_tiles.begin(), all_tiles.end(), c->h_tiles.p);
+  if (!all_tiles.empty())
+    HIP_TRY(hipMemcpyAsync(c->d_tiles.p, c->h_tiles.p, sizeof(Tile) * all_tiles.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(c->d_phi.ensure((size_t)std::max<int64_t>(max_px, 1)));
+  HIP_TRY(c->d_items.ensure(std::max<size_t>(max_items, 1)));
+  HIP_TRY(c->h_items.ensure(std::max<size_t>(max_items, 1)));
+
+  // Alg. 2 line 2: random initial labels and their per-pixel costs.
+  std::vector<float> mirror((size_t)W * H * 3);
+  if ((st = lexp_init_labels_host(W, H, c->prm.disp_max, seed, mirror.data()))) return st;
+  if ((st = upload_labels(c, mirror.data(), labels, s))) return st;
+  if ((st = pixel_costs_impl(c, labels, cur_cost, s))) return st;
+  if (energy_trace) {
+    if ((st = energy_impl(c, labels, cur_cost, &energy_trace[0], nullptr, nullptr, s))) return st;
+  }
+  if (time_trace) time_trace[0] = now_s();
+
+  std::vector<lexp_plane> alphas(max_items);
+  double r_d = c->prm.disp_max / 2.0, r_n = 1.0;  // Alg. 2 line 3
+  for (int it = 0; it < sch->iterations; ++it) {
+    for (int h = 0; h < sch->n_levels; ++h) {
+      const int cell = sch->cell[h], kp = sch->k_prop[h], kr = sch->k_rand[h];
+      for (int k = 0; k < 16; ++k) {
+        Group& g = groups[(size_t)h * 16 + k];
+        const int n = (int)g.items.size();
+        if (n == 0) continue;
+        for (int step = 0; step < kp + kr; ++step) {
+          // proposals from the latest labels (Alg. 1)
+          c->pool->parallel_for(n, [&](int q, int) {
+            float a[3];
+            lexp::propose(W, H, mirror.data(), 3, seed, it, h, cell, g.ci[q], g.cj[q], step, kp, r_d, r_n, a);
+            g.items[q].a = a[0];
+            g.items[q].b = a[1];
+            g.items[q].c = a[2];
+          });
+          if ((st = wait_staging(c))) return st;
+          std::copy(g.items.begin(), g.items.end(), c->h_items.p);
+          HIP_TRY(hipMemcpyAsync(c->d_items.p, c->h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
+          st = launch_unary<0>(c, c->d_items.p, c->d_tiles.p + g.tile_off, (int)g.n_tiles, g.caps, nullptr,
+                               c->d_phi.p, s, g.bytes, g.n_px, n);
+          if (st) return st;
+          st = expand_batch(c, n, g.n_px, c->d_phi.p, labels, cur_cost, nullptr, nullptr, mirror.data(), nullptr, s,
+                            true);
+          if (st) return st;
+        }
+      }
+    }
+    r_d *= 0.5;  // Alg. 2 line 12
+    r_n *= 0.5;
+    if (energy_trace) {
+      if ((st = energy_impl(c, labels, cur_cost, &energy_trace[it + 1], nullptr, nullptr, s))) return st;
+    }
+    if (time_trace) time_trace[it + 1] = now_s();
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (c->timing) collect_timing(c);
+  return LEXP_OK;
+}
+
+lexp_status lexp_set_timing(lexp_ctx* c, int32_t enable) {
+  if (!c) return fail(LEXP_EINVAL, "null context");
+  c->timing = enable != 0;
+  return LEXP_OK;
+}
+
+lexp_status lexp_get_stats(lexp_ctx* c, lexp_stats* out) {
+  if (!c || !out) return fail(LEXP_EINVAL, "null argument");
+  collect_timing(c);
+  *out = c->stats;
+  return LEXP_OK;
+}
+
+lexp_status lexp_reset_stats(lexp_ctx* c) {
+  if (!c) return fail(LEXP_EINVAL, "null context");
+  collect_timing(c);
+  c->stats = lexp_stats{};
+  return LEXP_OK;
+}
+
+lexp_status lexp_debug_guide(lexp_ctx* c, float* left4, float* right4, float* guide, double* weights,
+                             void* hip_stream) {
+  if (!c) return fail(LEXP_EINVAL, "null context");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t n = (size_t)c->W * c->H;
+  if (left4) HIP_TRY(hipMemcpyAsync(left4, c->left4, n * 16, hipMemcpyDeviceToDevice, s));
+  if (right4) HIP_TRY(hipMemcpyAsync(right4, c->right4, n * 16, hipMemcpyDeviceToDevice, s));
+  if (guide) HIP_TRY(hipMemcpyAsync(guide, c->guide, n * 36, hipMemcpyDeviceToDevice, s));
+  if (weights) HIP_TRY(hipMemcpyAsync(weights, c->wts, n * 32, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return LEXP_OK;
+}
+
+// ---- host-side pieces ------------------------------------------------------
+lexp_status lexp_solve_binary(int32_t w, int32_t h, int32_t neighbours, const int64_t* U, const int64_t* w4,
+                              uint8_t* x) {
+  if (w < 0 || h < 0 || (neighbours != 4 && neighbours != 8)) return fail(LEXP_EINVAL, "bad grid");
+  if ((int64_t)w * h > 0 && (!U || !w4 || !x)) return fail(LEXP_EINVAL, "null argument");
+  for (int64_t i = 0; i < (int64_t)w * h * 4; ++i)
+    if (w4[i] < 0) return fail(LEXP_EINVAL, "negative pairwise weight (not submodular)");
+  if ((int64_t)w * h == 0) return LEXP_OK;
+  lexp::BKSolver bk;
+  bk.load<int64_t>(w, h, neighbours == 8 ? 4 : 2, U, 1, w4, 4);
+  bk.solve(x);
+  return LEXP_OK;
+}
+
+uint64_t lexp_rng_key(uint64_t seed, const uint64_t* fields, int32_t n_fields) {
+  return lexp::key_chain(seed, fields, n_fields > 0 && fields ? n_fields : 0);
+}
+
+lexp_status lexp_init_labels_host(int32_t width, int32_t height, double disp_max, uint64_t seed, float* labels) {
+  if (width <= 0 || height <= 0 || !labels) return fail(LEXP_EINVAL, "bad argument");
+  for (int v = 0; v < height; ++v)
+    for (int u = 0; u < width; ++u) lexp::init_label(width, u, v, disp_max, seed, labels + ((size_t)v * width + u) * 3);
+  return LEXP_OK;
+}
+
+lexp_status lexp_propose(int32_t width, int32_t height, const float* labels, uint64_t seed, int32_t iteration,
+                         int32_t level, int32_t cell, int32_t ci, int32_t cj, int32_t step, int32_t k_prop,
+                         double r_d, double r_n, lexp_plane* out) {
+  if (width <= 0 || height <= 0 || !labels || !out || cell < 1) return fail(LEXP_EINVAL, "bad argument");
+  if (ci < 0 || cj < 0 || ci * cell >= width || cj * cell >= height) return fail(LEXP_EINVAL, "cell outside the image");
+  float a[3];
+  lexp::propose(width, height, labels, 3, seed, iteration, level, cell, ci, cj, step, k_prop, r_d, r_n, a);
+  out->a = a[0];
+  out->b = a[1];
+  out->c = a[2];
+  return LEXP_OK;
+}
+
+}  // extern "C"

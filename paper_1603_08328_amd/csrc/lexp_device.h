@@ -1,0 +1,64 @@
+// Types shared by the device kernels and their host-side launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lexp {
+
+constexpr int kChunk = 4;              // rows per pipeline step of the fused cost kernel (one per wave)
+constexpr double kQuantum = 1048576.0;  // 2^20: binary-problem terms are ceil(x * 2^20)
+
+// forward neighbour offsets: each unordered pair of the 8-neighbourhood once
+__device__ constexpr int kFwdDU[4] = {1, 0, 1, -1};
+__device__ constexpr int kFwdDV[4] = {0, 1, 1, 1};
+
+enum TileFlags : int { kFirstCol = 1, kLastCol = 2, kFirstRow = 4, kLastRow = 8 };
+
+struct DevParams {
+  int W, H, r, nf;
+  float oma, al, tc, tg, rho_max;  // 1-alpha, alpha, tau_col, tau_grad, rho_max (FP32 data term)
+  double lam, tau_dis, w_floor;    // smoothness term (FP64)
+};
+
+// One (region, label) item: clipped region, candidate label, output offset.
+struct Item {
+  int ru0, rv0, rw, rh;
+  float a, b, c, pad;
+  long long out_off;  // first phi value of the item (caller layout)
+  long long aux_off;  // first pixel of the item in the graph-term / cut buffers
+};
+
+// One workgroup's sub-rectangle of an item's region.
+struct Tile {
+  int item;
+  int tu0, tv0, tu1, tv1;
+  int flags;
+  int pad0, pad1;
+};
+
+// LDS bytes of one fused-cost workgroup for the given capacities.
+inline size_t unary_lds_bytes(int ring, int wp_cap, int tw_cap, int ws_cap) {
+  const size_t n = (size_t)ring * wp_cap + (size_t)kChunk * wp_cap + (size_t)ring * tw_cap + 4 * (size_t)ws_cap;
+  return n * (sizeof(float) * 4 + sizeof(float));
+}
+
+template <int MODE>
+__global__ void k_unary(DevParams P, const float4* left4, const float4* right4, const float* guide,
+                        const Item* items, const Tile* tiles, int n_tiles, const float4* label_field, float* out,
+                        int ring, int wp_cap, int tw_cap, int ws_cap);
+__global__ void k_pack(const float* img, float4* out, int W, int H);
+__global__ void k_guide_h(const float4* left4, double* tmp, int W, int H, int r);
+__global__ void k_guide_v(const double* tmp, float* guide, int W, int H, int r, double eps);
+__global__ void k_weights(const float* left, double* wts, int W, int H, double gamma);
+__global__ void k_graph_terms(DevParams P, const Item* items, const float4* labels, const float* cur_cost,
+                              const float* phi_alpha, const double* wts, int* terms, int* flag);
+__global__ void k_apply(int W, const Item* items, const uint8_t* x, const float* phi_alpha, float4* labels,
+                        float* cur_cost);
+__global__ void k_energy(DevParams P, const float4* labels, const float* cur_cost, const double* wts,
+                         double* partial);
+__global__ void k_pair1(DevParams P, const double* wts, int pu, int pv, int qu, int qv, float4 fp, float4 fq,
+                        double* out);
+
+}  // namespace lexp

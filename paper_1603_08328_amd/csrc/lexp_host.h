@@ -1,0 +1,94 @@
+// Host-side pieces of the library that need no device: counter-based random
+// numbers, the proposers of Alg. 1 / Alg. 2, the Boykov-Kolmogorov max-flow
+// used to solve one local expansion exactly, and a small thread pool.
+#pragma once
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <functional>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+namespace lexp {
+
+// ---- random numbers ------------------------------------------------------
+uint64_t sm64(uint64_t x);
+uint64_t key_chain(uint64_t seed, const uint64_t* fields, int n);
+double u01_open1(uint64_t x);    // [0, 1)
+double u01_open0(uint64_t x);    // (0, 1]
+
+// Random initial label of pixel (u, v) (Alg. 2 line 2).
+void init_label(int width, int u, int v, double disp_max, uint64_t seed, float out[3]);
+
+// Candidate label of one alpha_ij-expansion step (Alg. 1).  labels: HxWx3
+// host mirror (stride `stride` floats per pixel).
+void propose(int width, int height, const float* labels, int stride, uint64_t seed, int iteration, int level,
+             int cell, int ci, int cj, int step, int k_prop, double r_d, double r_n, float out[3]);
+
+// ---- exact binary minimisation ------------------------------------------
+// E(x) = sum_i U_i x_i + sum_{i, d < nf} w_{i,d} (1 - x_i) x_{i + fwd_d} on a
+// w x h grid, forward directions (1,0), (0,1), (1,1), (-1,1) (nf = 4 for the
+// 8-neighbourhood, 2 for the 4-neighbourhood).
+class BKSolver {
+ public:
+  // terms: per node (U, w_0..w_3) at `stride` elements apart.
+  template <class T>
+  void load(int w, int h, int nf, const T* U, int u_stride, const T* w4, int w_stride);
+  // Max-flow, then x_i = 1 for nodes reachable from the source in the
+  // residual graph (the minimiser with the fewest ones).
+  void solve(uint8_t* x);
+  int64_t flow() const { return flow_; }
+
+ private:
+  enum : int8_t { kNone = -1, kTerm = 8, kOrphan = 9 };
+  enum : uint8_t { kFree = 0, kS = 1, kT = 2 };
+  int nbr(int i, int k) const { return nbr_[(size_t)i * 8 + k]; }
+  void push_active(int i);
+  void make_orphan(int i);
+  void augment(int a, int k, int b);
+  void adopt();
+
+  int w_ = 0, h_ = 0, n_ = 0, nf_ = 4;
+  int dirs_[8];
+  int ndirs_ = 0;
+  int64_t flow_ = 0;
+  int32_t time_ = 0;
+  std::vector<int64_t> tr_;
+  std::vector<int64_t> rc_;
+  std::vector<int32_t> nbr_;
+  std::vector<int8_t> parent_;
+  std::vector<uint8_t> tree_;
+  std::vector<uint8_t> in_active_;
+  std::vector<int32_t> ts_, dist_;
+  std::vector<int32_t> active_;   // circular FIFO
+  size_t a_head_ = 0, a_tail_ = 0, a_cap_ = 0;
+  std::vector<int32_t> orphans_;
+  size_t o_head_ = 0;
+  std::vector<int32_t> bfs_;
+};
+
+// ---- thread pool -----------------------------------------------------------
+class ThreadPool {
+ public:
+  explicit ThreadPool(int n_threads);
+  ~ThreadPool();
+  int size() const { return (int)workers_.size() + 1; }
+  // Runs fn(item, worker) for item in [0, n); the caller takes part as worker 0.
+  void parallel_for(int n, const std::function<void(int, int)>& fn);
+
+ private:
+  void worker_loop(int id);
+  std::vector<std::thread> workers_;
+  std::mutex mu_;
+  std::condition_variable cv_start_, cv_done_;
+  const std::function<void(int, int)>* job_ = nullptr;
+  int n_items_ = 0;
+  std::atomic<int> next_{0};
+  int pending_ = 0;
+  uint64_t generation_ = 0;
+  bool stop_ = false;
+};
+
+}  // namespace lexp

@@ -1,0 +1,549 @@
+// Device kernels of the local-expansion-move hot path for CDNA4 (gfx950).
+//
+//   k_pack / k_guide_h / k_guide_v / k_weights : label-independent set-up
+//   k_unary<MODE>                              : fused raw cost (Eqs. 8, 9, 18)
+//                                                + guided-filter aggregation
+//                                                (Eq. 7 box form, Eq. 19)
+//   k_graph_terms                              : binary problem of one local
+//                                                expansion (Eq. 13, Lemma 2)
+//   k_apply, k_energy, k_pair1                 : label update, Eq. (5), Eq. (10)
+//
+// Built with -ffp-contract=off: products and sums are rounded as written and
+// fused multiply-adds appear only where fmaf() is called explicitly.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lexp_device.h"
+
+namespace lexp {
+
+// ---------------------------------------------------------------------------
+// Set-up
+// ---------------------------------------------------------------------------
+__device__ inline float gray_of(const float* px) {
+  return 0.299f * px[0] + 0.587f * px[1] + 0.114f * px[2];
+}
+
+// (R, G, B, x-gradient of the gray value by [-0.5 0 0.5], replicated borders)
+__global__ void k_pack(const float* __restrict__ img, float4* __restrict__ out, int W, int H) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= W * H) return;
+  const int u = i % W, v = i / W;
+  const int ul = u > 0 ? u - 1 : 0, ur = u < W - 1 ? u + 1 : W - 1;
+  const float* row = img + (size_t)v * W * 3;
+  const float gx = 0.5f * (gray_of(row + ur * 3) - gray_of(row + ul * 3));
+  out[i] = make_float4(row[u * 3 + 0], row[u * 3 + 1], row[u * 3 + 2], gx);
+}
+
+// Horizontal window sums of I = I_L/255 and I I^T (FP64).
+__global__ void k_guide_h(const float4* __restrict__ left4, double* __restrict__ tmp, int W, int H, int r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= W * H) return;
+  const int u = i % W, v = i / W;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const int x0 = u - r > 0 ? u - r : 0, x1 = u + r < W - 1 ? u + r : W - 1;
+  for (int x = x0; x <= x1; ++x) {
+    const float4 p = left4[(size_t)v * W + x];
+    const double I0 = (double)p.x / 255.0, I1 = (double)p.y / 255.0, I2 = (double)p.z / 255.0;
+    acc[0] += I0; acc[1] += I1; acc[2] += I2;
+    acc[3] += I0 * I0; acc[4] += I0 * I1; acc[5] += I0 * I2;
+    acc[6] += I1 * I1; acc[7] += I1 * I2; acc[8] += I2 * I2;
+  }
+  for (int q = 0; q < 9; ++q) tmp[(size_t)q * W * H + i] = acc[q];
+}
+
+// Vertical sums -> mean mu_k and (Sigma_k + eU)^-1 by the adjugate, stored as
+// nine float planes (mu0, mu1, mu2, i00, i01, i02, i11, i12, i22).
+__global__ void k_guide_v(const double* __restrict__ tmp, float* __restrict__ guide, int W, int H, int r,
+                          double eps) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= W * H) return;
+  const int u = i % W, v = i / W;
+  const int y0 = v - r > 0 ? v - r : 0, y1 = v + r < H - 1 ? v + r : H - 1;
+  const int x0 = u - r > 0 ? u - r : 0, x1 = u + r < W - 1 ? u + r : W - 1;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int y = y0; y <= y1; ++y)
+    for (int q = 0; q < 9; ++q) acc[q] += tmp[(size_t)q * W * H + (size_t)y * W + u];
+  const double n = (double)(x1 - x0 + 1) * (double)(y1 - y0 + 1);
+  const double m0 = acc[0] / n, m1 = acc[1] / n, m2 = acc[2] / n;
+  const double a00 = acc[3] / n - m0 * m0 + eps, a01 = acc[4] / n - m0 * m1, a02 = acc[5] / n - m0 * m2;
+  const double a11 = acc[6] / n - m1 * m1 + eps, a12 = acc[7] / n - m1 * m2;
+  const double a22 = acc[8] / n - m2 * m2 + eps;
+  const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+  const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
+  const double det = a00 * c00 + a01 * c01 + a02 * c02;
+  const double id = 1.0 / det;
+  const size_t hw = (size_t)W * H;
+  guide[0 * hw + i] = (float)m0;
+  guide[1 * hw + i] = (float)m1;
+  guide[2 * hw + i] = (float)m2;
+  guide[3 * hw + i] = (float)(c00 * id);
+  guide[4 * hw + i] = (float)(c01 * id);
+  guide[5 * hw + i] = (float)(c02 * id);
+  guide[6 * hw + i] = (float)(c11 * id);
+  guide[7 * hw + i] = (float)(c12 * id);
+  guide[8 * hw + i] = (float)(c22 * id);
+}
+
+// Contrast weights w_pq = exp(-||I_L(p) - I_L(q)||_1 / gamma), Eq. (11), for
+// the forward neighbours q = p + (1,0), (0,1), (1,1), (-1,1); 0 outside.
+__global__ void k_weights(const float* __restrict__ left, double* __restrict__ wts, int W, int H, double gamma) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= W * H) return;
+  const int u = i % W, v = i / W;
+  const float* a = left + (size_t)i * 3;
+  for (int d = 0; d < 4; ++d) {
+    const int qu = u + kFwdDU[d], qv = v + kFwdDV[d];
+    double w = 0.0;
+    if (qu >= 0 && qu < W && qv < H) {
+      const float* b = left + ((size_t)qv * W + qu) * 3;
+      double s = fabs((double)a[0] - (double)b[0]) + fabs((double)a[1] - (double)b[1]);
+      s = s + fabs((double)a[2] - (double)b[2]);
+      w = exp(-s / gamma);
+    }
+    wts[(size_t)i * 4 + d] = w;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused unary cost.  One workgroup (4 wave64) per tile: a sub-rectangle of
+// one item's region.  Rows stream top to bottom through four stages per
+// chunk of kChunk rows:
+//   A  raw cost rho' = rho - rho_max and rho' * I over one row of M per wave,
+//      wave prefix scan, horizontal window sums at the R+ columns -> ring1
+//   C  per R+ column: running vertical sums -> means over W'_k ->
+//      a_k = (Sigma_k + eU)^-1 (mean(I rho) - mu mean(rho)), b_k -> coef rows
+//   E  per coef row (one per wave): prefix scan, window sums at R columns -> ring3
+//   G  per R column: running vertical sums -> phi = abar^T I_p + bbar + rho_max
+// A fifth channel counts samples with rho' != 0 (an exact integer in FP32):
+// where a window holds none, the sums are zero exactly, so a fully truncated
+// or out-of-view patch costs exactly rho_max under any label.
+// ---------------------------------------------------------------------------
+__device__ inline float4 f4add(float4 a, float4 b) { return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
+__device__ inline float4 f4sub(float4 a, float4 b) { return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w); }
+
+__device__ inline void wave_scan(float4& v, float& c, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const float tx = __shfl_up(v.x, o, 64), ty = __shfl_up(v.y, o, 64);
+    const float tz = __shfl_up(v.z, o, 64), tw = __shfl_up(v.w, o, 64);
+    const float tc = __shfl_up(c, o, 64);
+    if (lane >= o) {
+      v.x += tx; v.y += ty; v.z += tz; v.w += tw; c += tc;
+    }
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_unary(DevParams P, const float4* __restrict__ left4,
+                                               const float4* __restrict__ right4, const float* __restrict__ guide,
+                                               const Item* __restrict__ items, const Tile* __restrict__ tiles,
+                                               int n_tiles, const float4* __restrict__ label_field,
+                                               float* __restrict__ out, int ring, int wp_cap, int tw_cap,
+                                               int ws_cap) {
+  extern __shared__ float4 smem4[];
+  // blocks are dispatched round-robin over the 8 XCDs; give every XCD a
+  // contiguous run of tiles so neighbouring tiles share its L2
+  const int per = (int)(gridDim.x >> 3);
+  const int t_id = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+  if (t_id >= n_tiles) return;
+
+  const int W = P.W, H = P.H, r = P.r;
+  int tu0, tv0, tu1, tv1, ru0 = 0, rv0 = 0, rw = 1, flags = 15;
+  float la, lb, lc;
+  long long out_off;
+  if (MODE == 2) {
+    tu0 = t_id % W; tv0 = t_id / W; tu1 = tu0 + 1; tv1 = tv0 + 1;
+    const float4 f = label_field[t_id];
+    la = f.x; lb = f.y; lc = f.z;
+    ru0 = tu0; rv0 = tv0; rw = 1;
+    out_off = t_id;
+  } else {
+    const Tile tl = tiles[t_id];
+    const Item it = items[tl.item];
+    tu0 = tl.tu0; tv0 = tl.tv0; tu1 = tl.tu1; tv1 = tl.tv1; flags = tl.flags;
+    la = it.a; lb = it.b; lc = it.c;
+    ru0 = it.ru0; rv0 = it.rv0; rw = it.rw;
+    out_off = it.out_off;
+    if (MODE == 1) {  // output indexed over the item's R+
+      const int pu0 = ru0 - r > 0 ? ru0 - r : 0, pv0 = rv0 - r > 0 ? rv0 - r : 0;
+      const int pu1 = ru0 + rw + r < W ? ru0 + rw + r : W;
+      rw = pu1 - pu0;
+      ru0 = pu0;
+      rv0 = pv0;
+    }
+  }
+  const int xp0 = tu0 - r > 0 ? tu0 - r : 0, xp1 = tu1 + r < W ? tu1 + r : W;
+  const int yp0 = tv0 - r > 0 ? tv0 - r : 0, yp1 = tv1 + r < H ? tv1 + r : H;
+  const int xm0 = tu0 - 2 * r > 0 ? tu0 - 2 * r : 0, xm1 = tu1 + 2 * r < W ? tu1 + 2 * r : W;
+  const int ym0 = tv0 - 2 * r > 0 ? tv0 - 2 * r : 0, ym1 = tv1 + 2 * r < H ? tv1 + 2 * r : H;
+  const int wM = xm1 - xm0, wP = xp1 - xp0, tw = tu1 - tu0;
+  // R+ part this tile reports in MODE 1 (column / row strips own disjoint parts)
+  const int own_u0 = (flags & kFirstCol) ? xp0 : tu0, own_u1 = (flags & kLastCol) ? xp1 : tu1;
+  const int own_v0 = (flags & kFirstRow) ? yp0 : tv0, own_v1 = (flags & kLastRow) ? yp1 : tv1;
+
+  // shared memory carve-up
+  float4* ring1v = smem4;
+  float4* coefv = ring1v + (size_t)ring * wp_cap;
+  float4* ring3v = coefv + (size_t)kChunk * wp_cap;
+  float4* scanv = ring3v + (size_t)ring * tw_cap;
+  float* ring1c = reinterpret_cast<float*>(scanv + (size_t)4 * ws_cap);
+  float* coefc = ring1c + (size_t)ring * wp_cap;
+  float* ring3c = coefc + (size_t)kChunk * wp_cap;
+  float* scanc = ring3c + (size_t)ring * tw_cap;
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const float inv255 = 1.0f / 255.0f;
+  const float fW1 = (float)(W - 1);
+
+  int produced = ym0;                 // next M row to produce
+  int kv = yp0;                       // next R+ row to emit
+  int hi_cur = ym0 - 1, lo_cur = ym0; // rows summed in V1
+  int pv = tv0;                       // next R row to output
+  int hi2_cur = yp0 - 1, lo2_cur = yp0;
+  float4 V1 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float V1c = 0.f;
+  float4 V2 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float V2c = 0.f;
+
+  for (;;) {
+    if (MODE == 1 ? (kv >= own_v1) : (pv >= tv1)) break;
+    // ---- A: raw cost rows -> horizontal window sums ----------------------
+    const int nA = min(kChunk, ym1 - produced);
+    float4* sv = scanv + (size_t)wave * ws_cap;
+    float* sc = scanc + (size_t)wave * ws_cap;
+    if (wave < nA) {
+      const int y = produced + wave;
+      const float vf = (float)y;
+      float4 carry = make_float4(0.f, 0.f, 0.f, 0.f);
+      float carryc = 0.f;
+      for (int s0 = 0; s0 < wM; s0 += 64) {
+        const int xi = s0 + lane;
+        float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+        float nz = 0.f;
+        if (xi < wM) {
+          const int x = xm0 + xi;
+          const float uf = (float)x;
+          const float d = fmaf(la, uf, fmaf(lb, vf, lc));
+          const float xs = uf - d;
+          if (xs >= 0.f && xs <= fW1) {
+            const float xf = floorf(xs);
+            int i0 = (int)xf;
+            float t = xs - xf;
+            int i1 = i0 + 1;
+            if (i0 >= W - 1) { i0 = W - 1; i1 = W - 1; t = 0.f; }
+            const float4 R0 = right4[(size_t)y * W + i0];
+            const float4 R1 = right4[(size_t)y * W + i1];
+            const float4 L = left4[(size_t)y * W + x];
+            const float col = fabsf(L.x - fmaf(t, R1.x - R0.x, R0.x)) + fabsf(L.y - fmaf(t, R1.y - R0.y, R0.y)) +
+                              fabsf(L.z - fmaf(t, R1.z - R0.z, R0.z));
+            const float gr = fabsf(L.w - fmaf(t, R1.w - R0.w, R0.w));
+            const float rp = P.oma * (fminf(col, P.tc) - P.tc) + P.al * (fminf(gr, P.tg) - P.tg);
+            if (rp != 0.f) {
+              val = make_float4(rp, rp * (L.x * inv255), rp * (L.y * inv255), rp * (L.z * inv255));
+              nz = 1.f;
+            }
+          }
+        }
+        wave_scan(val, nz, lane);
+        val = f4add(val, carry);
+        nz += carryc;
+        if (xi < wM) { sv[xi] = val; sc[xi] = nz; }
+        carry = make_float4(__shfl(val.x, 63, 64), __shfl(val.y, 63, 64), __shfl(val.z, 63, 64),
+                            __shfl(val.w, 63, 64));
+        carryc = __shfl(nz, 63, 64);
+      }
+    }
+    __syncthreads();
+    if (wave < nA) {
+      const int y = produced + wave;
+      const int slot = y % ring;
+      for (int s0 = 0; s0 < wP; s0 += 64) {
+        const int xi = s0 + lane;
+        if (xi < wP) {
+          const int x = xp0 + xi;
+          const int lo = (x - r > 0 ? x - r : 0) - xm0;
+          const int hi = (x + r < W - 1 ? x + r : W - 1) - xm0;
+          float4 h = sv[hi];
+          float hc = sc[hi];
+          if (lo > 0) { h = f4sub(h, sv[lo - 1]); hc -= sc[lo - 1]; }
+          if (hc == 0.f) h = make_float4(0.f, 0.f, 0.f, 0.f);
+          ring1v[(size_t)slot * wp_cap + xi] = h;
+          ring1c[(size_t)slot * wp_cap + xi] = hc;
+        }
+      }
+    }
+    produced += nA;
+    __syncthreads();
+
+    // ---- C: vertical sums over W'_k, linear coefficients -----------------
+    const int kv_start = kv;
+    int nC = 0;
+    while (nC < kChunk && kv < yp1) {
+      const int hi_k = kv + r < H - 1 ? kv + r : H - 1;
+      if (hi_k >= produced) break;
+      const int lo_k = kv - r > 0 ? kv - r : 0;
+      if (tid < wP) {
+        for (int y = hi_cur + 1; y <= hi_k; ++y) {
+          V1 = f4add(V1, ring1v[(size_t)(y % ring) * wp_cap + tid]);
+          V1c += ring1c[(size_t)(y % ring) * wp_cap + tid];
+        }
+        for (int y = lo_cur; y < lo_k; ++y) {
+          V1 = f4sub(V1, ring1v[(size_t)(y % ring) * wp_cap + tid]);
+          V1c -= ring1c[(size_t)(y % ring) * wp_cap + tid];
+        }
+        const int x = xp0 + tid;
+        const int cx0 = x - r > 0 ? x - r : 0, cx1 = x + r < W - 1 ? x + r : W - 1;
+        const float nk = (float)((cx1 - cx0 + 1) * (hi_k - lo_k + 1));
+        const float inv_n = 1.0f / nk;
+        float4 coef = make_float4(0.f, 0.f, 0.f, 0.f);
+        float z = 0.f;
+        if (V1c != 0.f) {
+          const size_t hw = (size_t)W * H, gi = (size_t)kv * W + x;
+          const float mu0 = guide[gi], mu1 = guide[hw + gi], mu2 = guide[2 * hw + gi];
+          const float i00 = guide[3 * hw + gi], i01 = guide[4 * hw + gi], i02 = guide[5 * hw + gi];
+          const float i11 = guide[6 * hw + gi], i12 = guide[7 * hw + gi], i22 = guide[8 * hw + gi];
+          const float m0 = V1.x * inv_n;
+          const float c0 = V1.y * inv_n - mu0 * m0;
+          const float c1 = V1.z * inv_n - mu1 * m0;
+          const float c2 = V1.w * inv_n - mu2 * m0;
+          const float a0 = i00 * c0 + i01 * c1 + i02 * c2;
+          const float a1 = i01 * c0 + i11 * c1 + i12 * c2;
+          const float a2 = i02 * c0 + i12 * c1 + i22 * c2;
+          const float b = m0 - (a0 * mu0 + a1 * mu1 + a2 * mu2);
+          coef = make_float4(a0, a1, a2, b);
+          z = 1.f;
+        }
+        if (MODE == 1) {
+          if (x >= own_u0 && x < own_u1 && kv >= own_v0 && kv < own_v1) {
+            // coefficients of rho itself: a is unchanged by the shift, b gains rho_max
+            float* o = out + (out_off + (long long)(kv - rv0) * rw + (x - ru0)) * 4;
+            o[0] = coef.x; o[1] = coef.y; o[2] = coef.z; o[3] = coef.w + P.rho_max;
+          }
+        } else {
+          coefv[(size_t)nC * wp_cap + tid] = coef;
+          coefc[(size_t)nC * wp_cap + tid] = z;
+        }
+      }
+      hi_cur = hi_k;
+      lo_cur = lo_k;
+      ++kv;
+      ++nC;
+    }
+    __syncthreads();
+    if (MODE == 1) continue;
+
+    // ---- E: horizontal sums of (a, b) at the R columns --------------------
+    if (wave < nC) {
+      float4 carry = make_float4(0.f, 0.f, 0.f, 0.f);
+      float carryc = 0.f;
+      const float4* cv = coefv + (size_t)wave * wp_cap;
+      const float* cc = coefc + (size_t)wave * wp_cap;
+      for (int s0 = 0; s0 < wP; s0 += 64) {
+        const int xi = s0 + lane;
+        float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+        float z = 0.f;
+        if (xi < wP) { val = cv[xi]; z = cc[xi]; }
+        wave_scan(val, z, lane);
+        val = f4add(val, carry);
+        z += carryc;
+        if (xi < wP) { sv[xi] = val; sc[xi] = z; }
+        carry = make_float4(__shfl(val.x, 63, 64), __shfl(val.y, 63, 64), __shfl(val.z, 63, 64),
+                            __shfl(val.w, 63, 64));
+        carryc = __shfl(z, 63, 64);
+      }
+    }
+    __syncthreads();
+    if (wave < nC) {
+      const int slot = (kv_start + wave) % ring;
+      for (int s0 = 0; s0 < tw; s0 += 64) {
+        const int xi = s0 + lane;
+        if (xi < tw) {
+          const int x = tu0 + xi;
+          const int lo = (x - r > 0 ? x - r : 0) - xp0;
+          const int hi = (x + r < W - 1 ? x + r : W - 1) - xp0;
+          float4 h = sv[hi];
+          float hc = sc[hi];
+          if (lo > 0) { h = f4sub(h, sv[lo - 1]); hc -= sc[lo - 1]; }
+          if (hc == 0.f) h = make_float4(0.f, 0.f, 0.f, 0.f);
+          ring3v[(size_t)slot * tw_cap + xi] = h;
+          ring3c[(size_t)slot * tw_cap + xi] = hc;
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- G: vertical sums over W'(p), output -------------------------------
+    while (pv < tv1) {
+      const int hi2 = pv + r < H - 1 ? pv + r : H - 1;
+      if (hi2 >= kv) break;
+      const int lo2 = pv - r > 0 ? pv - r : 0;
+      if (tid < tw) {
+        for (int y = hi2_cur + 1; y <= hi2; ++y) {
+          V2 = f4add(V2, ring3v[(size_t)(y % ring) * tw_cap + tid]);
+          V2c += ring3c[(size_t)(y % ring) * tw_cap + tid];
+        }
+        for (int y = lo2_cur; y < lo2; ++y) {
+          V2 = f4sub(V2, ring3v[(size_t)(y % ring) * tw_cap + tid]);
+          V2c -= ring3c[(size_t)(y % ring) * tw_cap + tid];
+        }
+        const int x = tu0 + tid;
+        const int cx0 = x - r > 0 ? x - r : 0, cx1 = x + r < W - 1 ? x + r : W - 1;
+        const float np = (float)((cx1 - cx0 + 1) * (hi2 - lo2 + 1));
+        float phi = 0.f;
+        if (V2c != 0.f) {
+          const float4 L = left4[(size_t)pv * W + x];
+          phi = (V2.x * (L.x * inv255) + V2.y * (L.y * inv255) + V2.z * (L.z * inv255) + V2.w) / np;
+        }
+        out[out_off + (long long)(pv - rv0) * rw + (x - ru0)] = phi + P.rho_max;
+      }
+      hi2_cur = hi2;
+      lo2_cur = lo2;
+      ++pv;
+    }
+  }
+}
+
+template __global__ void k_unary<0>(DevParams, const float4*, const float4*, const float*, const Item*, const Tile*,
+                                    int, const float4*, float*, int, int, int, int);
+template __global__ void k_unary<1>(DevParams, const float4*, const float4*, const float*, const Item*, const Tile*,
+                                    int, const float4*, float*, int, int, int, int);
+template __global__ void k_unary<2>(DevParams, const float4*, const float4*, const float*, const Item*, const Tile*,
+                                    int, const float4*, float*, int, int, int, int);
+
+// ---------------------------------------------------------------------------
+// Smoothness term (Eqs. 10-12) in FP64, rounded as written.
+// ---------------------------------------------------------------------------
+__device__ inline double plane_at(float a, float b, float c, int u, int v) {
+  const double t1 = (double)a * (double)u;
+  const double t2 = (double)b * (double)v;
+  const double s = t1 + t2;
+  return s + (double)c;
+}
+
+__device__ inline double psi(const DevParams& P, double w, float4 fp, float4 fq, int pu, int pv, int qu, int qv) {
+  const double dpp = plane_at(fp.x, fp.y, fp.z, pu, pv), dpq = plane_at(fq.x, fq.y, fq.z, pu, pv);
+  const double dqq = plane_at(fq.x, fq.y, fq.z, qu, qv), dqp = plane_at(fp.x, fp.y, fp.z, qu, qv);
+  const double pb = fabs(dpp - dpq) + fabs(dqq - dqp);
+  const double wt = w > P.w_floor ? w : P.w_floor;
+  const double tr = pb < P.tau_dis ? pb : P.tau_dis;
+  return P.lam * wt * tr;
+}
+
+__device__ inline long long qceil(double x) { return (long long)ceil(x * kQuantum); }
+
+__device__ inline bool same_label(float4 a, float4 b) {
+  return __float_as_uint(a.x) == __float_as_uint(b.x) && __float_as_uint(a.y) == __float_as_uint(b.y) &&
+         __float_as_uint(a.z) == __float_as_uint(b.z);
+}
+
+// Binary problem of one local expansion per item: for every p in the region,
+// U_p (cost of taking alpha) and w_d (cost of x_p = 0, x_{p+fwd_d} = 1).
+__global__ void k_graph_terms(DevParams P, const Item* __restrict__ items, const float4* __restrict__ labels,
+                              const float* __restrict__ cur_cost, const float* __restrict__ phi_alpha,
+                              const double* __restrict__ wts, int* __restrict__ terms, int* __restrict__ flag) {
+  const Item it = items[blockIdx.y];
+  const int li = blockIdx.x * blockDim.x + threadIdx.x;
+  if (li >= it.rw * it.rh) return;
+  const int W = P.W, H = P.H;
+  const int pu = it.ru0 + li % it.rw, pv = it.rv0 + li / it.rw;
+  const float4 fp = labels[(size_t)pv * W + pu];
+  const float4 al = make_float4(it.a, it.b, it.c, 0.f);
+  int* o = terms + (size_t)(it.aux_off + li) * 5;
+  if (same_label(fp, al)) {  // phi_p(alpha) = phi_p(f_p): every term cancels
+    o[0] = 0; o[1] = 0; o[2] = 0; o[3] = 0; o[4] = 0;
+    return;
+  }
+  long long U = qceil((double)phi_alpha[it.out_off + li]) - qceil((double)cur_cost[(size_t)pv * W + pu]);
+  long long wf[4] = {0, 0, 0, 0};
+  const int nf = P.nf;
+  for (int q = 0; q < 2 * nf; ++q) {
+    const bool fwd = q < nf;
+    const int d = fwd ? q : q - nf;
+    const int nu = fwd ? pu + kFwdDU[d] : pu - kFwdDU[d];
+    const int nv = fwd ? pv + kFwdDV[d] : pv - kFwdDV[d];
+    if (nu < 0 || nu >= W || nv < 0 || nv >= H) continue;
+    const float4 fn = labels[(size_t)nv * W + nu];
+    const double w = fwd ? wts[((size_t)pv * W + pu) * 4 + d] : wts[((size_t)nv * W + nu) * 4 + d];
+    const bool inside = nu >= it.ru0 && nu < it.ru0 + it.rw && nv >= it.rv0 && nv < it.rv0 + it.rh;
+    if (!inside) {
+      U += qceil(psi(P, w, al, fn, pu, pv, nu, nv)) - qceil(psi(P, w, fp, fn, pu, pv, nu, nv));
+    } else if (fwd) {
+      const long long A = qceil(psi(P, w, fp, fn, pu, pv, nu, nv));
+      const long long B = qceil(psi(P, w, fp, al, pu, pv, nu, nv));
+      const long long C = qceil(psi(P, w, al, fn, pu, pv, nu, nv));
+      U += C - A;
+      const long long e = B + C - A;
+      wf[d] = e > 0 ? e : 0;
+    } else {
+      U -= qceil(psi(P, w, al, fp, nu, nv, pu, pv));
+    }
+  }
+  const long long lim = 1ll << 30;
+  if (U > lim || U < -lim || wf[0] > lim || wf[1] > lim || wf[2] > lim || wf[3] > lim) atomicOr(flag, 1);
+  o[0] = (int)U;
+  o[1] = (int)wf[0];
+  o[2] = (int)wf[1];
+  o[3] = (int)wf[2];
+  o[4] = (int)wf[3];
+}
+
+// labels[p] = alpha and cur_cost[p] = phi_p(alpha) where the cut took alpha.
+__global__ void k_apply(int W, const Item* __restrict__ items, const uint8_t* __restrict__ x,
+                        const float* __restrict__ phi_alpha, float4* __restrict__ labels, float* __restrict__ cur_cost) {
+  const Item it = items[blockIdx.y];
+  const int li = blockIdx.x * blockDim.x + threadIdx.x;
+  if (li >= it.rw * it.rh) return;
+  if (!x[it.aux_off + li]) return;
+  const int pu = it.ru0 + li % it.rw, pv = it.rv0 + li / it.rw;
+  labels[(size_t)pv * W + pu] = make_float4(it.a, it.b, it.c, 0.f);
+  cur_cost[(size_t)pv * W + pu] = phi_alpha[it.out_off + li];
+}
+
+// Eq. (5): per-block partial sums (FP64) of the unary and pairwise parts.
+__global__ void k_energy(DevParams P, const float4* __restrict__ labels, const float* __restrict__ cur_cost,
+                         const double* __restrict__ wts, double* __restrict__ partial) {
+  __shared__ double su[256], sp[256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double eu = 0.0, ep = 0.0;
+  if (i < P.W * P.H) {
+    const int u = i % P.W, v = i / P.W;
+    eu = (double)cur_cost[i];
+    const float4 fp = labels[i];
+    for (int d = 0; d < P.nf; ++d) {
+      const int qu = u + kFwdDU[d], qv = v + kFwdDV[d];
+      if (qu < 0 || qu >= P.W || qv >= P.H) continue;
+      ep += psi(P, wts[(size_t)i * 4 + d], fp, labels[(size_t)qv * P.W + qu], u, v, qu, qv);
+    }
+  }
+  su[threadIdx.x] = eu;
+  sp[threadIdx.x] = ep;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      su[threadIdx.x] += su[threadIdx.x + s];
+      sp[threadIdx.x] += sp[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = su[0];
+    partial[2 * blockIdx.x + 1] = sp[0];
+  }
+}
+
+// One smoothness term through the device path (inspection).
+__global__ void k_pair1(DevParams P, const double* __restrict__ wts, int pu, int pv, int qu, int qv, float4 fp,
+                        float4 fq, double* out) {
+  // weight of the unordered pair: stored at the endpoint it is forward from
+  double w = 0.0;
+  for (int d = 0; d < 4; ++d) {
+    if (qu - pu == kFwdDU[d] && qv - pv == kFwdDV[d]) w = wts[((size_t)pv * P.W + pu) * 4 + d];
+    if (pu - qu == kFwdDU[d] && pv - qv == kFwdDV[d]) w = wts[((size_t)qv * P.W + qu) * 4 + d];
+  }
+  out[0] = psi(P, w, fp, fq, pu, pv, qu, qv);
+}
+
+}  // namespace lexp

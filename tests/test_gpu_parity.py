@@ -1,0 +1,410 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Costs: |phi_gpu - phi_oracle| <= 1e-4 * max(|phi_oracle|, rho_max) (FP32
+device arithmetic against FP64 direct sums).  Integer outputs (binary-problem
+weights, labels after moves) are compared exactly; where the two sides'
+unary values straddle a decision, the FP64 margin of that decision is
+reported instead (near ties only).
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from synth import make_workload_pair, params_for, random_labels
+from _util import base_params, texture
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+L = pytest.importorskip("paper_1603_08328_amd.lexp")
+
+REL = 1e-4
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _label4(lab3):
+    h, w = lab3.shape[:2]
+    out = np.zeros((h, w, 4), np.float32)
+    out[..., :3] = lab3
+    return out
+
+
+def assert_cost_close(gpu, ora, rho_max, what=""):
+    gpu = np.asarray(gpu, np.float64)
+    ora = np.asarray(ora, np.float64)
+    assert gpu.shape == ora.shape
+    err = np.abs(gpu - ora)
+    bound = REL * np.maximum(np.abs(ora), rho_max)
+    bad = err > bound
+    assert not bad.any(), f"{what}: {bad.sum()} of {bad.size} beyond tolerance, max err {err.max():.3e}"
+
+
+class Pair:
+    def __init__(self, name=None, params=None, left=None, right=None):
+        if name is not None:
+            pair = make_workload_pair(name)
+            params = params_for(name)
+            left, right = pair.left, pair.right
+            self.gt = pair.gt_labels
+        self.p = dict(params)
+        self.left, self.right = left, right
+        self.ora = Oracle(self.p, left, right)
+        self.ctx = L.lexp_create(self.p, _cuda(left), _cuda(right))
+        self.W, self.H, self.r = int(self.p["width"]), int(self.p["height"]), int(self.p["gf_radius"])
+        self.rho_max = self.ora.rho_max
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    assert torch.cuda.is_available()
+    return Pair("tiny-64x48")
+
+
+@pytest.fixture(scope="module")
+def lowres():
+    return Pair("lowres-450x375")
+
+
+def _unary(P, rects, labels):
+    rects = np.asarray(rects, np.int32).reshape(-1, 4)
+    labels = np.asarray(labels, np.float32).reshape(-1, 3)
+    sizes = []
+    for u0, v0, u1, v1 in rects:
+        w = max(min(u1, P.W) - max(u0, 0), 0)
+        h = max(min(v1, P.H) - max(v0, 0), 0)
+        sizes.append(w * h)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    out = torch.full((max(int(np.sum(sizes)), 1),), float("nan"), dtype=torch.float32, device="cuda")
+    L.lexp_unary_cost(P.ctx, rects, labels, offs, out)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    return [out[o:o + s] for o, s in zip(offs, sizes)]
+
+
+def _label_mix(P, rng, n):
+    """GT planes, random slanted planes, fronto-parallel, steep, out-of-view."""
+    labs = []
+    for k in range(n):
+        kind = k % 5
+        if kind == 0:
+            labs.append(P.gt[rng.integers(P.H), rng.integers(P.W)])
+        elif kind == 1:
+            labs.append(random_labels(rng, 1, 1, float(P.p["disp_max"]))[0, 0])
+        elif kind == 2:
+            labs.append([0.0, 0.0, rng.uniform(0, P.p["disp_max"])])
+        elif kind == 3:
+            labs.append([rng.uniform(-3, 3), rng.uniform(-3, 3), rng.uniform(-100, 100)])
+        else:
+            labs.append([0.0, 0.0, 1e4])
+    return np.array(labs, np.float32)
+
+
+# ---------------------------------------------------------------------------
+def test_setup_buffers(tiny):
+    P = tiny
+    l4, r4, g, wt = (t.cpu().numpy() for t in L.lexp_debug_guide(P.ctx))
+    assert np.array_equal(l4[..., :3], P.left) and np.array_equal(r4[..., :3], P.right)
+    gl, gr = P.ora.grads()
+    assert np.allclose(l4[..., 3], gl, atol=2e-4) and np.allclose(r4[..., 3], gr, atol=2e-4)
+    mu, sg = P.ora.guide()
+    assert np.allclose(np.moveaxis(g[:3], 0, -1), mu, atol=1e-6)
+    e = P.p["gf_eps"]
+    S = np.zeros((P.H, P.W, 3, 3))
+    idx = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    for k, (i, j) in enumerate(idx):
+        S[..., i, j] = sg[..., k]
+        S[..., j, i] = sg[..., k]
+    inv = np.linalg.inv(S + e * np.eye(3))
+    got = np.moveaxis(g[3:], 0, -1)
+    for k, (i, j) in enumerate(idx):
+        assert np.allclose(got[..., k], inv[..., i, j], rtol=1e-4, atol=1e-3 * np.abs(inv).max())
+    for v in range(0, P.H, 7):
+        for u in range(0, P.W, 5):
+            for d, (du, dv) in enumerate([(1, 0), (0, 1), (1, 1), (-1, 1)]):
+                q = (u + du, v + dv)
+                if 0 <= q[0] < P.W and q[1] < P.H:
+                    assert wt[v, u, d] == pytest.approx(P.ora.weight((u, v), q), rel=4e-16)
+                else:
+                    assert wt[v, u, d] == 0.0
+
+
+def test_unary_tiny_every_region_of_the_grid(tiny):
+    P = tiny
+    rng = np.random.default_rng(0)
+    rects, labels = [], []
+    for j in range(-(-P.H // 5)):
+        for i in range(-(-P.W // 5)):
+            for lab in _label_mix(P, rng, 4):
+                rects.append(((i - 1) * 5, (j - 1) * 5, (i + 2) * 5, (j + 2) * 5))
+                labels.append(lab)
+    got = _unary(P, rects, labels)
+    for rc, lab, g in zip(rects, labels, got):
+        ref = P.ora.unary_region(rc, lab).reshape(-1)
+        assert_cost_close(g, ref, P.rho_max, f"rect {rc} label {lab}")
+
+
+@pytest.mark.parametrize("size", [(1, 1), (15, 15), (45, 45), (75, 75), (130, 100), (17, 140)])
+def test_unary_lowres_random_rects(lowres, size):
+    P = lowres
+    rng = np.random.default_rng(size[0] * 1000 + size[1])
+    rects = []
+    for k in range(6):
+        u0 = int(rng.integers(-size[0] // 2, P.W - size[0] // 2))
+        v0 = int(rng.integers(-size[1] // 2, P.H - size[1] // 2))
+        rects.append((u0, v0, u0 + size[0], v0 + size[1]))
+    rects.append((P.W - size[0], P.H - size[1], P.W, P.H))  # bottom-right corner
+    labels = _label_mix(P, rng, len(rects))
+    got = _unary(P, rects, labels)
+    for rc, lab, g in zip(rects, labels, got):
+        assert_cost_close(g, P.ora.unary_region(rc, lab).reshape(-1), P.rho_max, f"rect {rc} label {lab}")
+
+
+def test_unary_whole_image_one_item(lowres):
+    P = lowres
+    lab = P.gt[200, 220]
+    g = _unary(P, [(0, 0, P.W, P.H)], [lab])[0]
+    assert_cost_close(g, P.ora.unary_region((0, 0, P.W, P.H), lab).reshape(-1), P.rho_max, "whole image")
+
+
+def test_fully_truncated_patch_costs_rho_max_exactly(tiny):
+    P = tiny
+    got = _unary(P, [(0, 0, 64, 48), (10, 10, 25, 25)], [[0, 0, 1e4], [0.0, 0.0, -500.0]])
+    rho_f32 = np.float32((1 - 0.9) * 10 + 0.9 * 2)
+    assert np.all(got[0] == rho_f32) and np.all(got[1] == rho_f32)
+    # wherever the oracle's phi is rho_max up to FP64 rounding, the device value is exactly rho_max
+    rng = np.random.default_rng(3)
+    labels = random_labels(rng, 1, 30, 16.0, max_slope=2.0)[0]
+    rects = [(0, 0, 64, 48)] * len(labels)
+    got = _unary(P, rects, labels)
+    n_plateau = 0
+    for lab, g in zip(labels, got):
+        ref = P.ora.unary_region((0, 0, 64, 48), lab).reshape(-1)
+        flat = np.abs(ref - P.rho_max) < 1e-12
+        n_plateau += flat.sum()
+        assert np.all(g[flat] == rho_f32)
+    assert n_plateau > 100
+
+
+def test_empty_and_outside_items_are_noops(tiny):
+    P = tiny
+    out = torch.full((10,), 7.0, device="cuda")
+    rects = np.array([(5, 5, 5, 9), (70, 0, 80, 5), (-9, -9, -1, -1)], np.int32)
+    L.lexp_unary_cost(P.ctx, rects, np.zeros((3, 3), np.float32), np.zeros(3, np.int64), out)
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0)
+    L.lexp_unary_cost(P.ctx, np.zeros((0, 4), np.int32), np.zeros((0, 3), np.float32), np.zeros(0, np.int64), out)
+
+
+def test_invalid_arguments_raise(tiny):
+    P = tiny
+    out = torch.zeros(300, device="cuda")
+    with pytest.raises(L.LexpError):
+        L.lexp_unary_cost(P.ctx, [(0, 0, 4, 4)], [[np.nan, 0, 0]], [0], out)
+    with pytest.raises(L.LexpError):
+        L.lexp_unary_cost(P.ctx, [(0, 0, 4, 4)], [[0, 0, 0]], [-1], out)
+    with pytest.raises(ValueError):
+        L.lexp_unary_cost(P.ctx, [(0, 0, 40, 40)], [[0, 0, 0]], [0], out)  # output too small
+    bad = dict(P.p, gf_radius=0)
+    with pytest.raises(L.LexpError):
+        L.lexp_create(bad, _cuda(P.left), _cuda(P.right))
+
+
+@pytest.mark.parametrize("r", [1, 2, 5, 9])
+def test_unary_small_image_windows_larger_than_image(r):
+    rng = np.random.default_rng(r)
+    h, w = 5, 7
+    p = base_params(w, h, r)
+    P = Pair(params=p, left=texture(rng, h, w), right=texture(rng, h, w))
+    labs = [[0, 0, 1.5], [0.2, -0.1, 2.0], [0, 0, 0]]
+    got = _unary(P, [(0, 0, w, h), (2, 1, 4, 4), (6, 4, 7, 5)], labs)
+    for rc, lab, g in zip([(0, 0, w, h), (2, 1, 4, 4), (6, 4, 7, 5)], labs, got):
+        assert_cost_close(g, P.ora.unary_region(rc, lab).reshape(-1), P.rho_max, f"r={r} {rc}")
+
+
+def test_guided_coeffs(lowres):
+    P = lowres
+    rng = np.random.default_rng(9)
+    rects = [(100, 100, 115, 115), (0, 0, 45, 45), (400, 300, 475, 375), (10, 200, 90, 230)]
+    labels = [P.gt[107, 107], P.gt[20, 20], P.gt[340, 430], random_labels(rng, 1, 1, 60.0)[0, 0]]
+    sizes = []
+    for u0, v0, u1, v1 in rects:
+        sizes.append((min(u1 + P.r, P.W) - max(u0 - P.r, 0)) * (min(v1 + P.r, P.H) - max(v0 - P.r, 0)))
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    out = torch.full((int(np.sum(sizes)) * 4,), float("nan"), device="cuda")
+    L.lexp_guided_coeffs(P.ctx, rects, labels, offs, out)
+    out = out.cpu().numpy().reshape(-1, 4)
+    for rc, lab, o, s in zip(rects, labels, offs, sizes):
+        ref = P.ora.coeffs_region(rc, lab).reshape(-1, 4)
+        got = out[o:o + s]
+        scale = np.maximum(np.abs(ref), 1.0)
+        assert np.all(np.abs(got - ref) <= 2e-3 * scale), np.abs(got - ref).max()
+
+
+def test_pixel_costs_tiny_all_pixels(tiny):
+    P = tiny
+    lab = P.ora.init_labels(21)
+    out = torch.zeros((P.H, P.W), device="cuda")
+    L.lexp_pixel_costs(P.ctx, _cuda(_label4(lab)), out)
+    assert_cost_close(out.cpu().numpy(), P.ora.pixel_costs(lab), P.rho_max, "pixel costs")
+
+
+def test_pixel_costs_lowres_sampled(lowres):
+    P = lowres
+    lab = P.ora.init_labels(4)
+    lab[100:200, 100:300] = P.gt[100:200, 100:300]
+    out = torch.zeros((P.H, P.W), device="cuda")
+    L.lexp_pixel_costs(P.ctx, _cuda(_label4(lab)), out)
+    rng = np.random.default_rng(1)
+    mask = np.zeros((P.H, P.W), np.uint8)
+    mask.reshape(-1)[rng.choice(P.H * P.W, 600, replace=False)] = 1
+    mask[0, :] = 1
+    mask[:, -1] = 1
+    ref = P.ora.pixel_costs(lab, mask)
+    m = mask.astype(bool)
+    assert_cost_close(out.cpu().numpy()[m], ref[m], P.rho_max, "sampled pixel costs")
+
+
+def test_pairwise_device_path(tiny):
+    P = tiny
+    rng = np.random.default_rng(2)
+    for _ in range(300):
+        p = (int(rng.integers(1, P.W - 1)), int(rng.integers(0, P.H - 1)))
+        d = [(1, 0), (0, 1), (1, 1), (-1, 1)][rng.integers(4)]
+        q = (p[0] + d[0], p[1] + d[1])
+        fp = rng.uniform([-0.5, -0.5, 0], [0.5, 0.5, 16]).astype(np.float32)
+        fq = fp.copy() if rng.random() < 0.2 else rng.uniform([-0.5, -0.5, 0], [0.5, 0.5, 16]).astype(np.float32)
+        a = L.lexp_pairwise(P.ctx, p, q, fp, fq)
+        b = P.ora.pairwise(p, q, fp, fq)
+        assert a == pytest.approx(b, rel=1e-15, abs=0)
+        assert L.lexp_pairwise(P.ctx, q, p, fq, fp) == a
+
+
+def test_energy_matches_oracle(tiny):
+    P = tiny
+    lab = P.ora.init_labels(8)
+    lab[10:30, 10:40] = P.gt[10:30, 10:40]
+    costs = np.random.default_rng(0).uniform(0, 3, (P.H, P.W)).astype(np.float32)
+    t, u, pw = L.lexp_energy(P.ctx, _cuda(_label4(lab)), _cuda(costs))
+    e, eu, ep = P.ora.energy(lab, costs.astype(np.float64))
+    assert u == pytest.approx(eu, rel=1e-12) and pw == pytest.approx(ep, rel=1e-12)
+    assert t == pytest.approx(e, rel=1e-12)
+
+
+def _gpu_state(P, seed):
+    lab = torch.zeros((P.H, P.W, 4), device="cuda")
+    L.lexp_init_labels(P.ctx, seed, lab)
+    cost = torch.zeros((P.H, P.W), device="cuda")
+    L.lexp_pixel_costs(P.ctx, lab, cost)
+    torch.cuda.synchronize()
+    return lab, cost
+
+
+def test_graph_terms_pairwise_part_exact(tiny):
+    P = tiny
+    lab, cost = _gpu_state(P, 13)
+    lab3 = lab.cpu().numpy()[..., :3]
+    assert np.array_equal(lab3, P.ora.init_labels(13))
+    ocost = P.ora.pixel_costs(lab3)
+    rects = [(0, 0, 10, 10), (15, 0, 30, 10), (35, 20, 50, 35), (0, 38, 64, 48)]
+    rng = np.random.default_rng(4)
+    alphas = np.array([lab3[3, 3], P.gt[5, 20], P.gt[25, 40], lab3[40, 30]], np.float32)
+    alphas[1] = rng.uniform([-0.2, -0.2, 2], [0.2, 0.2, 14])
+    sizes = [(u1 - u0) * (v1 - v0) for u0, v0, u1, v1 in rects]
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    phi = torch.zeros(int(np.sum(sizes)), device="cuda")
+    L.lexp_unary_cost(P.ctx, rects, alphas, offs, phi)
+    terms = torch.zeros(int(np.sum(sizes)) * 5, dtype=torch.int32, device="cuda")
+    L.lexp_graph_terms(P.ctx, rects, alphas, phi, offs, lab, cost, terms)
+    terms = terms.cpu().numpy().reshape(-1, 5)
+    for rc, a, o, s in zip(rects, alphas, offs, sizes):
+        phi_o = P.ora.unary_region(rc, a)
+        U, w4 = P.ora.expand_problem(lab3, ocost, phi_o, rc, a)
+        t = terms[o:o + s]
+        assert np.array_equal(t[:, 1:], w4.reshape(-1, 4)), "pairwise weights differ"
+        # unary part: both sides round phi differences of < 1e-4 * 2.8 each
+        assert np.all(np.abs(t[:, 0] - U.reshape(-1)) <= 2 * 2.8e-4 * 2 ** 20 + 2)
+
+
+def _margin(P, lab3, cost, rect, alpha, x_gpu, x_ora):
+    """FP64 energy difference between the two binary labellings."""
+    phi = P.ora.unary_region(rect, alpha)
+    U, w4 = P.ora.expand_problem(lab3, cost, phi, rect, alpha)
+    return abs(P.ora.binary_energy(U, w4, x_gpu) - P.ora.binary_energy(U, w4, x_ora)) * 2.0 ** -20
+
+
+def test_expansion_steps_match_oracle_in_lockstep(tiny):
+    """Both sides start from the same labels and apply the same sequence of
+    group steps (candidates drawn by the oracle's proposer from its state);
+    labels are compared after every step.  A differing pixel is accepted only
+    as a near tie of the FP64 binary energy."""
+    P = tiny
+    seed = 0
+    lab, cost = _gpu_state(P, seed)
+    olab = P.ora.init_labels(seed)
+    ocost = P.ora.pixel_costs(olab)
+    cell, kp, kr = 5, 1, 3
+    nci, ncj = -(-P.W // cell), -(-P.H // cell)
+    near_ties = 0
+    for k in range(16):
+        cells = [(i, j) for j in range(k // 4, ncj, 4) for i in range(k % 4, nci, 4)]
+        rects = [((i - 1) * cell, (j - 1) * cell, (i + 2) * cell, (j + 2) * cell) for i, j in cells]
+        for step in range(kp + kr):
+            alphas = np.array([P.ora.propose(olab, seed, 0, 0, cell, i, j, step, kp, 8.0, 1.0)
+                               for i, j in cells], np.float32)
+            got = _unary(P, rects, alphas)
+            offs = np.concatenate([[0], np.cumsum([len(g) for g in got])[:-1]]).astype(np.int64)
+            phi = _cuda(np.concatenate(got).astype(np.float32))
+            before = olab.copy()
+            for rc, a in zip(rects, alphas):
+                P.ora.expand(olab, ocost, rc, a)
+            L.lexp_expand_region(P.ctx, rects, alphas, phi, offs, lab, cost)
+            g3 = lab.cpu().numpy()[..., :3]
+            diff = np.any(g3 != olab, axis=-1)
+            if diff.any():
+                for rc, a in zip(rects, alphas):
+                    u0, v0, u1, v1 = max(rc[0], 0), max(rc[1], 0), min(rc[2], P.W), min(rc[3], P.H)
+                    if not diff[v0:v1, u0:u1].any():
+                        continue
+                    xg = np.all(g3[v0:v1, u0:u1] == a, axis=-1) & np.any(before[v0:v1, u0:u1] != a, axis=-1)
+                    xo = np.all(olab[v0:v1, u0:u1] == a, axis=-1) & np.any(before[v0:v1, u0:u1] != a, axis=-1)
+                    m = _margin(P, before, P.ora.pixel_costs(before), rc, a, xg.astype(np.uint8),
+                                xo.astype(np.uint8))
+                    assert m < 1e-3, f"group {k} step {step} rect {rc}: margin {m}"
+                    near_ties += 1
+                # continue from the oracle's state on both sides
+                lab = _cuda(_label4(olab))
+                cost = torch.zeros((P.H, P.W), device="cuda")
+                L.lexp_pixel_costs(P.ctx, lab, cost)
+    assert near_ties <= 2
+
+
+def test_expand_rejects_touching_regions_and_leaves_state(tiny):
+    P = tiny
+    lab, cost = _gpu_state(P, 1)
+    before = lab.clone()
+    rects = [(0, 0, 10, 10), (10, 10, 20, 20)]  # diagonal contact
+    phi = torch.zeros(200, device="cuda")
+    with pytest.raises(L.LexpError):
+        L.lexp_expand_region(P.ctx, rects, [[0, 0, 1]] * 2, phi, [0, 100], lab, cost)
+    assert torch.equal(lab, before)
+
+
+def test_optimize_tiny_bit_identical_to_oracle(tiny):
+    P = tiny
+    lab = torch.zeros((P.H, P.W, 4), device="cuda")
+    cost = torch.zeros((P.H, P.W), device="cuda")
+    e, t = L.lexp_optimize(P.ctx, [(5, 1, 3)], 2, 0, lab, cost)
+    olab, ocost, oe, _ = P.ora.optimize(0, [(5, 1, 3)], 2)
+    g3 = lab.cpu().numpy()[..., :3]
+    assert np.array_equal(g3.view(np.uint32), olab.view(np.uint32)), \
+        f"{np.any(g3 != olab, axis=-1).sum()} pixels differ"
+    assert np.allclose(e, oe, rtol=1e-5)
+    assert_cost_close(cost.cpu().numpy(), ocost, P.rho_max, "final costs")
+    # determinism
+    lab2 = torch.zeros_like(lab)
+    cost2 = torch.zeros_like(cost)
+    L.lexp_optimize(P.ctx, [(5, 1, 3)], 2, 0, lab2, cost2)
+    assert torch.equal(lab, lab2) and torch.equal(cost, cost2)

@@ -1,0 +1,154 @@
+"""Host-side parts of liblexp.so, checked against the oracle on the CPU (no
+device calls): exported symbols, the Boykov-Kolmogorov max-flow, the
+counter-based random numbers, random initialisation and proposals."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+import paper_1603_08328_amd.lexp as L
+from _util import base_params, texture
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    src = open(os.path.join(ROOT, "include", "lexp.h")).read()
+    return sorted(set(re.findall(r"^(?:lexp_status|const char\*|uint64_t)\s+(lexp_\w+)\(", src, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load_library()
+    syms = _header_symbols()
+    assert len(syms) >= 19
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(L._SIGS), set(syms) ^ set(L._SIGS)
+
+
+def _oracle(rng, w=12, h=10, **kw):
+    return Oracle(base_params(w, h, **kw), texture(rng, h, w), texture(rng, h, w))
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (3, 5), (1, 1), (1, 9), (6, 2), (5, 5)])
+@pytest.mark.parametrize("kind", ["generic", "ties", "sparse"])
+@pytest.mark.parametrize("nb", [8, 4])
+def test_bk_equals_exhaustive_minimal_set(rng, shape, kind, nb):
+    o = _oracle(rng, neighbours=nb)
+    h, w = shape
+    for _ in range(30):
+        if kind == "generic":
+            U = rng.integers(-60, 61, (h, w))
+            w4 = rng.integers(0, 41, (h, w, 4))
+        elif kind == "ties":
+            U = rng.integers(-2, 3, (h, w))
+            w4 = rng.integers(0, 3, (h, w, 4))
+        else:
+            U = rng.integers(-5, 6, (h, w)) * (rng.random((h, w)) < 0.3)
+            w4 = rng.integers(0, 9, (h, w, 4)) * (rng.random((h, w, 4)) < 0.5)
+        U = U.astype(np.int64)
+        w4 = w4.astype(np.int64)
+        if h * w <= 20:
+            xb, _ = o.solve_bruteforce(U, w4)
+        else:
+            xb = o.solve_maxflow(U, w4)
+        xk = L.lexp_solve_binary(U, w4, nb)
+        assert np.array_equal(xb, xk)
+
+
+@pytest.mark.parametrize("shape", [(15, 15), (45, 45), (20, 75)])
+def test_bk_equals_dinic_on_region_sized_grids(rng, shape):
+    o = _oracle(rng)
+    h, w = shape
+    for scale in (1, 1000, 2 ** 20):
+        U = (rng.normal(0, 1, (h, w)) * scale).astype(np.int64)
+        w4 = (np.abs(rng.normal(0, 0.7, (h, w, 4))) * scale).astype(np.int64)
+        w4[rng.random((h, w, 4)) < 0.2] = 0
+        xd = o.solve_maxflow(U, w4)
+        xk = L.lexp_solve_binary(U, w4)
+        assert np.array_equal(xd, xk)
+        assert o.binary_energy(U, w4, xk) == o.binary_energy(U, w4, xd)
+
+
+def test_bk_rejects_negative_weights():
+    U = np.zeros((2, 2), np.int64)
+    w4 = np.zeros((2, 2, 4), np.int64)
+    w4[0, 0, 0] = -1
+    with pytest.raises(L.LexpError):
+        L.lexp_solve_binary(U, w4)
+
+
+def test_rng_key_chain_matches_oracle(tiny_oracle, rng):
+    for _ in range(200):
+        seed = int(rng.integers(0, 2 ** 63))
+        fields = [int(x) for x in rng.integers(0, 2 ** 31, int(rng.integers(0, 8)))]
+        assert L.lexp_rng_key(seed, fields) == tiny_oracle.rng_key(seed, fields)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 12345, 2 ** 61 + 7])
+def test_init_labels_bitwise_equal_to_oracle(tiny_oracle, seed):
+    a = L.lexp_init_labels_host(64, 48, 16.0, seed)
+    b = tiny_oracle.init_labels(seed)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_proposals_bitwise_equal_to_oracle(tiny_oracle):
+    o = tiny_oracle
+    rng = np.random.default_rng(5)
+    lab = o.init_labels(3)
+    n = 0
+    for it in range(3):
+        for level, cell in enumerate((5, 15, 25)):
+            nci, ncj = -(-64 // cell), -(-48 // cell)
+            for _ in range(20):
+                ci, cj = int(rng.integers(0, nci)), int(rng.integers(0, ncj))
+                for step in range(8):
+                    kp = 1 if level == 0 else 2
+                    args = (lab, 77, it, level, cell, ci, cj, step, kp, 8.0 / 2 ** it, 1.0 / 2 ** it)
+                    a = L.lexp_propose(*args)
+                    b = o.propose(*args)
+                    assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (args[2:], a, b)
+                    n += 1
+    assert n == 3 * 3 * 20 * 8
+
+
+def test_fused_kernel_row_pipeline_fits_its_rings():
+    """Replays the fused cost kernel's row pipeline (rows produced, window
+    rows emitted, output rows) on the CPU for many tile shapes, checking that
+    the ring buffers never have to hold more than 2r+1+kChunk rows and that
+    the loop always ends."""
+    CH = 4
+    for H in (1, 2, 7, 48, 120):
+        for r in (1, 2, 5, 20):
+            ring = 2 * r + 1 + CH
+            for tv0 in range(0, H, max(1, H // 7)):
+                for th in (1, 3, 16, 128):
+                    tv1 = min(tv0 + th, H)
+                    yp0, yp1 = max(tv0 - r, 0), min(tv1 + r, H)
+                    ym0, ym1 = max(tv0 - 2 * r, 0), min(tv1 + 2 * r, H)
+                    produced, kv, lo_cur, pv, lo2_cur = ym0, yp0, ym0, tv0, yp0
+                    iters = 0
+                    while pv < tv1:
+                        iters += 1
+                        assert iters < 10 * (ym1 - ym0 + 10)
+                        produced += min(CH, ym1 - produced)
+                        assert produced - lo_cur <= ring           # live rows of ring1
+                        kv0 = kv
+                        n = 0
+                        while n < CH and kv < yp1:
+                            hi = min(kv + r, H - 1)
+                            if hi >= produced:
+                                break
+                            lo_cur = max(kv - r, 0)
+                            kv += 1
+                            n += 1
+                        assert kv - lo2_cur <= ring                # live rows of ring3
+                        while pv < tv1:
+                            hi2 = min(pv + r, H - 1)
+                            if hi2 >= kv:
+                                break
+                            lo2_cur = max(pv - r, 0)
+                            pv += 1
+                        assert kv0 <= kv
