@@ -157,20 +157,33 @@ double item_alg_bytes(const lexp_ctx* c, const Item& it) {
 
 int max_tile_width(int r, size_t budget) {
   const int ring = 2 * r + 1 + lexp::kChunk;
-  for (int tw = 256 - 2 * r; tw >= 1; --tw)
+  int tw = std::min({lexp::kMaxTW, lexp::kMaxWP - 2 * r, lexp::kMaxWM - 4 * r});
+  for (; tw >= 1; --tw)
     if (lexp::unary_lds_bytes(ring, tw + 2 * r, tw, std::max(tw + 4 * r, tw + 2 * r)) <= budget) return tw;
   return 0;
 }
 
-// Splits items into column strips (LDS-bounded width) and row strips.
+// Splits items into column strips (width bounded by LDS and the kernel's
+// register layout) and row strips.  When a launch has fewer column strips
+// than two per CU, taller items are also cut into row strips (of at least
+// kMinStripRows rows) so the launch fills the device; every strip recomputes
+// its own vertical margin.
+constexpr int kFillTiles = 512;
+constexpr int kMinStripRows = 16;
+
 void plan_tiles(const lexp_ctx* c, const Item* items, int n, std::vector<Tile>& tiles, TileCaps& caps) {
   tiles.clear();
   caps = TileCaps{};
+  int64_t col_tiles = 0;
+  for (int i = 0; i < n; ++i)
+    if (items[i].rw > 0 && items[i].rh > 0) col_tiles += (items[i].rw + c->tw_lim - 1) / c->tw_lim;
+  const int fill = col_tiles > 0 ? (int)std::max<int64_t>(1, kFillTiles / col_tiles) : 1;
   for (int i = 0; i < n; ++i) {
     const Item& it = items[i];
     if (it.rw <= 0 || it.rh <= 0) continue;
     const int ncs = (it.rw + c->tw_lim - 1) / c->tw_lim;
-    const int nrs = (it.rh + kMaxTileRows - 1) / kMaxTileRows;
+    const int nrs = std::max((it.rh + kMaxTileRows - 1) / kMaxTileRows,
+                             std::min((it.rh + kMinStripRows - 1) / kMinStripRows, fill));
     for (int rs = 0; rs < nrs; ++rs) {
       const int tv0 = it.rv0 + (int)((int64_t)it.rh * rs / nrs);
       const int tv1 = it.rv0 + (int)((int64_t)it.rh * (rs + 1) / nrs);
@@ -224,7 +237,7 @@ lexp_status launch_unary(lexp_ctx* c, const Item* d_items, const Tile* d_tiles, 
   if (n_tiles <= 0) return LEXP_OK;
   const int ring = 2 * c->r + 1 + lexp::kChunk;
   const size_t lds = lexp::unary_lds_bytes(ring, caps.wp, caps.tw, caps.ws);
-  if (lds > c->lds_limit || caps.wp > 256 || caps.tw > 256)
+  if (lds > c->lds_limit || caps.wp > lexp::kMaxWP || caps.tw > lexp::kMaxTW || caps.ws > lexp::kMaxWM)
     return fail(LEXP_EINVAL, "tile exceeds kernel limits (lds %zu > %zu or width)", lds, c->lds_limit);
   const int grid = ((n_tiles + 7) / 8) * 8;
   // timing covers the region-cost launches (MODE 0), the hot loop of the method

@@ -39,10 +39,19 @@ struct Tile {
 };
 
 // LDS bytes of one fused-cost workgroup for the given capacities.
+// Rings of 2r+1+kChunk rows (R+ and R widths), the coefficient rows, one scan
+// row per wave, and double-buffered vertical-sum carries; 4+1 floats each.
 inline size_t unary_lds_bytes(int ring, int wp_cap, int tw_cap, int ws_cap) {
-  const size_t n = (size_t)ring * wp_cap + (size_t)kChunk * wp_cap + (size_t)ring * tw_cap + 4 * (size_t)ws_cap;
+  const size_t n = (size_t)ring * wp_cap + (size_t)kChunk * wp_cap + (size_t)ring * tw_cap + 4 * (size_t)ws_cap +
+                   2 * (size_t)wp_cap + 2 * (size_t)tw_cap;
   return n * (sizeof(float) * 4 + sizeof(float));
 }
+
+// Widths the fused kernel's register layout supports: an M row in three
+// 64-lane segments, R+ and R rows in two.
+constexpr int kMaxWM = 192;
+constexpr int kMaxWP = 128;
+constexpr int kMaxTW = 128;
 
 template <int MODE>
 __global__ void k_unary(DevParams P, const float4* left4, const float4* right4, const float* guide,

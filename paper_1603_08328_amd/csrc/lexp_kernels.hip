@@ -108,14 +108,17 @@ __global__ void k_weights(const float* __restrict__ left, double* __restrict__ w
 
 // ---------------------------------------------------------------------------
 // Fused unary cost.  One workgroup (4 wave64) per tile: a sub-rectangle of
-// one item's region.  Rows stream top to bottom through four stages per
-// chunk of kChunk rows:
-//   A  raw cost rho' = rho - rho_max and rho' * I over one row of M per wave,
-//      wave prefix scan, horizontal window sums at the R+ columns -> ring1
-//   C  per R+ column: running vertical sums -> means over W'_k ->
+// one item's region.  Rows stream top to bottom; each pipeline step handles
+// up to kChunk rows per stage, one row per wave:
+//   A  raw cost rho' = rho - rho_max and rho' * I over one row of M,
+//      wave prefix scan (DPP), horizontal window sums at R+ columns -> ring1
+//   C  one R+ row per wave: vertical window sum (carried sum plus the rows
+//      that entered minus those that left) -> means over W'_k ->
 //      a_k = (Sigma_k + eU)^-1 (mean(I rho) - mu mean(rho)), b_k -> coef rows
-//   E  per coef row (one per wave): prefix scan, window sums at R columns -> ring3
-//   G  per R column: running vertical sums -> phi = abar^T I_p + bbar + rho_max
+//   E  one coef row per wave: prefix scan, window sums at R columns -> ring3
+//   G  one R row per wave: vertical window sum -> phi = abar^T I_p + bbar + rho_max
+// Global operands of a step (image taps, guide statistics, I_p) are loaded one
+// step ahead; barriers wait on LDS traffic only, so those loads stay in flight.
 // A fifth channel counts samples with rho' != 0 (an exact integer in FP32):
 // where a window holds none, the sums are zero exactly, so a fully truncated
 // or out-of-view patch costs exactly rho_max under any label.
@@ -123,14 +126,64 @@ __global__ void k_weights(const float* __restrict__ left, double* __restrict__ w
 __device__ inline float4 f4add(float4 a, float4 b) { return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
 __device__ inline float4 f4sub(float4 a, float4 b) { return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w); }
 
-__device__ inline void wave_scan(float4& v, float& c, int lane) {
+// Workgroup barrier that orders LDS accesses only: outstanding global loads
+// are not waited for, so prefetches stay in flight across it.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+template <int CTRL, int ROWMASK>
+__device__ inline float dpp_add(float v) {
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xf, false));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave: shifts by 1, 2, 4, 8
+// inside each row of 16 lanes, then row broadcasts of lane 15 and lane 31.
+__device__ inline float wave_scan1(float v) {
+  v = dpp_add<0x111, 0xf>(v);
+  v = dpp_add<0x112, 0xf>(v);
+  v = dpp_add<0x114, 0xf>(v);
+  v = dpp_add<0x118, 0xf>(v);
+  v = dpp_add<0x142, 0xa>(v);
+  v = dpp_add<0x143, 0xc>(v);
+  return v;
+}
+
+__device__ inline float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
+
+constexpr int kSegA = 3;  // 64-column segments of an M row (wM <= 192)
+constexpr int kColC = 2;  // R+ columns per lane (wP <= 128)
+constexpr int kColG = 2;  // R columns per lane (tw <= 128)
+
+struct RowTaps {           // prefetched operands of one M row, per lane
+  float4 L[kSegA], R0[kSegA], R1[kSegA];
+  float t[kSegA];
+  bool ok[kSegA];
+};
+
+__device__ inline void load_row(RowTaps& tp, int y, bool active, int xm0, int wM, int W, float la, float lb, float lc,
+                                int lane, const float4* __restrict__ left4, const float4* __restrict__ right4) {
+  const float fW1 = (float)(W - 1);
+  const float vf = (float)y;
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const float tx = __shfl_up(v.x, o, 64), ty = __shfl_up(v.y, o, 64);
-    const float tz = __shfl_up(v.z, o, 64), tw = __shfl_up(v.w, o, 64);
-    const float tc = __shfl_up(c, o, 64);
-    if (lane >= o) {
-      v.x += tx; v.y += ty; v.z += tz; v.w += tw; c += tc;
+  for (int s = 0; s < kSegA; ++s) {
+    const int xi = s * 64 + lane;
+    tp.ok[s] = false;
+    if (active && xi < wM) {
+      const int x = xm0 + xi;
+      const float uf = (float)x;
+      const float d = fmaf(la, uf, fmaf(lb, vf, lc));
+      const float xs = uf - d;
+      if (xs >= 0.f && xs <= fW1) {
+        const float xf = floorf(xs);
+        int i0 = (int)xf;
+        float t = xs - xf;
+        int i1 = i0 + 1;
+        if (i0 >= W - 1) { i0 = W - 1; i1 = W - 1; t = 0.f; }
+        tp.R0[s] = right4[(size_t)y * W + i0];
+        tp.R1[s] = right4[(size_t)y * W + i1];
+        tp.L[s] = left4[(size_t)y * W + x];
+        tp.t[s] = t;
+        tp.ok[s] = true;
+      }
     }
   }
 }
@@ -183,83 +236,106 @@ __global__ __launch_bounds__(256) void k_unary(DevParams P, const float4* __rest
   const int own_u0 = (flags & kFirstCol) ? xp0 : tu0, own_u1 = (flags & kLastCol) ? xp1 : tu1;
   const int own_v0 = (flags & kFirstRow) ? yp0 : tv0, own_v1 = (flags & kLastRow) ? yp1 : tv1;
 
-  // shared memory carve-up
+  // shared memory carve-up: float4 arrays, then the count arrays in the same order
   float4* ring1v = smem4;
   float4* coefv = ring1v + (size_t)ring * wp_cap;
   float4* ring3v = coefv + (size_t)kChunk * wp_cap;
   float4* scanv = ring3v + (size_t)ring * tw_cap;
-  float* ring1c = reinterpret_cast<float*>(scanv + (size_t)4 * ws_cap);
+  float4* car1v = scanv + (size_t)4 * ws_cap;
+  float4* car2v = car1v + (size_t)2 * wp_cap;
+  float* ring1c = reinterpret_cast<float*>(car2v + (size_t)2 * tw_cap);
   float* coefc = ring1c + (size_t)ring * wp_cap;
   float* ring3c = coefc + (size_t)kChunk * wp_cap;
   float* scanc = ring3c + (size_t)ring * tw_cap;
+  float* car1c = scanc + (size_t)4 * ws_cap;
+  float* car2c = car1c + (size_t)2 * wp_cap;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const float inv255 = 1.0f / 255.0f;
-  const float fW1 = (float)(W - 1);
+  const size_t hw = (size_t)W * H;
+  float4* sv = scanv + (size_t)wave * ws_cap;
+  float* sc = scanc + (size_t)wave * ws_cap;
+
+  for (int i = tid; i < wp_cap; i += 256) { car1v[i] = make_float4(0.f, 0.f, 0.f, 0.f); car1c[i] = 0.f; }
+  for (int i = tid; i < tw_cap; i += 256) { car2v[i] = make_float4(0.f, 0.f, 0.f, 0.f); car2c[i] = 0.f; }
 
   int produced = ym0;                 // next M row to produce
   int kv = yp0;                       // next R+ row to emit
-  int hi_cur = ym0 - 1, lo_cur = ym0; // rows summed in V1
+  int hi_c = ym0 - 1, lo_c = ym0;     // M rows in the carried vertical sum
   int pv = tv0;                       // next R row to output
-  int hi2_cur = yp0 - 1, lo2_cur = yp0;
-  float4 V1 = make_float4(0.f, 0.f, 0.f, 0.f);
-  float V1c = 0.f;
-  float4 V2 = make_float4(0.f, 0.f, 0.f, 0.f);
-  float V2c = 0.f;
+  int hi2_c = yp0 - 1, lo2_c = yp0;   // R+ rows in the carried vertical sum
+  int par1 = 0, par2 = 0;             // carry buffer parity
+
+  // prefetch the first step's operands
+  RowTaps taps;
+  load_row(taps, produced + wave, produced + wave < ym1, xm0, wM, W, la, lb, lc, lane, left4, right4);
+  float gs[kColC][9];
+  auto load_guide = [&](int k) {
+#pragma unroll
+    for (int j = 0; j < kColC; ++j) {
+      const int xi = j * 64 + lane;
+      if (k < yp1 && xi < wP) {
+        const size_t gi = (size_t)k * W + xp0 + xi;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) gs[j][q] = guide[q * hw + gi];
+      }
+    }
+  };
+  load_guide(kv + wave);
+  float4 lp[kColG];
+  auto load_left = [&](int p) {
+#pragma unroll
+    for (int j = 0; j < kColG; ++j) {
+      const int xi = j * 64 + lane;
+      if (p < tv1 && xi < tw) lp[j] = left4[(size_t)p * W + tu0 + xi];
+    }
+  };
+  if (MODE != 1) load_left(pv + wave);
+  lds_barrier();
 
   for (;;) {
     if (MODE == 1 ? (kv >= own_v1) : (pv >= tv1)) break;
     // ---- A: raw cost rows -> horizontal window sums ----------------------
     const int nA = min(kChunk, ym1 - produced);
-    float4* sv = scanv + (size_t)wave * ws_cap;
-    float* sc = scanc + (size_t)wave * ws_cap;
     if (wave < nA) {
       const int y = produced + wave;
-      const float vf = (float)y;
       float4 carry = make_float4(0.f, 0.f, 0.f, 0.f);
       float carryc = 0.f;
-      for (int s0 = 0; s0 < wM; s0 += 64) {
-        const int xi = s0 + lane;
+#pragma unroll
+      for (int s = 0; s < kSegA; ++s) {
+        if (s * 64 >= wM) break;
+        const int xi = s * 64 + lane;
         float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
         float nz = 0.f;
-        if (xi < wM) {
-          const int x = xm0 + xi;
-          const float uf = (float)x;
-          const float d = fmaf(la, uf, fmaf(lb, vf, lc));
-          const float xs = uf - d;
-          if (xs >= 0.f && xs <= fW1) {
-            const float xf = floorf(xs);
-            int i0 = (int)xf;
-            float t = xs - xf;
-            int i1 = i0 + 1;
-            if (i0 >= W - 1) { i0 = W - 1; i1 = W - 1; t = 0.f; }
-            const float4 R0 = right4[(size_t)y * W + i0];
-            const float4 R1 = right4[(size_t)y * W + i1];
-            const float4 L = left4[(size_t)y * W + x];
-            const float col = fabsf(L.x - fmaf(t, R1.x - R0.x, R0.x)) + fabsf(L.y - fmaf(t, R1.y - R0.y, R0.y)) +
-                              fabsf(L.z - fmaf(t, R1.z - R0.z, R0.z));
-            const float gr = fabsf(L.w - fmaf(t, R1.w - R0.w, R0.w));
-            const float rp = P.oma * (fminf(col, P.tc) - P.tc) + P.al * (fminf(gr, P.tg) - P.tg);
-            if (rp != 0.f) {
-              val = make_float4(rp, rp * (L.x * inv255), rp * (L.y * inv255), rp * (L.z * inv255));
-              nz = 1.f;
-            }
+        if (taps.ok[s]) {
+          const float t = taps.t[s];
+          const float4 L = taps.L[s], R0 = taps.R0[s], R1 = taps.R1[s];
+          const float col = fabsf(L.x - fmaf(t, R1.x - R0.x, R0.x)) + fabsf(L.y - fmaf(t, R1.y - R0.y, R0.y)) +
+                            fabsf(L.z - fmaf(t, R1.z - R0.z, R0.z));
+          const float gr = fabsf(L.w - fmaf(t, R1.w - R0.w, R0.w));
+          const float rp = P.oma * (fminf(col, P.tc) - P.tc) + P.al * (fminf(gr, P.tg) - P.tg);
+          if (rp != 0.f) {
+            val = make_float4(rp, rp * (L.x * inv255), rp * (L.y * inv255), rp * (L.z * inv255));
+            nz = 1.f;
           }
         }
-        wave_scan(val, nz, lane);
-        val = f4add(val, carry);
-        nz += carryc;
+        val.x = wave_scan1(val.x) + carry.x;
+        val.y = wave_scan1(val.y) + carry.y;
+        val.z = wave_scan1(val.z) + carry.z;
+        val.w = wave_scan1(val.w) + carry.w;
+        nz = wave_scan1(nz) + carryc;
         if (xi < wM) { sv[xi] = val; sc[xi] = nz; }
-        carry = make_float4(__shfl(val.x, 63, 64), __shfl(val.y, 63, 64), __shfl(val.z, 63, 64),
-                            __shfl(val.w, 63, 64));
-        carryc = __shfl(nz, 63, 64);
+        carry = make_float4(lane63(val.x), lane63(val.y), lane63(val.z), lane63(val.w));
+        carryc = lane63(nz);
       }
+      (void)y;
     }
-    __syncthreads();
+    // next step's image taps (rows produced + nA + wave), in flight from here
+    load_row(taps, produced + nA + wave, produced + nA + wave < ym1, xm0, wM, W, la, lb, lc, lane, left4, right4);
     if (wave < nA) {
-      const int y = produced + wave;
-      const int slot = y % ring;
+      // the scan row is private to this wave: its LDS writes precede these reads
+      const int slot = (produced + wave) % ring;
       for (int s0 = 0; s0 < wP; s0 += 64) {
         const int xi = s0 + lane;
         if (xi < wP) {
@@ -276,63 +352,78 @@ __global__ __launch_bounds__(256) void k_unary(DevParams P, const float4* __rest
       }
     }
     produced += nA;
-    __syncthreads();
+    lds_barrier();
 
     // ---- C: vertical sums over W'_k, linear coefficients -----------------
-    const int kv_start = kv;
     int nC = 0;
-    while (nC < kChunk && kv < yp1) {
-      const int hi_k = kv + r < H - 1 ? kv + r : H - 1;
-      if (hi_k >= produced) break;
-      const int lo_k = kv - r > 0 ? kv - r : 0;
-      if (tid < wP) {
-        for (int y = hi_cur + 1; y <= hi_k; ++y) {
-          V1 = f4add(V1, ring1v[(size_t)(y % ring) * wp_cap + tid]);
-          V1c += ring1c[(size_t)(y % ring) * wp_cap + tid];
+    while (nC < kChunk && kv + nC < yp1) {
+      const int k = kv + nC;
+      if ((k + r < H - 1 ? k + r : H - 1) >= produced) break;
+      ++nC;
+    }
+    if (wave < nC) {
+      const int k = kv + wave;
+      const int hi_k = k + r < H - 1 ? k + r : H - 1;
+      const int lo_k = k - r > 0 ? k - r : 0;
+      const float inv_rows = (float)(hi_k - lo_k + 1);
+#pragma unroll
+      for (int j = 0; j < kColC; ++j) {
+        const int xi = j * 64 + lane;
+        if (xi >= wP) continue;
+        float4 V = car1v[(size_t)par1 * wp_cap + xi];
+        float Vc = car1c[(size_t)par1 * wp_cap + xi];
+        for (int y = hi_c + 1; y <= hi_k; ++y) {
+          V = f4add(V, ring1v[(size_t)(y % ring) * wp_cap + xi]);
+          Vc += ring1c[(size_t)(y % ring) * wp_cap + xi];
         }
-        for (int y = lo_cur; y < lo_k; ++y) {
-          V1 = f4sub(V1, ring1v[(size_t)(y % ring) * wp_cap + tid]);
-          V1c -= ring1c[(size_t)(y % ring) * wp_cap + tid];
+        for (int y = lo_c; y < lo_k; ++y) {
+          V = f4sub(V, ring1v[(size_t)(y % ring) * wp_cap + xi]);
+          Vc -= ring1c[(size_t)(y % ring) * wp_cap + xi];
         }
-        const int x = xp0 + tid;
+        if (wave == nC - 1) {
+          car1v[(size_t)(par1 ^ 1) * wp_cap + xi] = V;
+          car1c[(size_t)(par1 ^ 1) * wp_cap + xi] = Vc;
+        }
+        const int x = xp0 + xi;
         const int cx0 = x - r > 0 ? x - r : 0, cx1 = x + r < W - 1 ? x + r : W - 1;
-        const float nk = (float)((cx1 - cx0 + 1) * (hi_k - lo_k + 1));
-        const float inv_n = 1.0f / nk;
+        const float inv_n = 1.0f / ((float)(cx1 - cx0 + 1) * inv_rows);
         float4 coef = make_float4(0.f, 0.f, 0.f, 0.f);
         float z = 0.f;
-        if (V1c != 0.f) {
-          const size_t hw = (size_t)W * H, gi = (size_t)kv * W + x;
-          const float mu0 = guide[gi], mu1 = guide[hw + gi], mu2 = guide[2 * hw + gi];
-          const float i00 = guide[3 * hw + gi], i01 = guide[4 * hw + gi], i02 = guide[5 * hw + gi];
-          const float i11 = guide[6 * hw + gi], i12 = guide[7 * hw + gi], i22 = guide[8 * hw + gi];
-          const float m0 = V1.x * inv_n;
-          const float c0 = V1.y * inv_n - mu0 * m0;
-          const float c1 = V1.z * inv_n - mu1 * m0;
-          const float c2 = V1.w * inv_n - mu2 * m0;
-          const float a0 = i00 * c0 + i01 * c1 + i02 * c2;
-          const float a1 = i01 * c0 + i11 * c1 + i12 * c2;
-          const float a2 = i02 * c0 + i12 * c1 + i22 * c2;
-          const float b = m0 - (a0 * mu0 + a1 * mu1 + a2 * mu2);
+        if (Vc != 0.f) {
+          const float* g = gs[j];
+          const float m0 = V.x * inv_n;
+          const float c0 = V.y * inv_n - g[0] * m0;
+          const float c1 = V.z * inv_n - g[1] * m0;
+          const float c2 = V.w * inv_n - g[2] * m0;
+          const float a0 = g[3] * c0 + g[4] * c1 + g[5] * c2;
+          const float a1 = g[4] * c0 + g[6] * c1 + g[7] * c2;
+          const float a2 = g[5] * c0 + g[7] * c1 + g[8] * c2;
+          const float b = m0 - (a0 * g[0] + a1 * g[1] + a2 * g[2]);
           coef = make_float4(a0, a1, a2, b);
           z = 1.f;
         }
         if (MODE == 1) {
-          if (x >= own_u0 && x < own_u1 && kv >= own_v0 && kv < own_v1) {
+          if (x >= own_u0 && x < own_u1 && k >= own_v0 && k < own_v1) {
             // coefficients of rho itself: a is unchanged by the shift, b gains rho_max
-            float* o = out + (out_off + (long long)(kv - rv0) * rw + (x - ru0)) * 4;
+            float* o = out + (out_off + (long long)(k - rv0) * rw + (x - ru0)) * 4;
             o[0] = coef.x; o[1] = coef.y; o[2] = coef.z; o[3] = coef.w + P.rho_max;
           }
         } else {
-          coefv[(size_t)nC * wp_cap + tid] = coef;
-          coefc[(size_t)nC * wp_cap + tid] = z;
+          coefv[(size_t)wave * wp_cap + xi] = coef;
+          coefc[(size_t)wave * wp_cap + xi] = z;
         }
       }
-      hi_cur = hi_k;
-      lo_cur = lo_k;
-      ++kv;
-      ++nC;
     }
-    __syncthreads();
+    const int kv_start = kv;
+    if (nC > 0) {
+      const int k = kv + nC - 1;
+      hi_c = k + r < H - 1 ? k + r : H - 1;
+      lo_c = k - r > 0 ? k - r : 0;
+      kv += nC;
+      par1 ^= 1;
+      load_guide(kv + wave);
+    }
+    lds_barrier();
     if (MODE == 1) continue;
 
     // ---- E: horizontal sums of (a, b) at the R columns --------------------
@@ -346,17 +437,15 @@ __global__ __launch_bounds__(256) void k_unary(DevParams P, const float4* __rest
         float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
         float z = 0.f;
         if (xi < wP) { val = cv[xi]; z = cc[xi]; }
-        wave_scan(val, z, lane);
-        val = f4add(val, carry);
-        z += carryc;
+        val.x = wave_scan1(val.x) + carry.x;
+        val.y = wave_scan1(val.y) + carry.y;
+        val.z = wave_scan1(val.z) + carry.z;
+        val.w = wave_scan1(val.w) + carry.w;
+        z = wave_scan1(z) + carryc;
         if (xi < wP) { sv[xi] = val; sc[xi] = z; }
-        carry = make_float4(__shfl(val.x, 63, 64), __shfl(val.y, 63, 64), __shfl(val.z, 63, 64),
-                            __shfl(val.w, 63, 64));
-        carryc = __shfl(z, 63, 64);
+        carry = make_float4(lane63(val.x), lane63(val.y), lane63(val.z), lane63(val.w));
+        carryc = lane63(z);
       }
-    }
-    __syncthreads();
-    if (wave < nC) {
       const int slot = (kv_start + wave) % ring;
       for (int s0 = 0; s0 < tw; s0 += 64) {
         const int xi = s0 + lane;
@@ -373,36 +462,62 @@ __global__ __launch_bounds__(256) void k_unary(DevParams P, const float4* __rest
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
 
     // ---- G: vertical sums over W'(p), output -------------------------------
-    while (pv < tv1) {
-      const int hi2 = pv + r < H - 1 ? pv + r : H - 1;
-      if (hi2 >= kv) break;
-      const int lo2 = pv - r > 0 ? pv - r : 0;
-      if (tid < tw) {
-        for (int y = hi2_cur + 1; y <= hi2; ++y) {
-          V2 = f4add(V2, ring3v[(size_t)(y % ring) * tw_cap + tid]);
-          V2c += ring3c[(size_t)(y % ring) * tw_cap + tid];
+    int nG = 0;
+    while (pv + nG < tv1) {
+      const int p = pv + nG;
+      if ((p + r < H - 1 ? p + r : H - 1) >= kv) break;
+      ++nG;
+    }
+    for (int q0 = 0; q0 < nG; q0 += 4) {
+      const int q = q0 + wave;
+      if (q >= nG) continue;
+      const int p = pv + q;
+      const int hi2 = p + r < H - 1 ? p + r : H - 1;
+      const int lo2 = p - r > 0 ? p - r : 0;
+      const float rows = (float)(hi2 - lo2 + 1);
+#pragma unroll
+      for (int j = 0; j < kColG; ++j) {
+        const int xi = j * 64 + lane;
+        if (xi >= tw) continue;
+        float4 V2 = car2v[(size_t)par2 * tw_cap + xi];
+        float V2c = car2c[(size_t)par2 * tw_cap + xi];
+        for (int y = hi2_c + 1; y <= hi2; ++y) {
+          V2 = f4add(V2, ring3v[(size_t)(y % ring) * tw_cap + xi]);
+          V2c += ring3c[(size_t)(y % ring) * tw_cap + xi];
         }
-        for (int y = lo2_cur; y < lo2; ++y) {
-          V2 = f4sub(V2, ring3v[(size_t)(y % ring) * tw_cap + tid]);
-          V2c -= ring3c[(size_t)(y % ring) * tw_cap + tid];
+        for (int y = lo2_c; y < lo2; ++y) {
+          V2 = f4sub(V2, ring3v[(size_t)(y % ring) * tw_cap + xi]);
+          V2c -= ring3c[(size_t)(y % ring) * tw_cap + xi];
         }
-        const int x = tu0 + tid;
+        if (q == nG - 1) {
+          car2v[(size_t)(par2 ^ 1) * tw_cap + xi] = V2;
+          car2c[(size_t)(par2 ^ 1) * tw_cap + xi] = V2c;
+        }
+        const int x = tu0 + xi;
         const int cx0 = x - r > 0 ? x - r : 0, cx1 = x + r < W - 1 ? x + r : W - 1;
-        const float np = (float)((cx1 - cx0 + 1) * (hi2 - lo2 + 1));
+        const float np = (float)(cx1 - cx0 + 1) * rows;
         float phi = 0.f;
         if (V2c != 0.f) {
-          const float4 L = left4[(size_t)pv * W + x];
+          const float4 L = q0 == 0 ? lp[j] : left4[(size_t)p * W + x];
           phi = (V2.x * (L.x * inv255) + V2.y * (L.y * inv255) + V2.z * (L.z * inv255) + V2.w) / np;
         }
-        out[out_off + (long long)(pv - rv0) * rw + (x - ru0)] = phi + P.rho_max;
+        out[out_off + (long long)(p - rv0) * rw + (x - ru0)] = phi + P.rho_max;
       }
-      hi2_cur = hi2;
-      lo2_cur = lo2;
-      ++pv;
     }
+    if (nG > 0) {
+      const int p = pv + nG - 1;
+      hi2_c = p + r < H - 1 ? p + r : H - 1;
+      lo2_c = p - r > 0 ? p - r : 0;
+      pv += nG;
+      par2 ^= 1;
+      load_left(pv + wave);
+    }
+    // no barrier needed here: the next step's first LDS writes (scan rows,
+    // ring1) do not touch ring3 or the G carries, and E writes ring3 only
+    // after two more barriers
   }
 }
 
