@@ -232,6 +232,7 @@ def main():
         "final_energy": g["final_energy"],
         "energy_trace": [round(x, 3) for x in g["energy"]],
         "kernel_evals_per_s": (g["evals"] / (g["kernel_ms"] / 1e3) / 1e9) if g["kernel_ms"] > 0 else None,
+        "host_threads": len(os.sched_getaffinity(0)), "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
         "host_cut_ms_per_step": g["stats"]["host_cut_ms"],
         "host_wait_ms_per_step": g["stats"]["host_wait_ms"],
     }

@@ -202,8 +202,9 @@ lexp_status lexp_debug_guide(lexp_ctx* ctx, float* left4, float* right4, float* 
 
 /* Exact minimisation of E(x) = sum U_p x_p + sum_d w_d (1 - x_p) x_{p+fwd_d}
  * on a w x h grid by the library's Boykov-Kolmogorov max-flow; returns in x
- * the minimiser with the fewest ones.  U: [w*h], w4: [w*h*4] (w_d >= 0),
- * neighbours 8 or 4, x: [w*h].  Host memory. */
+ * the minimiser with the fewest ones.  U: [w*h], |U_p| <= 2^30; w4: [w*h*4],
+ * 0 <= w_d <= 2^30 (LEXP_EINVAL otherwise); neighbours 8 or 4; x: [w*h].
+ * Host memory. */
 lexp_status lexp_solve_binary(int32_t w, int32_t h, int32_t neighbours, const int64_t* U, const int64_t* w4,
                               uint8_t* x);
 

@@ -8,8 +8,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <sched.h>
 #include <string>
 #include <thread>
 #include <vector>
@@ -125,6 +127,20 @@ struct lexp_ctx {
   std::vector<hipEvent_t> ev_free;
   struct Pending { hipEvent_t a, b; double bytes; };
   std::vector<Pending> ev_pending;
+  // two halves of a group step in flight at once (host cuts one half while
+  // the device evaluates the other)
+  struct PartBuf {
+    DevBuf<Item> d_items;
+    DevBuf<float> d_phi;
+    DevBuf<int> d_terms;
+    DevBuf<uint8_t> d_x;
+    DevBuf<int> d_flag;
+    PinBuf<Item> h_items;
+    PinBuf<int> h_terms;
+    PinBuf<uint8_t> h_x;
+    PinBuf<int> h_flag;
+    hipEvent_t ready = nullptr;
+  } part[2];
 };
 
 namespace {
@@ -408,6 +424,18 @@ lexp_status expand_batch(lexp_ctx* c, int n, int64_t n_px, const float* alpha_co
   return LEXP_OK;
 }
 
+// Host threads for the min-cut pool: OMP_NUM_THREADS when set (the share of
+// cores the job was given), else the CPUs this process may run on.
+int default_threads() {
+  if (const char* e = std::getenv("OMP_NUM_THREADS")) {
+    const int v = std::atoi(e);
+    if (v > 0) return v;
+  }
+  cpu_set_t set;
+  if (sched_getaffinity(0, sizeof(set), &set) == 0) return std::max(1, CPU_COUNT(&set));
+  return (int)std::max(1u, std::thread::hardware_concurrency());
+}
+
 lexp_status energy_impl(lexp_ctx* c, const float* labels, const float* cur_cost, double* total, double* unary,
                         double* pair, hipStream_t s) {
   const int n = c->W * c->H;
@@ -522,7 +550,7 @@ lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const 
   HIP_TRY(hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming));
   HIP_TRY(hipEventRecord(c->staging_done, s));
   int nt = p.host_threads;
-  if (nt == 0) nt = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 64u);
+  if (nt == 0) nt = std::min(default_threads(), 64);
   c->pool.reset(new lexp::ThreadPool(nt));
   for (int i = 0; i < c->pool->size(); ++i) c->solvers.emplace_back(new lexp::BKSolver());
   *out = c.release();
@@ -543,6 +571,11 @@ lexp_status lexp_destroy(lexp_ctx* c) {
   c->d_flag.release(); c->d_partial.release(); c->d_labels_tmp.release();
   c->h_items.release(); c->h_tiles.release(); c->h_terms.release(); c->h_x.release(); c->h_flag.release();
   c->h_partial.release(); c->h_labels4.release();
+  for (auto& b : c->part) {
+    b.d_items.release(); b.d_phi.release(); b.d_terms.release(); b.d_x.release(); b.d_flag.release();
+    b.h_items.release(); b.h_terms.release(); b.h_x.release(); b.h_flag.release();
+    if (b.ready) (void)hipEventDestroy(b.ready);
+  }
   delete c;
   return LEXP_OK;
 }
@@ -693,8 +726,95 @@ lexp_status lexp_init_labels(lexp_ctx* c, uint64_t seed, float* labels, void* hi
   return upload_labels(c, h.data(), labels, (hipStream_t)hip_stream);
 }
 
-lexp_status lexp_optimize(lexp_ctx* c, const lexp_schedule* sch, uint64_t seed, float* labels, float* cur_cost,
-                          double* energy_trace, double* time_trace, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// One half of a group: its cells, clipped regions (compact offsets) and tiles.
+struct Part {
+  std::vector<int> ci, cj;
+  std::vector<Item> items;
+  int64_t n_px = 0;
+  int max_px = 1;
+  size_t tile_off = 0, n_tiles = 0;
+  TileCaps caps;
+  double bytes = 0.0;
+};
+
+struct StepArgs {
+  uint64_t seed;
+  int it, level, cell, kp;
+  double r_d, r_n;
+  const float* mirror;
+};
+
+// Proposals of one step for a part, then its cost kernel, graph terms and the
+// copy of the terms to the host, all queued on the stream.
+lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const Tile* d_tiles, const StepArgs& a,
+                         int step, const float* labels, const float* cur_cost, hipStream_t s) {
+  const int n = (int)P.items.size();
+  c->pool->parallel_for(n, [&](int q, int) {
+    float al[3];
+    lexp::propose(c->W, c->H, a.mirror, 3, a.seed, a.it, a.level, a.cell, P.ci[q], P.cj[q], step, a.kp, a.r_d, a.r_n,
+                  al);
+    P.items[q].a = al[0];
+    P.items[q].b = al[1];
+    P.items[q].c = al[2];
+  });
+  std::copy(P.items.begin(), P.items.end(), B.h_items.p);
+  HIP_TRY(hipMemcpyAsync(B.d_items.p, B.h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
+  lexp_status st = launch_unary<0>(c, B.d_items.p, d_tiles + P.tile_off, (int)P.n_tiles, P.caps, nullptr, B.d_phi.p, s,
+                                   P.bytes, P.n_px, n);
+  if (st) return st;
+  HIP_TRY(hipMemsetAsync(B.d_flag.p, 0, sizeof(int), s));
+  hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, c->dp, B.d_items.p,
+                     (const float4*)labels, cur_cost, B.d_phi.p, c->wts, B.d_terms.p, B.d_flag.p);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(B.h_terms.p, B.d_terms.p, sizeof(int) * 5 * P.n_px, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(B.h_flag.p, B.d_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(B.ready, s));
+  return LEXP_OK;
+}
+
+// Waits for a part's terms, solves its regions on the host pool, updates the
+// host label mirror and queues the label update on the device.
+lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, float* mirror, float* labels, float* cur_cost,
+                        hipStream_t s) {
+  const int n = (int)P.items.size();
+  const auto t0 = std::chrono::steady_clock::now();
+  HIP_TRY(hipEventSynchronize(B.ready));
+  const auto t1 = std::chrono::steady_clock::now();
+  if (B.h_flag.p[0]) return fail(LEXP_EINVAL, "binary-problem term exceeds 2^30 quanta (parameters too large)");
+  const int nf = c->dp.nf;
+  c->pool->parallel_for(n, [&](int i, int worker) {
+    const Item& it = P.items[i];
+    if (it.rw <= 0 || it.rh <= 0) return;
+    const int* t = B.h_terms.p + (size_t)it.aux_off * 5;
+    uint8_t* x = B.h_x.p + it.aux_off;
+    lexp::BKSolver& bk = *c->solvers[worker];
+    bk.load<int32_t>(it.rw, it.rh, nf, t, 5, t + 1, 5);
+    bk.solve(x);
+    for (int q = 0; q < it.rw * it.rh; ++q) {
+      if (!x[q]) continue;
+      float* m = mirror + ((size_t)(it.rv0 + q / it.rw) * c->W + (it.ru0 + q % it.rw)) * 3;
+      m[0] = it.a; m[1] = it.b; m[2] = it.c;
+    }
+  });
+  const auto t2 = std::chrono::steady_clock::now();
+  HIP_TRY(hipMemcpyAsync(B.d_x.p, B.h_x.p, (size_t)P.n_px, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(lexp::k_apply, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, c->W, B.d_items.p, B.d_x.p,
+                     B.d_phi.p, (float4*)labels, cur_cost);
+  HIP_TRY(hipGetLastError());
+  c->stats.expand_calls += 1;
+  c->stats.host_wait_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+  c->stats.host_cut_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
+  return LEXP_OK;
+}
+
+}  // namespace
+
+extern "C" lexp_status lexp_optimize(lexp_ctx* c, const lexp_schedule* sch, uint64_t seed, float* labels,
+                                     float* cur_cost, double* energy_trace, double* time_trace, void* hip_stream) {
   if (!c || !sch || !labels || !cur_cost) return fail(LEXP_EINVAL, "null argument");
   if (sch->n_levels < 1 || sch->n_levels > 4 || sch->iterations < 0) return fail(LEXP_EINVAL, "bad schedule");
   for (int h = 0; h < sch->n_levels; ++h)
@@ -707,46 +827,47 @@ lexp_status lexp_optimize(lexp_ctx* c, const lexp_schedule* sch, uint64_t seed, 
   lexp_status st = wait_staging(c);
   if (st) return st;
 
-  // Per (level, group): cells, clipped regions, compact offsets and tiles.
-  struct Group {
-    std::vector<int> ci, cj;
-    std::vector<Item> items;
-    int64_t n_px = 0;
-    size_t tile_off = 0, n_tiles = 0;
-    TileCaps caps;
-    double bytes = 0.0;
-  };
-  std::vector<Group> groups((size_t)sch->n_levels * 16);
+  // Per (level, group, half): cells (Eq. (15): group 4 (j mod 4) + (i mod 4)),
+  // clipped 3x3-cell regions, compact offsets and tiles.
+  std::vector<Part> parts((size_t)sch->n_levels * 16 * 2);
   std::vector<Tile> all_tiles;
-  int64_t max_px = 0;
-  size_t max_items = 0;
+  int64_t max_px = 1;
+  size_t max_items = 1;
   for (int h = 0; h < sch->n_levels; ++h) {
     const int cell = sch->cell[h];
     const int nci = (W + cell - 1) / cell, ncj = (H + cell - 1) / cell;
     for (int k = 0; k < 16; ++k) {
-      Group& g = groups[(size_t)h * 16 + k];
+      std::vector<std::pair<int, int>> cells;
       for (int j = k / 4; j < ncj; j += 4)
-        for (int i = k % 4; i < nci; i += 4) {
+        for (int i = k % 4; i < nci; i += 4) cells.emplace_back(i, j);
+      const size_t half = (cells.size() + 1) / 2;
+      for (int hp = 0; hp < 2; ++hp) {
+        Part& P = parts[((size_t)h * 16 + k) * 2 + hp];
+        const size_t b0 = hp == 0 ? 0 : half, b1 = hp == 0 ? half : cells.size();
+        for (size_t q = b0; q < b1; ++q) {
+          const int i = cells[q].first, j = cells[q].second;
           lexp_rect rr{(i - 1) * cell, (j - 1) * cell, (i + 2) * cell, (j + 2) * cell};
           int u0, v0, u1, v1;
           clip_rect(c, rr, &u0, &v0, &u1, &v1);
           Item it{};
           it.ru0 = u0; it.rv0 = v0; it.rw = u1 - u0; it.rh = v1 - v0;
-          it.out_off = g.n_px;
-          it.aux_off = g.n_px;
-          g.n_px += (int64_t)it.rw * it.rh;
-          g.ci.push_back(i);
-          g.cj.push_back(j);
-          g.items.push_back(it);
-          g.bytes += item_alg_bytes(c, it);
+          it.out_off = P.n_px;
+          it.aux_off = P.n_px;
+          P.n_px += (int64_t)it.rw * it.rh;
+          P.max_px = std::max(P.max_px, it.rw * it.rh);
+          P.ci.push_back(i);
+          P.cj.push_back(j);
+          P.items.push_back(it);
+          P.bytes += item_alg_bytes(c, it);
         }
-      std::vector<Tile> t;
-      plan_tiles(c, g.items.data(), (int)g.items.size(), t, g.caps);
-      g.tile_off = all_tiles.size();
-      g.n_tiles = t.size();
-      all_tiles.insert(all_tiles.end(), t.begin(), t.end());
-      max_px = std::max(max_px, g.n_px);
-      max_items = std::max(max_items, g.items.size());
+        std::vector<Tile> t;
+        plan_tiles(c, P.items.data(), (int)P.items.size(), t, P.caps);
+        P.tile_off = all_tiles.size();
+        P.n_tiles = t.size();
+        all_tiles.insert(all_tiles.end(), t.begin(), t.end());
+        max_px = std::max(max_px, P.n_px);
+        max_items = std::max(max_items, P.items.size());
+      }
     }
   }
   HIP_TRY(c->d_tiles.ensure(all_tiles.size()));
@@ -754,9 +875,18 @@ lexp_status lexp_optimize(lexp_ctx* c, const lexp_schedule* sch, uint64_t seed, 
   std::copy(all_tiles.begin(), all_tiles.end(), c->h_tiles.p);
   if (!all_tiles.empty())
     HIP_TRY(hipMemcpyAsync(c->d_tiles.p, c->h_tiles.p, sizeof(Tile) * all_tiles.size(), hipMemcpyHostToDevice, s));
-  HIP_TRY(c->d_phi.ensure((size_t)std::max<int64_t>(max_px, 1)));
-  HIP_TRY(c->d_items.ensure(std::max<size_t>(max_items, 1)));
-  HIP_TRY(c->h_items.ensure(std::max<size_t>(max_items, 1)));
+  for (auto& B : c->part) {
+    HIP_TRY(B.d_items.ensure(max_items));
+    HIP_TRY(B.d_phi.ensure((size_t)max_px));
+    HIP_TRY(B.d_terms.ensure((size_t)max_px * 5));
+    HIP_TRY(B.d_x.ensure((size_t)max_px));
+    HIP_TRY(B.d_flag.ensure(1));
+    HIP_TRY(B.h_items.ensure(max_items));
+    HIP_TRY(B.h_terms.ensure((size_t)max_px * 5));
+    HIP_TRY(B.h_x.ensure((size_t)max_px));
+    HIP_TRY(B.h_flag.ensure(1));
+    if (!B.ready) HIP_TRY(hipEventCreateWithFlags(&B.ready, hipEventDisableTiming));
+  }
 
   // Alg. 2 line 2: random initial labels and their per-pixel costs.
   std::vector<float> mirror((size_t)W * H * 3);
@@ -768,34 +898,27 @@ lexp_status lexp_optimize(lexp_ctx* c, const lexp_schedule* sch, uint64_t seed, 
   }
   if (time_trace) time_trace[0] = now_s();
 
-  std::vector<lexp_plane> alphas(max_items);
   double r_d = c->prm.disp_max / 2.0, r_n = 1.0;  // Alg. 2 line 3
   for (int it = 0; it < sch->iterations; ++it) {
     for (int h = 0; h < sch->n_levels; ++h) {
-      const int cell = sch->cell[h], kp = sch->k_prop[h], kr = sch->k_rand[h];
+      const int K = sch->k_prop[h] + sch->k_rand[h];
+      const StepArgs a{seed, it, h, sch->cell[h], sch->k_prop[h], r_d, r_n, mirror.data()};
       for (int k = 0; k < 16; ++k) {
-        Group& g = groups[(size_t)h * 16 + k];
-        const int n = (int)g.items.size();
-        if (n == 0) continue;
-        for (int step = 0; step < kp + kr; ++step) {
-          // proposals from the latest labels (Alg. 1)
-          c->pool->parallel_for(n, [&](int q, int) {
-            float a[3];
-            lexp::propose(W, H, mirror.data(), 3, seed, it, h, cell, g.ci[q], g.cj[q], step, kp, r_d, r_n, a);
-            g.items[q].a = a[0];
-            g.items[q].b = a[1];
-            g.items[q].c = a[2];
-          });
-          if ((st = wait_staging(c))) return st;
-          std::copy(g.items.begin(), g.items.end(), c->h_items.p);
-          HIP_TRY(hipMemcpyAsync(c->d_items.p, c->h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
-          st = launch_unary<0>(c, c->d_items.p, c->d_tiles.p + g.tile_off, (int)g.n_tiles, g.caps, nullptr,
-                               c->d_phi.p, s, g.bytes, g.n_px, n);
-          if (st) return st;
-          st = expand_batch(c, n, g.n_px, c->d_phi.p, labels, cur_cost, nullptr, nullptr, mirror.data(), nullptr, s,
-                            true);
-          if (st) return st;
-        }
+        Part* P[2] = {&parts[((size_t)h * 16 + k) * 2], &parts[((size_t)h * 16 + k) * 2 + 1]};
+        // Alg. 1 for every cell of the group.  The cells are independent
+        // (Lemma 3), so the two halves run staggered: while the host cuts
+        // one half, the device evaluates the other half's next candidate.
+        for (int hp = 0; hp < 2; ++hp)
+          if (!P[hp]->items.empty() && K > 0)
+            if ((st = enqueue_part(c, *P[hp], c->part[hp], c->d_tiles.p, a, 0, labels, cur_cost, s))) return st;
+        for (int step = 0; step < K; ++step)
+          for (int hp = 0; hp < 2; ++hp) {
+            if (P[hp]->items.empty()) continue;
+            if ((st = finish_part(c, *P[hp], c->part[hp], mirror.data(), labels, cur_cost, s))) return st;
+            if (step + 1 < K)
+              if ((st = enqueue_part(c, *P[hp], c->part[hp], c->d_tiles.p, a, step + 1, labels, cur_cost, s)))
+                return st;
+          }
       }
     }
     r_d *= 0.5;  // Alg. 2 line 12
@@ -806,9 +929,12 @@ lexp_status lexp_optimize(lexp_ctx* c, const lexp_schedule* sch, uint64_t seed, 
     if (time_trace) time_trace[it + 1] = now_s();
   }
   HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipEventRecord(c->staging_done, s));
   if (c->timing) collect_timing(c);
   return LEXP_OK;
 }
+
+extern "C" {
 
 lexp_status lexp_set_timing(lexp_ctx* c, int32_t enable) {
   if (!c) return fail(LEXP_EINVAL, "null context");
@@ -848,8 +974,13 @@ lexp_status lexp_solve_binary(int32_t w, int32_t h, int32_t neighbours, const in
                               uint8_t* x) {
   if (w < 0 || h < 0 || (neighbours != 4 && neighbours != 8)) return fail(LEXP_EINVAL, "bad grid");
   if ((int64_t)w * h > 0 && (!U || !w4 || !x)) return fail(LEXP_EINVAL, "null argument");
-  for (int64_t i = 0; i < (int64_t)w * h * 4; ++i)
+  const int64_t lim = (int64_t)1 << 30;
+  for (int64_t i = 0; i < (int64_t)w * h * 4; ++i) {
     if (w4[i] < 0) return fail(LEXP_EINVAL, "negative pairwise weight (not submodular)");
+    if (w4[i] > lim) return fail(LEXP_EINVAL, "pairwise weight exceeds 2^30");
+  }
+  for (int64_t i = 0; i < (int64_t)w * h; ++i)
+    if (U[i] > lim || U[i] < -lim) return fail(LEXP_EINVAL, "unary term exceeds 2^30 in magnitude");
   if ((int64_t)w * h == 0) return LEXP_OK;
   lexp::BKSolver bk;
   bk.load<int64_t>(w, h, neighbours == 8 ? 4 : 2, U, 1, w4, 4);

@@ -111,31 +111,35 @@ void propose(int width, int height, const float* labels, int stride, uint64_t se
 static const int kDU[8] = {1, 0, 1, -1, -1, 0, -1, 1};
 static const int kDV[8] = {0, 1, 1, 1, 0, -1, -1, -1};
 
+template <class V>
+static void reset(std::vector<V>& v, size_t n, V val) {
+  if (v.size() < n) v.resize(n);
+  std::fill(v.begin(), v.begin() + n, val);
+}
+
 template <class T>
 void BKSolver::load(int w, int h, int nf, const T* U, int u_stride, const T* w4, int w_stride) {
-  w_ = w; h_ = h; n_ = w * h; nf_ = nf;
+  w_ = w; h_ = h; nf_ = nf;
+  pw_ = w + 2;
+  pn_ = (w + 2) * (h + 2);
   ndirs_ = 0;
   for (int k = 0; k < nf; ++k) dirs_[ndirs_++] = k;
   for (int k = 0; k < nf; ++k) dirs_[ndirs_++] = k ^ 4;
-  tr_.assign(n_, 0);
-  rc_.assign((size_t)n_ * 8, 0);
-  nbr_.assign((size_t)n_ * 8, -1);
-  for (int i = 0; i < n_; ++i) {
-    const int u = i % w, v = i / w;
-    for (int k = 0; k < 8; ++k) {
-      const int nu = u + kDU[k], nv = v + kDV[k];
-      if (nu >= 0 && nu < w && nv >= 0 && nv < h) nbr_[(size_t)i * 8 + k] = nv * w + nu;
+  for (int k = 0; k < 8; ++k) off_[k] = kDV[k] * pw_ + kDU[k];
+  reset(tr_, (size_t)pn_, 0);
+  reset(rc_, (size_t)pn_ * 8, 0);
+  for (int v = 0; v < h; ++v)
+    for (int u = 0; u < w; ++u) {
+      const size_t q = (size_t)v * w + u;
+      const int i = (v + 1) * pw_ + (u + 1);
+      tr_[i] = -(int32_t)U[q * u_stride];  // U > 0: residual i->t; U < 0: residual s->i
+      for (int d = 0; d < nf; ++d) {
+        const int nu = u + kDU[d], nv = v + kDV[d];
+        if (nu < 0 || nu >= w || nv < 0 || nv >= h) continue;
+        const int32_t c = (int32_t)w4[q * w_stride + d];
+        if (c > 0) rc_[(size_t)(i + off_[d]) * 8 + (d ^ 4)] = c;  // arc n -> i: paid when x_n = 1, x_i = 0
+      }
     }
-  }
-  for (int i = 0; i < n_; ++i) {
-    tr_[i] = -(int64_t)U[(size_t)i * u_stride];  // U > 0: residual i->t; U < 0: residual s->i
-    for (int d = 0; d < nf; ++d) {
-      const int j = nbr(i, d);
-      if (j < 0) continue;
-      const int64_t c = (int64_t)w4[(size_t)i * w_stride + d];
-      if (c > 0) rc_[(size_t)j * 8 + (d ^ 4)] = c;  // arc j -> i: paid when x_j = 1, x_i = 0
-    }
-  }
 }
 
 template void BKSolver::load<int64_t>(int, int, int, const int64_t*, int, const int64_t*, int);
@@ -145,7 +149,7 @@ void BKSolver::push_active(int i) {
   if (in_active_[i]) return;
   in_active_[i] = 1;
   active_[a_tail_] = i;
-  a_tail_ = (a_tail_ + 1) % a_cap_;
+  a_tail_ = a_tail_ + 1 == a_cap_ ? 0 : a_tail_ + 1;
 }
 
 void BKSolver::make_orphan(int i) {
@@ -154,20 +158,19 @@ void BKSolver::make_orphan(int i) {
 }
 
 void BKSolver::augment(int a, int k, int b) {
-  int64_t f = rc_[(size_t)a * 8 + k];
+  int32_t f = rc_[(size_t)a * 8 + k];
   for (int i = a;;) {  // source side: tree arcs parent -> child
     const int p = parent_[i];
     if (p == kTerm) { f = std::min(f, tr_[i]); break; }
-    const int j = nbr(i, p);
+    const int j = i + off_[p];
     f = std::min(f, rc_[(size_t)j * 8 + (p ^ 4)]);
     i = j;
   }
   for (int i = b;;) {  // sink side: tree arcs child -> parent
     const int p = parent_[i];
     if (p == kTerm) { f = std::min(f, -tr_[i]); break; }
-    const int j = nbr(i, p);
     f = std::min(f, rc_[(size_t)i * 8 + p]);
-    i = j;
+    i += off_[p];
   }
   rc_[(size_t)a * 8 + k] -= f;
   rc_[(size_t)b * 8 + (k ^ 4)] += f;
@@ -178,7 +181,7 @@ void BKSolver::augment(int a, int k, int b) {
       if (tr_[i] == 0) make_orphan(i);
       break;
     }
-    const int j = nbr(i, p);
+    const int j = i + off_[p];
     rc_[(size_t)j * 8 + (p ^ 4)] -= f;
     rc_[(size_t)i * 8 + p] += f;
     if (rc_[(size_t)j * 8 + (p ^ 4)] == 0) make_orphan(i);
@@ -191,7 +194,7 @@ void BKSolver::augment(int a, int k, int b) {
       if (tr_[i] == 0) make_orphan(i);
       break;
     }
-    const int j = nbr(i, p);
+    const int j = i + off_[p];
     rc_[(size_t)i * 8 + p] -= f;
     rc_[(size_t)j * 8 + (p ^ 4)] += f;
     if (rc_[(size_t)i * 8 + p] == 0) make_orphan(i);
@@ -209,9 +212,9 @@ void BKSolver::adopt() {
     int best_d = INT_MAX;
     for (int q = 0; q < ndirs_; ++q) {
       const int k = dirs_[q];
-      const int j = nbr(i, k);
-      if (j < 0 || tree_[j] != t) continue;
-      const int64_t cap = (t == kS) ? rc_[(size_t)j * 8 + (k ^ 4)] : rc_[(size_t)i * 8 + k];
+      const int j = i + off_[k];
+      if (tree_[j] != t) continue;
+      const int32_t cap = (t == kS) ? rc_[(size_t)j * 8 + (k ^ 4)] : rc_[(size_t)i * 8 + k];
       if (cap <= 0) continue;
       // does j still lead to its terminal?
       int d = 0;
@@ -223,12 +226,12 @@ void BKSolver::adopt() {
         const int pm = parent_[m];
         if (pm == kTerm) { ts_[m] = time_; dist_[m] = 1; ok = true; break; }
         if (pm == kOrphan || pm == kNone) { ok = false; break; }
-        m = nbr(m, pm);
+        m += off_[pm];
       }
       if (!ok) continue;
       if (d < best_d) { best_d = d; best_k = k; }
       int dd = d;
-      for (m = j; ts_[m] != time_; m = nbr(m, parent_[m])) {
+      for (m = j; ts_[m] != time_; m += off_[parent_[m]]) {
         ts_[m] = time_;
         dist_[m] = dd--;
       }
@@ -243,9 +246,9 @@ void BKSolver::adopt() {
     // reach it become active, its children become orphans.
     for (int q = 0; q < ndirs_; ++q) {
       const int k = dirs_[q];
-      const int j = nbr(i, k);
-      if (j < 0 || tree_[j] != t) continue;
-      const int64_t cap = (t == kS) ? rc_[(size_t)j * 8 + (k ^ 4)] : rc_[(size_t)i * 8 + k];
+      const int j = i + off_[k];
+      if (tree_[j] != t) continue;
+      const int32_t cap = (t == kS) ? rc_[(size_t)j * 8 + (k ^ 4)] : rc_[(size_t)i * 8 + k];
       if (cap > 0) push_active(j);
       if (parent_[j] == (k ^ 4)) make_orphan(j);
     }
@@ -258,57 +261,81 @@ void BKSolver::adopt() {
 
 void BKSolver::solve(uint8_t* x) {
   flow_ = 0;
+  // Saturate the length-one paths s -> i -> j -> t first, in one linear pass:
+  // most augmentations of these small grids are of this kind, and pushing
+  // them here spares the search trees their bookkeeping.  The search below
+  // then completes a maximum flow from this residual graph.
+  for (int v = 0; v < h_; ++v)
+    for (int u = 0; u < w_; ++u) {
+      const int i = (v + 1) * pw_ + (u + 1);
+      for (int q = 0; q < ndirs_ && tr_[i] > 0; ++q) {
+        const int k = dirs_[q];
+        const int j = i + off_[k];
+        const int32_t c = rc_[(size_t)i * 8 + k];
+        if (c <= 0 || tr_[j] >= 0) continue;
+        const int32_t f = std::min(std::min(tr_[i], c), -tr_[j]);
+        tr_[i] -= f;
+        tr_[j] += f;
+        rc_[(size_t)i * 8 + k] -= f;
+        rc_[(size_t)j * 8 + (k ^ 4)] += f;
+        flow_ += f;
+      }
+    }
   time_ = 0;
-  parent_.assign(n_, kNone);
-  tree_.assign(n_, kFree);
-  in_active_.assign(n_, 0);
-  ts_.assign(n_, 0);
-  dist_.assign(n_, 0);
-  a_cap_ = (size_t)n_ + 1;
-  active_.assign(a_cap_, 0);
+  reset(parent_, (size_t)pn_, (int8_t)kNone);
+  reset(tree_, (size_t)pn_, (uint8_t)kFree);
+  reset(in_active_, (size_t)pn_, (uint8_t)0);
+  reset(ts_, (size_t)pn_, 0);
+  reset(dist_, (size_t)pn_, 0);
+  a_cap_ = (size_t)pn_ + 1;
+  if (active_.size() < a_cap_) active_.resize(a_cap_);
   a_head_ = a_tail_ = 0;
   orphans_.clear();
   o_head_ = 0;
-  for (int i = 0; i < n_; ++i) {
-    if (tr_[i] > 0) { tree_[i] = kS; parent_[i] = kTerm; dist_[i] = 1; push_active(i); }
-    else if (tr_[i] < 0) { tree_[i] = kT; parent_[i] = kTerm; dist_[i] = 1; push_active(i); }
-  }
+  for (int v = 0; v < h_; ++v)
+    for (int u = 0; u < w_; ++u) {
+      const int i = (v + 1) * pw_ + (u + 1);
+      if (tr_[i] > 0) { tree_[i] = kS; parent_[i] = kTerm; dist_[i] = 1; push_active(i); }
+      else if (tr_[i] < 0) { tree_[i] = kT; parent_[i] = kTerm; dist_[i] = 1; push_active(i); }
+    }
   for (;;) {
     int a = -1, b = -1, k_ab = -1;
     while (a_head_ != a_tail_) {
       const int i = active_[a_head_];
       if (tree_[i] == kFree) {
-        a_head_ = (a_head_ + 1) % a_cap_;
+        a_head_ = a_head_ + 1 == a_cap_ ? 0 : a_head_ + 1;
         in_active_[i] = 0;
         continue;
       }
       if (tree_[i] == kS) {
-        for (int q = 0; q < ndirs_ && a < 0; ++q) {
+        for (int q = 0; q < ndirs_; ++q) {
           const int k = dirs_[q];
-          const int j = nbr(i, k);
-          if (j < 0 || rc_[(size_t)i * 8 + k] <= 0) continue;
+          if (rc_[(size_t)i * 8 + k] <= 0) continue;
+          const int j = i + off_[k];
           if (tree_[j] == kFree) {
             tree_[j] = kS; parent_[j] = (int8_t)(k ^ 4); ts_[j] = ts_[i]; dist_[j] = dist_[i] + 1;
             push_active(j);
           } else if (tree_[j] == kT) {
             a = i; b = j; k_ab = k;
+            break;
           }
         }
       } else {
-        for (int q = 0; q < ndirs_ && a < 0; ++q) {
+        for (int q = 0; q < ndirs_; ++q) {
           const int k = dirs_[q];
-          const int j = nbr(i, k);
-          if (j < 0 || rc_[(size_t)j * 8 + (k ^ 4)] <= 0) continue;
+          const int j = i + off_[k];
+          if (rc_[(size_t)j * 8 + (k ^ 4)] <= 0) continue;
           if (tree_[j] == kFree) {
             tree_[j] = kT; parent_[j] = (int8_t)(k ^ 4); ts_[j] = ts_[i]; dist_[j] = dist_[i] + 1;
             push_active(j);
           } else if (tree_[j] == kS) {
             a = j; b = i; k_ab = k ^ 4;
+            break;
           }
         }
       }
       if (a >= 0) break;  // i stays at the head of the queue
-      a_head_ = (a_head_ + 1) % a_cap_;
+      a_head_ = a_head_ + 1 == a_cap_ ? 0 : a_head_ + 1;
       in_active_[i] = 0;
     }
     if (a < 0) break;
@@ -316,18 +343,23 @@ void BKSolver::solve(uint8_t* x) {
     adopt();
   }
   // source side of the residual graph
-  std::memset(x, 0, (size_t)n_);
+  reset(seen_, (size_t)pn_, (uint8_t)0);
   bfs_.clear();
-  for (int i = 0; i < n_; ++i)
-    if (tr_[i] > 0) { x[i] = 1; bfs_.push_back(i); }
-  for (size_t h = 0; h < bfs_.size(); ++h) {
-    const int i = bfs_[h];
+  for (int v = 0; v < h_; ++v)
+    for (int u = 0; u < w_; ++u) {
+      const int i = (v + 1) * pw_ + (u + 1);
+      if (tr_[i] > 0) { seen_[i] = 1; bfs_.push_back(i); }
+    }
+  for (size_t hd = 0; hd < bfs_.size(); ++hd) {
+    const int i = bfs_[hd];
     for (int q = 0; q < ndirs_; ++q) {
       const int k = dirs_[q];
-      const int j = nbr(i, k);
-      if (j >= 0 && !x[j] && rc_[(size_t)i * 8 + k] > 0) { x[j] = 1; bfs_.push_back(j); }
+      const int j = i + off_[k];
+      if (!seen_[j] && rc_[(size_t)i * 8 + k] > 0) { seen_[j] = 1; bfs_.push_back(j); }
     }
   }
+  for (int v = 0; v < h_; ++v)
+    for (int u = 0; u < w_; ++u) x[(size_t)v * w_ + u] = seen_[(v + 1) * pw_ + (u + 1)];
 }
 
 // ---------------------------------------------------------------------------

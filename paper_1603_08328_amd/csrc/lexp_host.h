@@ -33,7 +33,7 @@ void propose(int width, int height, const float* labels, int stride, uint64_t se
 // 8-neighbourhood, 2 for the 4-neighbourhood).
 class BKSolver {
  public:
-  // terms: per node (U, w_0..w_3) at `stride` elements apart.
+  // terms: per node U at u_stride, w_0..w_3 at w_stride (w_d >= 0).
   template <class T>
   void load(int w, int h, int nf, const T* U, int u_stride, const T* w4, int w_stride);
   // Max-flow, then x_i = 1 for nodes reachable from the source in the
@@ -42,22 +42,24 @@ class BKSolver {
   int64_t flow() const { return flow_; }
 
  private:
+  // Nodes live on a grid padded by one dead node on every side, so
+  // neighbours are plain index offsets; dead nodes have no capacity and
+  // never join a search tree.
   enum : int8_t { kNone = -1, kTerm = 8, kOrphan = 9 };
   enum : uint8_t { kFree = 0, kS = 1, kT = 2 };
-  int nbr(int i, int k) const { return nbr_[(size_t)i * 8 + k]; }
   void push_active(int i);
   void make_orphan(int i);
   void augment(int a, int k, int b);
   void adopt();
 
-  int w_ = 0, h_ = 0, n_ = 0, nf_ = 4;
+  int w_ = 0, h_ = 0, pw_ = 0, pn_ = 0, nf_ = 4;
+  int off_[8];
   int dirs_[8];
   int ndirs_ = 0;
   int64_t flow_ = 0;
   int32_t time_ = 0;
-  std::vector<int64_t> tr_;
-  std::vector<int64_t> rc_;
-  std::vector<int32_t> nbr_;
+  std::vector<int32_t> tr_;   // residual terminal capacity: > 0 from s, < 0 to t
+  std::vector<int32_t> rc_;   // residual arc capacities, 8 per node
   std::vector<int8_t> parent_;
   std::vector<uint8_t> tree_;
   std::vector<uint8_t> in_active_;
@@ -67,6 +69,7 @@ class BKSolver {
   std::vector<int32_t> orphans_;
   size_t o_head_ = 0;
   std::vector<int32_t> bfs_;
+  std::vector<uint8_t> seen_;
 };
 
 // ---- thread pool -----------------------------------------------------------
