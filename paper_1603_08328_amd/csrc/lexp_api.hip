@@ -172,7 +172,7 @@ double item_alg_bytes(const lexp_ctx* c, const Item& it) {
 }
 
 int max_tile_width(int r, size_t budget) {
-  const int ring = 2 * r + 1 + lexp::kChunk;
+  const int ring = lexp::unary_ring_rows(r);
   int tw = std::min({lexp::kMaxTW, lexp::kMaxWP - 2 * r, lexp::kMaxWM - 4 * r});
   for (; tw >= 1; --tw)
     if (lexp::unary_lds_bytes(ring, tw + 2 * r, tw, std::max(tw + 4 * r, tw + 2 * r)) <= budget) return tw;
@@ -181,10 +181,10 @@ int max_tile_width(int r, size_t budget) {
 
 // Splits items into column strips (width bounded by LDS and the kernel's
 // register layout) and row strips.  When a launch has fewer column strips
-// than two per CU, taller items are also cut into row strips (of at least
+// than CUs, taller items are also cut into row strips (of at least
 // kMinStripRows rows) so the launch fills the device; every strip recomputes
 // its own vertical margin.
-constexpr int kFillTiles = 512;
+constexpr int kFillTiles = 256;
 constexpr int kMinStripRows = 16;
 
 void plan_tiles(const lexp_ctx* c, const Item* items, int n, std::vector<Tile>& tiles, TileCaps& caps) {
@@ -251,7 +251,7 @@ lexp_status launch_unary(lexp_ctx* c, const Item* d_items, const Tile* d_tiles, 
                          const float4* label_field, float* out, hipStream_t s, double alg_bytes, int64_t evals,
                          int64_t n_items) {
   if (n_tiles <= 0) return LEXP_OK;
-  const int ring = 2 * c->r + 1 + lexp::kChunk;
+  const int ring = lexp::unary_ring_rows(c->r);
   const size_t lds = lexp::unary_lds_bytes(ring, caps.wp, caps.tw, caps.ws);
   if (lds > c->lds_limit || caps.wp > lexp::kMaxWP || caps.tw > lexp::kMaxTW || caps.ws > lexp::kMaxWM)
     return fail(LEXP_EINVAL, "tile exceeds kernel limits (lds %zu > %zu or width)", lds, c->lds_limit);
@@ -264,8 +264,25 @@ lexp_status launch_unary(lexp_ctx* c, const Item* d_items, const Tile* d_tiles, 
     eb = take_event(c);
     if (ea && eb) HIP_TRY(hipEventRecord(ea, s));
   }
-  hipLaunchKernelGGL(lexp::k_unary<MODE>, dim3(grid), dim3(256), lds, s, c->dp, c->left4, c->right4, c->guide,
-                     d_items, d_tiles, n_tiles, label_field, out, ring, caps.wp, caps.tw, caps.ws);
+  // instance by the number of 64-lane segments of an M row and of an R+ row
+  const int nseg = (caps.ws + 63) / 64, nc = (std::max(caps.wp, caps.tw) + 63) / 64;
+#define LEXP_LAUNCH(M, S, C)                                                                                       \
+  hipLaunchKernelGGL((lexp::k_unary<M, S, C>), dim3(grid), dim3(lexp::kWaves * 64), lds, s, c->dp, c->left4, c->right4, c->guide, \
+                     d_items, d_tiles, n_tiles, label_field, out, ring, caps.wp, caps.tw, caps.ws)
+  if constexpr (MODE == 1) {
+    LEXP_LAUNCH(1, 3, 2);
+  } else if (nseg <= 1 && nc <= 1) {
+    LEXP_LAUNCH(MODE, 1, 1);
+  } else if (nseg <= 2 && nc <= 1) {
+    LEXP_LAUNCH(MODE, 2, 1);
+  } else if (nseg <= 2) {
+    LEXP_LAUNCH(MODE, 2, 2);
+  } else if (nc <= 1) {
+    LEXP_LAUNCH(MODE, 3, 1);
+  } else {
+    LEXP_LAUNCH(MODE, 3, 2);
+  }
+#undef LEXP_LAUNCH
   HIP_TRY(hipGetLastError());
   if (timed && ea && eb) {
     HIP_TRY(hipEventRecord(eb, s));
@@ -525,9 +542,8 @@ lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const 
   int lds = 0;
   HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   c->lds_limit = (size_t)std::max(lds, 16384);
-  // two workgroups per CU when the tile allows it, else one
-  c->tw_lim = max_tile_width(c->r, c->lds_limit / 2);
-  if (c->tw_lim < 1) c->tw_lim = max_tile_width(c->r, c->lds_limit);
+  // one 16-wave workgroup per CU: a tile may use all of the CU's LDS
+  c->tw_lim = max_tile_width(c->r, c->lds_limit);
   if (c->tw_lim < 1) return fail(LEXP_EINVAL, "gf_radius %d needs more LDS than the device has", c->r);
   const size_t n = (size_t)c->W * c->H;
   HIP_TRY(hipMalloc((void**)&c->left4, n * sizeof(float4)));

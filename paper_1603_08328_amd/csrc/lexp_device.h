@@ -7,7 +7,8 @@
 
 namespace lexp {
 
-constexpr int kChunk = 4;              // rows per pipeline step of the fused cost kernel (one per wave)
+constexpr int kWaves = 16;              // waves per fused-cost workgroup (1024 threads)
+constexpr int kChunk = kWaves;          // rows per pipeline step of the fused cost kernel (one per wave)
 constexpr double kQuantum = 1048576.0;  // 2^20: binary-problem terms are ceil(x * 2^20)
 
 // forward neighbour offsets: each unordered pair of the 8-neighbourhood once
@@ -39,21 +40,29 @@ struct Tile {
 };
 
 // LDS bytes of one fused-cost workgroup for the given capacities.
-// Rings of 2r+1+kChunk rows (R+ and R widths), the coefficient rows, one scan
-// row per wave, and double-buffered vertical-sum carries; 4+1 floats each.
+// Rows held by the fused kernel's rings: the 2r+1 rows of a vertical window,
+// plus the rows one stage may run ahead of the next (two pipeline steps).
+inline int unary_ring_rows(int r) { return 2 * r + 1 + 2 * kChunk; }
+
+// LDS of one fused-cost workgroup: rings (R+ and R widths), two buffers of
+// coefficient rows, one scan row per wave and double-buffered vertical-sum
+// carries (float4 each); FP32 counts of the scan rows and carries; byte
+// counts of the ring and coefficient entries.
 inline size_t unary_lds_bytes(int ring, int wp_cap, int tw_cap, int ws_cap) {
-  const size_t n = (size_t)ring * wp_cap + (size_t)kChunk * wp_cap + (size_t)ring * tw_cap + 4 * (size_t)ws_cap +
-                   2 * (size_t)wp_cap + 2 * (size_t)tw_cap;
-  return n * (sizeof(float) * 4 + sizeof(float));
+  const size_t f4 = (size_t)ring * wp_cap + (size_t)2 * kChunk * wp_cap + (size_t)ring * tw_cap +
+                    (size_t)kWaves * ws_cap + 2 * (size_t)wp_cap + 2 * (size_t)tw_cap;
+  const size_t f1 = (size_t)kWaves * ws_cap + 2 * (size_t)wp_cap + 2 * (size_t)tw_cap;
+  const size_t b1 = (size_t)ring * wp_cap + (size_t)2 * kChunk * wp_cap + (size_t)ring * tw_cap;
+  return f4 * 16 + f1 * 4 + b1;
 }
 
-// Widths the fused kernel's register layout supports: an M row in three
-// 64-lane segments, R+ and R rows in two.
+// Widths the fused kernel's register layout supports: an M row in up to
+// three 64-lane segments, R+ and R rows in up to two.
 constexpr int kMaxWM = 192;
 constexpr int kMaxWP = 128;
 constexpr int kMaxTW = 128;
 
-template <int MODE>
+template <int MODE, int NSEG, int NC>
 __global__ void k_unary(DevParams P, const float4* left4, const float4* right4, const float* guide,
                         const Item* items, const Tile* tiles, int n_tiles, const float4* label_field, float* out,
                         int ring, int wp_cap, int tw_cap, int ws_cap);

@@ -107,21 +107,23 @@ __global__ void k_weights(const float* __restrict__ left, double* __restrict__ w
 }
 
 // ---------------------------------------------------------------------------
-// Fused unary cost.  One workgroup (4 wave64) per tile: a sub-rectangle of
-// one item's region.  Rows stream top to bottom; each pipeline step handles
-// up to kChunk rows per stage, one row per wave:
-//   A  raw cost rho' = rho - rho_max and rho' * I over one row of M,
-//      wave prefix scan (DPP), horizontal window sums at R+ columns -> ring1
-//   C  one R+ row per wave: vertical window sum (carried sum plus the rows
-//      that entered minus those that left) -> means over W'_k ->
-//      a_k = (Sigma_k + eU)^-1 (mean(I rho) - mu mean(rho)), b_k -> coef rows
-//   E  one coef row per wave: prefix scan, window sums at R columns -> ring3
-//   G  one R row per wave: vertical window sum -> phi = abar^T I_p + bbar + rho_max
-// Global operands of a step (image taps, guide statistics, I_p) are loaded one
-// step ahead; barriers wait on LDS traffic only, so those loads stay in flight.
-// A fifth channel counts samples with rho' != 0 (an exact integer in FP32):
-// where a window holds none, the sums are zero exactly, so a fully truncated
-// or out-of-view patch costs exactly rho_max under any label.
+// Fused unary cost.  One workgroup (16 wave64) per tile: a sub-rectangle of
+// one item's region.  Rows stream top to bottom through four stages; in every
+// pipeline step each stage handles up to kChunk rows, one row per wave, and
+// each stage consumes what the previous stage produced in the previous step,
+// so one workgroup barrier per step suffices:
+//   A  raw cost rho' = rho - rho_max and rho' * I over one row of M, wave
+//      prefix scan (DPP), horizontal window sums at the R+ columns -> ring1
+//   C  one R+ row: vertical window sum (the carried sum of the previous row
+//      plus the rows that entered minus those that left) -> means over W'_k
+//      -> a_k = (Sigma_k + eU)^-1 (mean(I rho) - mu mean(rho)), b_k
+//   E  one coefficient row: prefix scan, window sums at the R columns -> ring3
+//   G  one R row: vertical window sum -> phi = abar^T I_p + bbar + rho_max
+// Global operands of a step (image taps, guide statistics, I_p) are loaded
+// one step ahead with clamped, unconditional loads; barriers wait on LDS
+// traffic only.  A fifth channel counts samples with rho' != 0 exactly (a
+// byte in the rings): where a window holds none, the sums are zero exactly,
+// so a fully truncated or out-of-view patch costs exactly rho_max.
 // ---------------------------------------------------------------------------
 __device__ inline float4 f4add(float4 a, float4 b) { return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
 __device__ inline float4 f4sub(float4 a, float4 b) { return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w); }
@@ -149,47 +151,51 @@ __device__ inline float wave_scan1(float v) {
 
 __device__ inline float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
 
-constexpr int kSegA = 3;  // 64-column segments of an M row (wM <= 192)
-constexpr int kColC = 2;  // R+ columns per lane (wP <= 128)
-constexpr int kColG = 2;  // R columns per lane (tw <= 128)
+// Ring slot of a row, given the slot of a base row no more than `ring` rows earlier.
+__device__ inline int slot_of(int y, int base_row, int base_slot, int ring) {
+  const int s = base_slot + (y - base_row);
+  return s >= ring ? s - ring : s;
+}
 
-struct RowTaps {           // prefetched operands of one M row, per lane
-  float4 L[kSegA], R0[kSegA], R1[kSegA];
-  float t[kSegA];
-  bool ok[kSegA];
+template <int NSEG>
+struct RowTaps {  // prefetched operands of one M row, per lane
+  float4 L[NSEG], R0[NSEG], R1[NSEG];
+  float t[NSEG];
+  bool ok[NSEG];
 };
 
-__device__ inline void load_row(RowTaps& tp, int y, bool active, int xm0, int wM, int W, float la, float lb, float lc,
+// Loads of one M row: always issued (row and column indices clamped into the
+// image), so the number of loads in flight is known to the compiler.
+template <int NSEG>
+__device__ inline void load_row(RowTaps<NSEG>& tp, int y, int xm0, int wM, int W, int H, float la, float lb, float lc,
                                 int lane, const float4* __restrict__ left4, const float4* __restrict__ right4) {
   const float fW1 = (float)(W - 1);
   const float vf = (float)y;
+  const int yc = y < H - 1 ? y : H - 1;
+  const size_t row = (size_t)yc * W;
 #pragma unroll
-  for (int s = 0; s < kSegA; ++s) {
+  for (int s = 0; s < NSEG; ++s) {
     const int xi = s * 64 + lane;
-    tp.ok[s] = false;
-    if (active && xi < wM) {
-      const int x = xm0 + xi;
-      const float uf = (float)x;
-      const float d = fmaf(la, uf, fmaf(lb, vf, lc));
-      const float xs = uf - d;
-      if (xs >= 0.f && xs <= fW1) {
-        const float xf = floorf(xs);
-        int i0 = (int)xf;
-        float t = xs - xf;
-        int i1 = i0 + 1;
-        if (i0 >= W - 1) { i0 = W - 1; i1 = W - 1; t = 0.f; }
-        tp.R0[s] = right4[(size_t)y * W + i0];
-        tp.R1[s] = right4[(size_t)y * W + i1];
-        tp.L[s] = left4[(size_t)y * W + x];
-        tp.t[s] = t;
-        tp.ok[s] = true;
-      }
-    }
+    const int x = xm0 + xi;
+    const float uf = (float)x;
+    const float d = fmaf(la, uf, fmaf(lb, vf, lc));
+    const float xs = uf - d;
+    const bool ok = xi < wM && xs >= 0.f && xs <= fW1;
+    const float xf = floorf(ok ? xs : 0.f);
+    int i0 = (int)xf;
+    float t = (ok ? xs : 0.f) - xf;
+    int i1 = i0 + 1;
+    if (i0 >= W - 1) { i0 = W - 1; i1 = W - 1; t = 0.f; }
+    tp.R0[s] = right4[row + i0];
+    tp.R1[s] = right4[row + i1];
+    tp.L[s] = left4[row + (x < W - 1 ? x : W - 1)];
+    tp.t[s] = t;
+    tp.ok[s] = ok;
   }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_unary(DevParams P, const float4* __restrict__ left4,
+template <int MODE, int NSEG, int NC>
+__global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __restrict__ left4,
                                                const float4* __restrict__ right4, const float* __restrict__ guide,
                                                const Item* __restrict__ items, const Tile* __restrict__ tiles,
                                                int n_tiles, const float4* __restrict__ label_field,
@@ -236,19 +242,19 @@ __global__ __launch_bounds__(256) void k_unary(DevParams P, const float4* __rest
   const int own_u0 = (flags & kFirstCol) ? xp0 : tu0, own_u1 = (flags & kLastCol) ? xp1 : tu1;
   const int own_v0 = (flags & kFirstRow) ? yp0 : tv0, own_v1 = (flags & kLastRow) ? yp1 : tv1;
 
-  // shared memory carve-up: float4 arrays, then the count arrays in the same order
+  // shared memory: float4 arrays, float arrays, then byte counts
   float4* ring1v = smem4;
   float4* coefv = ring1v + (size_t)ring * wp_cap;
-  float4* ring3v = coefv + (size_t)kChunk * wp_cap;
+  float4* ring3v = coefv + (size_t)2 * kChunk * wp_cap;
   float4* scanv = ring3v + (size_t)ring * tw_cap;
-  float4* car1v = scanv + (size_t)4 * ws_cap;
+  float4* car1v = scanv + (size_t)kWaves * ws_cap;
   float4* car2v = car1v + (size_t)2 * wp_cap;
-  float* ring1c = reinterpret_cast<float*>(car2v + (size_t)2 * tw_cap);
-  float* coefc = ring1c + (size_t)ring * wp_cap;
-  float* ring3c = coefc + (size_t)kChunk * wp_cap;
-  float* scanc = ring3c + (size_t)ring * tw_cap;
-  float* car1c = scanc + (size_t)4 * ws_cap;
+  float* scanc = reinterpret_cast<float*>(car2v + (size_t)2 * tw_cap);
+  float* car1c = scanc + (size_t)kWaves * ws_cap;
   float* car2c = car1c + (size_t)2 * wp_cap;
+  uint8_t* ring1c = reinterpret_cast<uint8_t*>(car2c + (size_t)2 * tw_cap);
+  uint8_t* coefc = ring1c + (size_t)ring * wp_cap;
+  uint8_t* ring3c = coefc + (size_t)2 * kChunk * wp_cap;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -257,38 +263,42 @@ __global__ __launch_bounds__(256) void k_unary(DevParams P, const float4* __rest
   float4* sv = scanv + (size_t)wave * ws_cap;
   float* sc = scanc + (size_t)wave * ws_cap;
 
-  for (int i = tid; i < wp_cap; i += 256) { car1v[i] = make_float4(0.f, 0.f, 0.f, 0.f); car1c[i] = 0.f; }
-  for (int i = tid; i < tw_cap; i += 256) { car2v[i] = make_float4(0.f, 0.f, 0.f, 0.f); car2c[i] = 0.f; }
+  for (int i = tid; i < wp_cap; i += kWaves * 64) { car1v[i] = make_float4(0.f, 0.f, 0.f, 0.f); car1c[i] = 0.f; }
+  for (int i = tid; i < tw_cap; i += kWaves * 64) { car2v[i] = make_float4(0.f, 0.f, 0.f, 0.f); car2c[i] = 0.f; }
 
-  int produced = ym0;                 // next M row to produce
-  int kv = yp0;                       // next R+ row to emit
-  int hi_c = ym0 - 1, lo_c = ym0;     // M rows in the carried vertical sum
-  int pv = tv0;                       // next R row to output
-  int hi2_c = yp0 - 1, lo2_c = yp0;   // R+ rows in the carried vertical sum
-  int par1 = 0, par2 = 0;             // carry buffer parity
+  int produced = ym0;                    // M rows handed to ring1 (visible after the step)
+  int kv = yp0;                          // next R+ row to emit
+  int hi_c = ym0 - 1, lo_c = ym0;        // M rows in the carried vertical sum
+  int sb1 = 0;                           // ring1 slot of row lo_c
+  int e_first = yp0, e_rows = 0;         // coefficient rows emitted in the previous step
+  int kv_e = yp0;                        // R+ rows in ring3 (visible to G)
+  int pv = tv0;                          // next R row to output
+  int hi2_c = yp0 - 1, lo2_c = yp0;      // R+ rows in the carried vertical sum
+  int sb3 = 0;                           // ring3 slot of row lo2_c
+  int par1 = 0, par2 = 0, pc = 0;        // carry and coefficient buffer parities
 
-  // prefetch the first step's operands
-  RowTaps taps;
-  load_row(taps, produced + wave, produced + wave < ym1, xm0, wM, W, la, lb, lc, lane, left4, right4);
-  float gs[kColC][9];
+  // first step's operands
+  RowTaps<NSEG> taps;
+  load_row<NSEG>(taps, produced + wave, xm0, wM, W, H, la, lb, lc, lane, left4, right4);
+  float gs[NC][9];
   auto load_guide = [&](int k) {
+    const int kc = k < yp1 - 1 ? k : yp1 - 1;
 #pragma unroll
-    for (int j = 0; j < kColC; ++j) {
+    for (int j = 0; j < NC; ++j) {
       const int xi = j * 64 + lane;
-      if (k < yp1 && xi < wP) {
-        const size_t gi = (size_t)k * W + xp0 + xi;
+      const size_t gi = (size_t)kc * W + xp0 + (xi < wP - 1 ? xi : wP - 1);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) gs[j][q] = guide[q * hw + gi];
-      }
+      for (int q = 0; q < 9; ++q) gs[j][q] = guide[q * hw + gi];
     }
   };
   load_guide(kv + wave);
-  float4 lp[kColG];
+  float4 lp[NC];
   auto load_left = [&](int p) {
+    const int pc_ = p < tv1 - 1 ? p : tv1 - 1;
 #pragma unroll
-    for (int j = 0; j < kColG; ++j) {
+    for (int j = 0; j < NC; ++j) {
       const int xi = j * 64 + lane;
-      if (p < tv1 && xi < tw) lp[j] = left4[(size_t)p * W + tu0 + xi];
+      lp[j] = left4[(size_t)pc_ * W + tu0 + (xi < tw - 1 ? xi : tw - 1)];
     }
   };
   if (MODE != 1) load_left(pv + wave);
@@ -296,15 +306,16 @@ __global__ __launch_bounds__(256) void k_unary(DevParams P, const float4* __rest
 
   for (;;) {
     if (MODE == 1 ? (kv >= own_v1) : (pv >= tv1)) break;
+    const int avail1 = produced;  // ring1 rows written in earlier steps
+    const int avail3 = kv_e;      // ring3 rows written in earlier steps
+
     // ---- A: raw cost rows -> horizontal window sums ----------------------
     const int nA = min(kChunk, ym1 - produced);
     if (wave < nA) {
-      const int y = produced + wave;
       float4 carry = make_float4(0.f, 0.f, 0.f, 0.f);
       float carryc = 0.f;
 #pragma unroll
-      for (int s = 0; s < kSegA; ++s) {
-        if (s * 64 >= wM) break;
+      for (int s = 0; s < NSEG; ++s) {
         const int xi = s * 64 + lane;
         float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
         float nz = 0.f;
@@ -326,18 +337,16 @@ __global__ __launch_bounds__(256) void k_unary(DevParams P, const float4* __rest
         val.w = wave_scan1(val.w) + carry.w;
         nz = wave_scan1(nz) + carryc;
         if (xi < wM) { sv[xi] = val; sc[xi] = nz; }
-        carry = make_float4(lane63(val.x), lane63(val.y), lane63(val.z), lane63(val.w));
-        carryc = lane63(nz);
+        if (s + 1 < NSEG) {
+          carry = make_float4(lane63(val.x), lane63(val.y), lane63(val.z), lane63(val.w));
+          carryc = lane63(nz);
+        }
       }
-      (void)y;
-    }
-    // next step's image taps (rows produced + nA + wave), in flight from here
-    load_row(taps, produced + nA + wave, produced + nA + wave < ym1, xm0, wM, W, la, lb, lc, lane, left4, right4);
-    if (wave < nA) {
       // the scan row is private to this wave: its LDS writes precede these reads
-      const int slot = (produced + wave) % ring;
-      for (int s0 = 0; s0 < wP; s0 += 64) {
-        const int xi = s0 + lane;
+      const int slot = slot_of(produced + wave, lo_c, sb1, ring);
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const int xi = j * 64 + lane;
         if (xi < wP) {
           const int x = xp0 + xi;
           const int lo = (x - r > 0 ? x - r : 0) - xm0;
@@ -347,38 +356,40 @@ __global__ __launch_bounds__(256) void k_unary(DevParams P, const float4* __rest
           if (lo > 0) { h = f4sub(h, sv[lo - 1]); hc -= sc[lo - 1]; }
           if (hc == 0.f) h = make_float4(0.f, 0.f, 0.f, 0.f);
           ring1v[(size_t)slot * wp_cap + xi] = h;
-          ring1c[(size_t)slot * wp_cap + xi] = hc;
+          ring1c[(size_t)slot * wp_cap + xi] = (uint8_t)hc;
         }
       }
     }
-    produced += nA;
-    lds_barrier();
+    // next step's image taps, in flight from here
+    load_row<NSEG>(taps, produced + nA + wave, xm0, wM, W, H, la, lb, lc, lane, left4, right4);
 
     // ---- C: vertical sums over W'_k, linear coefficients -----------------
     int nC = 0;
     while (nC < kChunk && kv + nC < yp1) {
       const int k = kv + nC;
-      if ((k + r < H - 1 ? k + r : H - 1) >= produced) break;
+      if ((k + r < H - 1 ? k + r : H - 1) >= avail1) break;
       ++nC;
     }
     if (wave < nC) {
       const int k = kv + wave;
       const int hi_k = k + r < H - 1 ? k + r : H - 1;
       const int lo_k = k - r > 0 ? k - r : 0;
-      const float inv_rows = (float)(hi_k - lo_k + 1);
+      const float rows = (float)(hi_k - lo_k + 1);
 #pragma unroll
-      for (int j = 0; j < kColC; ++j) {
+      for (int j = 0; j < NC; ++j) {
         const int xi = j * 64 + lane;
         if (xi >= wP) continue;
         float4 V = car1v[(size_t)par1 * wp_cap + xi];
         float Vc = car1c[(size_t)par1 * wp_cap + xi];
         for (int y = hi_c + 1; y <= hi_k; ++y) {
-          V = f4add(V, ring1v[(size_t)(y % ring) * wp_cap + xi]);
-          Vc += ring1c[(size_t)(y % ring) * wp_cap + xi];
+          const int sl = slot_of(y, lo_c, sb1, ring);
+          V = f4add(V, ring1v[(size_t)sl * wp_cap + xi]);
+          Vc += (float)ring1c[(size_t)sl * wp_cap + xi];
         }
         for (int y = lo_c; y < lo_k; ++y) {
-          V = f4sub(V, ring1v[(size_t)(y % ring) * wp_cap + xi]);
-          Vc -= ring1c[(size_t)(y % ring) * wp_cap + xi];
+          const int sl = slot_of(y, lo_c, sb1, ring);
+          V = f4sub(V, ring1v[(size_t)sl * wp_cap + xi]);
+          Vc -= (float)ring1c[(size_t)sl * wp_cap + xi];
         }
         if (wave == nC - 1) {
           car1v[(size_t)(par1 ^ 1) * wp_cap + xi] = V;
@@ -386,7 +397,7 @@ __global__ __launch_bounds__(256) void k_unary(DevParams P, const float4* __rest
         }
         const int x = xp0 + xi;
         const int cx0 = x - r > 0 ? x - r : 0, cx1 = x + r < W - 1 ? x + r : W - 1;
-        const float inv_n = 1.0f / ((float)(cx1 - cx0 + 1) * inv_rows);
+        const float inv_n = 1.0f / ((float)(cx1 - cx0 + 1) * rows);
         float4 coef = make_float4(0.f, 0.f, 0.f, 0.f);
         float z = 0.f;
         if (Vc != 0.f) {
@@ -409,124 +420,145 @@ __global__ __launch_bounds__(256) void k_unary(DevParams P, const float4* __rest
             o[0] = coef.x; o[1] = coef.y; o[2] = coef.z; o[3] = coef.w + P.rho_max;
           }
         } else {
-          coefv[(size_t)wave * wp_cap + xi] = coef;
-          coefc[(size_t)wave * wp_cap + xi] = z;
+          coefv[((size_t)pc * kChunk + wave) * wp_cap + xi] = coef;
+          coefc[((size_t)pc * kChunk + wave) * wp_cap + xi] = (uint8_t)z;
         }
       }
     }
-    const int kv_start = kv;
+    const int emitted_first = kv;
     if (nC > 0) {
       const int k = kv + nC - 1;
+      const int new_lo = k - r > 0 ? k - r : 0;
+      sb1 = slot_of(new_lo, lo_c, sb1, ring);
+      lo_c = new_lo;
       hi_c = k + r < H - 1 ? k + r : H - 1;
-      lo_c = k - r > 0 ? k - r : 0;
       kv += nC;
       par1 ^= 1;
-      load_guide(kv + wave);
     }
-    lds_barrier();
-    if (MODE == 1) continue;
+    load_guide(kv + wave);
 
-    // ---- E: horizontal sums of (a, b) at the R columns --------------------
-    if (wave < nC) {
-      float4 carry = make_float4(0.f, 0.f, 0.f, 0.f);
-      float carryc = 0.f;
-      const float4* cv = coefv + (size_t)wave * wp_cap;
-      const float* cc = coefc + (size_t)wave * wp_cap;
-      for (int s0 = 0; s0 < wP; s0 += 64) {
-        const int xi = s0 + lane;
-        float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-        float z = 0.f;
-        if (xi < wP) { val = cv[xi]; z = cc[xi]; }
-        val.x = wave_scan1(val.x) + carry.x;
-        val.y = wave_scan1(val.y) + carry.y;
-        val.z = wave_scan1(val.z) + carry.z;
-        val.w = wave_scan1(val.w) + carry.w;
-        z = wave_scan1(z) + carryc;
-        if (xi < wP) { sv[xi] = val; sc[xi] = z; }
-        carry = make_float4(lane63(val.x), lane63(val.y), lane63(val.z), lane63(val.w));
-        carryc = lane63(z);
-      }
-      const int slot = (kv_start + wave) % ring;
-      for (int s0 = 0; s0 < tw; s0 += 64) {
-        const int xi = s0 + lane;
-        if (xi < tw) {
-          const int x = tu0 + xi;
-          const int lo = (x - r > 0 ? x - r : 0) - xp0;
-          const int hi = (x + r < W - 1 ? x + r : W - 1) - xp0;
-          float4 h = sv[hi];
-          float hc = sc[hi];
-          if (lo > 0) { h = f4sub(h, sv[lo - 1]); hc -= sc[lo - 1]; }
-          if (hc == 0.f) h = make_float4(0.f, 0.f, 0.f, 0.f);
-          ring3v[(size_t)slot * tw_cap + xi] = h;
-          ring3c[(size_t)slot * tw_cap + xi] = hc;
-        }
-      }
-    }
-    lds_barrier();
-
-    // ---- G: vertical sums over W'(p), output -------------------------------
-    int nG = 0;
-    while (pv + nG < tv1) {
-      const int p = pv + nG;
-      if ((p + r < H - 1 ? p + r : H - 1) >= kv) break;
-      ++nG;
-    }
-    for (int q0 = 0; q0 < nG; q0 += 4) {
-      const int q = q0 + wave;
-      if (q >= nG) continue;
-      const int p = pv + q;
-      const int hi2 = p + r < H - 1 ? p + r : H - 1;
-      const int lo2 = p - r > 0 ? p - r : 0;
-      const float rows = (float)(hi2 - lo2 + 1);
+    if (MODE != 1) {
+      // ---- E: horizontal sums of (a, b) at the R columns ------------------
+      if (wave < e_rows) {
+        float4 carry = make_float4(0.f, 0.f, 0.f, 0.f);
+        float carryc = 0.f;
+        const float4* cv = coefv + ((size_t)(pc ^ 1) * kChunk + wave) * wp_cap;
+        const uint8_t* cc = coefc + ((size_t)(pc ^ 1) * kChunk + wave) * wp_cap;
 #pragma unroll
-      for (int j = 0; j < kColG; ++j) {
-        const int xi = j * 64 + lane;
-        if (xi >= tw) continue;
-        float4 V2 = car2v[(size_t)par2 * tw_cap + xi];
-        float V2c = car2c[(size_t)par2 * tw_cap + xi];
-        for (int y = hi2_c + 1; y <= hi2; ++y) {
-          V2 = f4add(V2, ring3v[(size_t)(y % ring) * tw_cap + xi]);
-          V2c += ring3c[(size_t)(y % ring) * tw_cap + xi];
+        for (int j = 0; j < NC; ++j) {
+          const int xi = j * 64 + lane;
+          float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+          float z = 0.f;
+          if (xi < wP) { val = cv[xi]; z = (float)cc[xi]; }
+          val.x = wave_scan1(val.x) + carry.x;
+          val.y = wave_scan1(val.y) + carry.y;
+          val.z = wave_scan1(val.z) + carry.z;
+          val.w = wave_scan1(val.w) + carry.w;
+          z = wave_scan1(z) + carryc;
+          if (xi < wP) { sv[xi] = val; sc[xi] = z; }
+          if (j + 1 < NC) {
+            carry = make_float4(lane63(val.x), lane63(val.y), lane63(val.z), lane63(val.w));
+            carryc = lane63(z);
+          }
         }
-        for (int y = lo2_c; y < lo2; ++y) {
-          V2 = f4sub(V2, ring3v[(size_t)(y % ring) * tw_cap + xi]);
-          V2c -= ring3c[(size_t)(y % ring) * tw_cap + xi];
+        const int slot = slot_of(e_first + wave, lo2_c, sb3, ring);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const int xi = j * 64 + lane;
+          if (xi < tw) {
+            const int x = tu0 + xi;
+            const int lo = (x - r > 0 ? x - r : 0) - xp0;
+            const int hi = (x + r < W - 1 ? x + r : W - 1) - xp0;
+            float4 h = sv[hi];
+            float hc = sc[hi];
+            if (lo > 0) { h = f4sub(h, sv[lo - 1]); hc -= sc[lo - 1]; }
+            if (hc == 0.f) h = make_float4(0.f, 0.f, 0.f, 0.f);
+            ring3v[(size_t)slot * tw_cap + xi] = h;
+            ring3c[(size_t)slot * tw_cap + xi] = (uint8_t)hc;
+          }
         }
-        if (q == nG - 1) {
-          car2v[(size_t)(par2 ^ 1) * tw_cap + xi] = V2;
-          car2c[(size_t)(par2 ^ 1) * tw_cap + xi] = V2c;
-        }
-        const int x = tu0 + xi;
-        const int cx0 = x - r > 0 ? x - r : 0, cx1 = x + r < W - 1 ? x + r : W - 1;
-        const float np = (float)(cx1 - cx0 + 1) * rows;
-        float phi = 0.f;
-        if (V2c != 0.f) {
-          const float4 L = q0 == 0 ? lp[j] : left4[(size_t)p * W + x];
-          phi = (V2.x * (L.x * inv255) + V2.y * (L.y * inv255) + V2.z * (L.z * inv255) + V2.w) / np;
-        }
-        out[out_off + (long long)(p - rv0) * rw + (x - ru0)] = phi + P.rho_max;
       }
-    }
-    if (nG > 0) {
-      const int p = pv + nG - 1;
-      hi2_c = p + r < H - 1 ? p + r : H - 1;
-      lo2_c = p - r > 0 ? p - r : 0;
-      pv += nG;
-      par2 ^= 1;
+
+      // ---- G: vertical sums over W'(p), output -----------------------------
+      int nG = 0;
+      while (pv + nG < tv1) {
+        const int p = pv + nG;
+        if ((p + r < H - 1 ? p + r : H - 1) >= avail3) break;
+        ++nG;
+      }
+      for (int q0 = 0; q0 < nG; q0 += kWaves) {
+        const int q = q0 + wave;
+        if (q >= nG) continue;
+        const int p = pv + q;
+        const int hi2 = p + r < H - 1 ? p + r : H - 1;
+        const int lo2 = p - r > 0 ? p - r : 0;
+        const float rows = (float)(hi2 - lo2 + 1);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const int xi = j * 64 + lane;
+          if (xi >= tw) continue;
+          float4 V2 = car2v[(size_t)par2 * tw_cap + xi];
+          float V2c = car2c[(size_t)par2 * tw_cap + xi];
+          for (int y = hi2_c + 1; y <= hi2; ++y) {
+            const int sl = slot_of(y, lo2_c, sb3, ring);
+            V2 = f4add(V2, ring3v[(size_t)sl * tw_cap + xi]);
+            V2c += (float)ring3c[(size_t)sl * tw_cap + xi];
+          }
+          for (int y = lo2_c; y < lo2; ++y) {
+            const int sl = slot_of(y, lo2_c, sb3, ring);
+            V2 = f4sub(V2, ring3v[(size_t)sl * tw_cap + xi]);
+            V2c -= (float)ring3c[(size_t)sl * tw_cap + xi];
+          }
+          if (q == nG - 1) {
+            car2v[(size_t)(par2 ^ 1) * tw_cap + xi] = V2;
+            car2c[(size_t)(par2 ^ 1) * tw_cap + xi] = V2c;
+          }
+          const int x = tu0 + xi;
+          const int cx0 = x - r > 0 ? x - r : 0, cx1 = x + r < W - 1 ? x + r : W - 1;
+          const float np = (float)(cx1 - cx0 + 1) * rows;
+          float phi = 0.f;
+          if (V2c != 0.f) {
+            const float4 L = q0 == 0 ? lp[j] : left4[(size_t)p * W + x];
+            phi = (V2.x * (L.x * inv255) + V2.y * (L.y * inv255) + V2.z * (L.z * inv255) + V2.w) / np;
+          }
+          out[out_off + (long long)(p - rv0) * rw + (x - ru0)] = phi + P.rho_max;
+        }
+      }
+      if (nG > 0) {
+        const int p = pv + nG - 1;
+        const int new_lo2 = p - r > 0 ? p - r : 0;
+        sb3 = slot_of(new_lo2, lo2_c, sb3, ring);
+        lo2_c = new_lo2;
+        hi2_c = p + r < H - 1 ? p + r : H - 1;
+        pv += nG;
+        par2 ^= 1;
+      }
       load_left(pv + wave);
+      kv_e = e_first + e_rows;  // rows E wrote this step become visible next step
+      e_first = emitted_first;
+      e_rows = nC;
+      pc ^= 1;
     }
-    // no barrier needed here: the next step's first LDS writes (scan rows,
-    // ring1) do not touch ring3 or the G carries, and E writes ring3 only
-    // after two more barriers
+    produced += nA;
+    lds_barrier();
   }
 }
 
-template __global__ void k_unary<0>(DevParams, const float4*, const float4*, const float*, const Item*, const Tile*,
-                                    int, const float4*, float*, int, int, int, int);
-template __global__ void k_unary<1>(DevParams, const float4*, const float4*, const float*, const Item*, const Tile*,
-                                    int, const float4*, float*, int, int, int, int);
-template __global__ void k_unary<2>(DevParams, const float4*, const float4*, const float*, const Item*, const Tile*,
-                                    int, const float4*, float*, int, int, int, int);
+#define LEXP_UNARY_INST(M, S, C)                                                                                    \
+  template __global__ void k_unary<M, S, C>(DevParams, const float4*, const float4*, const float*, const Item*,    \
+                                            const Tile*, int, const float4*, float*, int, int, int, int);
+LEXP_UNARY_INST(0, 1, 1)
+LEXP_UNARY_INST(0, 2, 1)
+LEXP_UNARY_INST(0, 2, 2)
+LEXP_UNARY_INST(0, 3, 1)
+LEXP_UNARY_INST(0, 3, 2)
+LEXP_UNARY_INST(1, 3, 2)
+LEXP_UNARY_INST(2, 1, 1)
+LEXP_UNARY_INST(2, 2, 1)
+LEXP_UNARY_INST(2, 2, 2)
+LEXP_UNARY_INST(2, 3, 1)
+LEXP_UNARY_INST(2, 3, 2)
+#undef LEXP_UNARY_INST
 
 // ---------------------------------------------------------------------------
 // Smoothness term (Eqs. 10-12) in FP64, rounded as written.

@@ -114,41 +114,46 @@ def test_proposals_bitwise_equal_to_oracle(tiny_oracle):
     assert n == 3 * 3 * 20 * 8
 
 
-def test_fused_kernel_row_pipeline_fits_its_rings():
-    """Replays the fused cost kernel's row pipeline (rows produced, window
-    rows emitted, output rows) on the CPU for many tile shapes, checking that
-    the ring buffers never have to hold more than 2r+1+kChunk rows and that
-    the loop always ends."""
-    CH = 4
-    for H in (1, 2, 7, 48, 120):
-        for r in (1, 2, 5, 20):
-            ring = 2 * r + 1 + CH
+@pytest.mark.parametrize("CH", [4, 16])
+def test_fused_kernel_row_pipeline_fits_its_rings(CH):
+    """Replays the fused cost kernel's row pipeline on the CPU for many tile
+    shapes: per step, stage A produces up to kChunk rows, C emits window rows
+    from rows produced in earlier steps, E moves the previous step's rows into
+    the second ring and G outputs from rows E wrote in earlier steps.  Checks
+    that neither ring ever holds more than 2r+1+2*kChunk live rows and that
+    the loop ends.  The kernel moves 16 rows per step."""
+    for H in (1, 2, 7, 48, 120, 300):
+        for r in (1, 2, 5, 20, 32):
+            ring = 2 * r + 1 + 2 * CH
             for tv0 in range(0, H, max(1, H // 7)):
                 for th in (1, 3, 16, 128):
                     tv1 = min(tv0 + th, H)
                     yp0, yp1 = max(tv0 - r, 0), min(tv1 + r, H)
                     ym0, ym1 = max(tv0 - 2 * r, 0), min(tv1 + 2 * r, H)
-                    produced, kv, lo_cur, pv, lo2_cur = ym0, yp0, ym0, tv0, yp0
-                    iters = 0
+                    produced, kv, lo_c = ym0, yp0, ym0
+                    e_first, e_rows, kv_e = yp0, 0, yp0
+                    pv, lo2_c = tv0, yp0
+                    steps = 0
                     while pv < tv1:
-                        iters += 1
-                        assert iters < 10 * (ym1 - ym0 + 10)
-                        produced += min(CH, ym1 - produced)
-                        assert produced - lo_cur <= ring           # live rows of ring1
-                        kv0 = kv
-                        n = 0
-                        while n < CH and kv < yp1:
-                            hi = min(kv + r, H - 1)
-                            if hi >= produced:
-                                break
-                            lo_cur = max(kv - r, 0)
-                            kv += 1
-                            n += 1
-                        assert kv - lo2_cur <= ring                # live rows of ring3
-                        while pv < tv1:
-                            hi2 = min(pv + r, H - 1)
-                            if hi2 >= kv:
-                                break
-                            lo2_cur = max(pv - r, 0)
-                            pv += 1
-                        assert kv0 <= kv
+                        steps += 1
+                        assert steps < 4 * (ym1 - ym0) + 20
+                        avail1, avail3 = produced, kv_e
+                        nA = min(CH, ym1 - produced)
+                        assert produced + nA - lo_c <= ring          # ring1: C's rows + A's new rows
+                        nC = 0
+                        while nC < CH and kv + nC < yp1 and min(kv + nC + r, H - 1) < avail1:
+                            nC += 1
+                        first = kv
+                        if nC:
+                            lo_c = max(kv + nC - 1 - r, 0)
+                            kv += nC
+                        assert kv_e + e_rows - lo2_c <= ring         # ring3: G's rows + E's new rows
+                        nG = 0
+                        while pv + nG < tv1 and min(pv + nG + r, H - 1) < avail3:
+                            nG += 1
+                        if nG:
+                            lo2_c = max(pv + nG - 1 - r, 0)
+                            pv += nG
+                        kv_e = e_first + e_rows
+                        e_first, e_rows = first, nC
+                        produced += nA
