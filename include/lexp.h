@@ -192,9 +192,10 @@ lexp_status lexp_get_stats(lexp_ctx* ctx, lexp_stats* out);
 lexp_status lexp_reset_stats(lexp_ctx* ctx);
 
 /* Copies of the set-up buffers for inspection (device destinations, any may
- * be NULL): left4/right4 HxWx4 (R, G, B, x-gradient), guide HxWx9
- * (mu_0..2, inv00, inv01, inv02, inv11, inv12, inv22), weights HxWx4 float64
- * (w_pq for the forward neighbours, 0 outside the image). */
+ * be NULL): left4/right4 HxWx4 (R, G, B, x-gradient); guide as nine HxW
+ * planes, one after the other (mu_0..2 of the window W'_k, then inv00, inv01,
+ * inv02, inv11, inv12, inv22 of (Sigma_k + eU)^-1, Eq. 7); weights HxWx4
+ * float64 (w_pq for the forward neighbours, 0 outside the image). */
 lexp_status lexp_debug_guide(lexp_ctx* ctx, float* left4, float* right4, float* guide, double* weights,
                              void* hip_stream);
 

@@ -101,6 +101,7 @@ struct lexp_ctx {
   int tw_lim = 1;           // widest R tile column strip
   size_t lds_limit = 65536; // dynamic LDS per workgroup
   float4* left4 = nullptr;
+  float4* left4T = nullptr;  // column-major copy (index u*H + v)
   float4* right4 = nullptr;
   float* guide = nullptr;
   double* wts = nullptr;
@@ -267,7 +268,7 @@ lexp_status launch_unary(lexp_ctx* c, const Item* d_items, const Tile* d_tiles, 
   // instance by the number of 64-lane segments of an M row and of an R+ row
   const int nseg = (caps.ws + 63) / 64, nc = (std::max(caps.wp, caps.tw) + 63) / 64;
 #define LEXP_LAUNCH(M, S, C)                                                                                       \
-  hipLaunchKernelGGL((lexp::k_unary<M, S, C>), dim3(grid), dim3(lexp::kWaves * 64), lds, s, c->dp, c->left4, c->right4, c->guide, \
+  hipLaunchKernelGGL((lexp::k_unary<M, S, C>), dim3(grid), dim3(lexp::kWaves * 64), lds, s, c->dp, c->left4, c->left4T, c->right4, c->guide, \
                      d_items, d_tiles, n_tiles, label_field, out, ring, caps.wp, caps.tw, caps.ws)
   if constexpr (MODE == 1) {
     LEXP_LAUNCH(1, 3, 2);
@@ -547,14 +548,15 @@ lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const 
   if (c->tw_lim < 1) return fail(LEXP_EINVAL, "gf_radius %d needs more LDS than the device has", c->r);
   const size_t n = (size_t)c->W * c->H;
   HIP_TRY(hipMalloc((void**)&c->left4, n * sizeof(float4)));
+  HIP_TRY(hipMalloc((void**)&c->left4T, n * sizeof(float4)));
   HIP_TRY(hipMalloc((void**)&c->right4, n * sizeof(float4)));
   HIP_TRY(hipMalloc((void**)&c->guide, n * 9 * sizeof(float)));
   HIP_TRY(hipMalloc((void**)&c->wts, n * 4 * sizeof(double)));
   double* tmp = nullptr;
   HIP_TRY(hipMalloc((void**)&tmp, n * 9 * sizeof(double)));
   const int nb = (int)((n + 255) / 256);
-  hipLaunchKernelGGL(lexp::k_pack, dim3(nb), dim3(256), 0, s, left_hwc, c->left4, c->W, c->H);
-  hipLaunchKernelGGL(lexp::k_pack, dim3(nb), dim3(256), 0, s, right_hwc, c->right4, c->W, c->H);
+  hipLaunchKernelGGL(lexp::k_pack, dim3(nb), dim3(256), 0, s, left_hwc, c->left4, c->left4T, c->W, c->H);
+  hipLaunchKernelGGL(lexp::k_pack, dim3(nb), dim3(256), 0, s, right_hwc, c->right4, (float4*)nullptr, c->W, c->H);
   hipLaunchKernelGGL(lexp::k_guide_h, dim3(nb), dim3(256), 0, s, c->left4, tmp, c->W, c->H, c->r);
   hipLaunchKernelGGL(lexp::k_guide_v, dim3(nb), dim3(256), 0, s, tmp, c->guide, c->W, c->H, c->r, p.gf_eps);
   hipLaunchKernelGGL(lexp::k_weights, dim3(nb), dim3(256), 0, s, left_hwc, c->wts, c->W, c->H, p.gamma);
@@ -580,6 +582,7 @@ lexp_status lexp_destroy(lexp_ctx* c) {
   for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
   if (c->staging_done) (void)hipEventDestroy(c->staging_done);
   (void)hipFree(c->left4);
+  (void)hipFree(c->left4T);
   (void)hipFree(c->right4);
   (void)hipFree(c->guide);
   (void)hipFree(c->wts);
@@ -979,7 +982,11 @@ lexp_status lexp_debug_guide(lexp_ctx* c, float* left4, float* right4, float* gu
   const size_t n = (size_t)c->W * c->H;
   if (left4) HIP_TRY(hipMemcpyAsync(left4, c->left4, n * 16, hipMemcpyDeviceToDevice, s));
   if (right4) HIP_TRY(hipMemcpyAsync(right4, c->right4, n * 16, hipMemcpyDeviceToDevice, s));
-  if (guide) HIP_TRY(hipMemcpyAsync(guide, c->guide, n * 36, hipMemcpyDeviceToDevice, s));
+  if (guide) {
+    hipLaunchKernelGGL(lexp::k_guide_planes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c->guide, guide,
+                       c->W, c->H);
+    HIP_TRY(hipGetLastError());
+  }
   if (weights) HIP_TRY(hipMemcpyAsync(weights, c->wts, n * 32, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   return LEXP_OK;

@@ -45,13 +45,13 @@ struct Tile {
 inline int unary_ring_rows(int r) { return 2 * r + 1 + 2 * kChunk; }
 
 // LDS of one fused-cost workgroup: rings (R+ and R widths), two buffers of
-// coefficient rows, one scan row per wave and double-buffered vertical-sum
-// carries (float4 each); FP32 counts of the scan rows and carries; byte
-// counts of the ring and coefficient entries.
+// coefficient rows, one scan row per wave and the vertical-sum carries
+// (float4 each); FP32 counts of the scan rows and carries; byte counts of the
+// ring and coefficient entries.
 inline size_t unary_lds_bytes(int ring, int wp_cap, int tw_cap, int ws_cap) {
   const size_t f4 = (size_t)ring * wp_cap + (size_t)2 * kChunk * wp_cap + (size_t)ring * tw_cap +
-                    (size_t)kWaves * ws_cap + 2 * (size_t)wp_cap + 2 * (size_t)tw_cap;
-  const size_t f1 = (size_t)kWaves * ws_cap + 2 * (size_t)wp_cap + 2 * (size_t)tw_cap;
+                    (size_t)kWaves * ws_cap + (size_t)wp_cap + (size_t)tw_cap;
+  const size_t f1 = (size_t)kWaves * ws_cap + (size_t)wp_cap + (size_t)tw_cap;
   const size_t b1 = (size_t)ring * wp_cap + (size_t)2 * kChunk * wp_cap + (size_t)ring * tw_cap;
   return f4 * 16 + f1 * 4 + b1;
 }
@@ -63,12 +63,14 @@ constexpr int kMaxWP = 128;
 constexpr int kMaxTW = 128;
 
 template <int MODE, int NSEG, int NC>
-__global__ void k_unary(DevParams P, const float4* left4, const float4* right4, const float* guide,
+__global__ void k_unary(DevParams P, const float4* left4, const float4* left4T, const float4* right4,
+                        const float* guide,
                         const Item* items, const Tile* tiles, int n_tiles, const float4* label_field, float* out,
                         int ring, int wp_cap, int tw_cap, int ws_cap);
-__global__ void k_pack(const float* img, float4* out, int W, int H);
+__global__ void k_pack(const float* img, float4* out, float4* outT, int W, int H);
 __global__ void k_guide_h(const float4* left4, double* tmp, int W, int H, int r);
 __global__ void k_guide_v(const double* tmp, float* guide, int W, int H, int r, double eps);
+__global__ void k_guide_planes(const float* guide, float* planes, int W, int H);
 __global__ void k_weights(const float* left, double* wts, int W, int H, double gamma);
 __global__ void k_graph_terms(DevParams P, const Item* items, const float4* labels, const float* cur_cost,
                               const float* phi_alpha, const double* wts, int* terms, int* flag);

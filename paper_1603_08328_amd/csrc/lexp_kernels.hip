@@ -25,15 +25,19 @@ __device__ inline float gray_of(const float* px) {
   return 0.299f * px[0] + 0.587f * px[1] + 0.114f * px[2];
 }
 
-// (R, G, B, x-gradient of the gray value by [-0.5 0 0.5], replicated borders)
-__global__ void k_pack(const float* __restrict__ img, float4* __restrict__ out, int W, int H) {
+// (R, G, B, x-gradient of the gray value by [-0.5 0 0.5], replicated borders),
+// row-major; a column-major copy too where outT is given.
+__global__ void k_pack(const float* __restrict__ img, float4* __restrict__ out, float4* __restrict__ outT, int W,
+                       int H) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= W * H) return;
   const int u = i % W, v = i / W;
   const int ul = u > 0 ? u - 1 : 0, ur = u < W - 1 ? u + 1 : W - 1;
   const float* row = img + (size_t)v * W * 3;
   const float gx = 0.5f * (gray_of(row + ur * 3) - gray_of(row + ul * 3));
-  out[i] = make_float4(row[u * 3 + 0], row[u * 3 + 1], row[u * 3 + 2], gx);
+  const float4 val = make_float4(row[u * 3 + 0], row[u * 3 + 1], row[u * 3 + 2], gx);
+  out[i] = val;
+  if (outT) outT[(size_t)u * H + v] = val;
 }
 
 // Horizontal window sums of I = I_L/255 and I I^T (FP64).
@@ -53,8 +57,10 @@ __global__ void k_guide_h(const float4* __restrict__ left4, double* __restrict__
   for (int q = 0; q < 9; ++q) tmp[(size_t)q * W * H + i] = acc[q];
 }
 
-// Vertical sums -> mean mu_k and (Sigma_k + eU)^-1 by the adjugate, stored as
-// nine float planes (mu0, mu1, mu2, i00, i01, i02, i11, i12, i22).
+// Vertical sums -> mean mu_k and (Sigma_k + eU)^-1 by the adjugate.  Stored
+// column-major (index u*H + v) as float4 (mu0, mu1, mu2, i00), float4 (i01,
+// i02, i11, i12) and float i22, for the fused kernel, whose lanes read runs of
+// consecutive rows of one column.
 __global__ void k_guide_v(const double* __restrict__ tmp, float* __restrict__ guide, int W, int H, int r,
                           double eps) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -74,16 +80,26 @@ __global__ void k_guide_v(const double* __restrict__ tmp, float* __restrict__ gu
   const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
   const double det = a00 * c00 + a01 * c01 + a02 * c02;
   const double id = 1.0 / det;
-  const size_t hw = (size_t)W * H;
-  guide[0 * hw + i] = (float)m0;
-  guide[1 * hw + i] = (float)m1;
-  guide[2 * hw + i] = (float)m2;
-  guide[3 * hw + i] = (float)(c00 * id);
-  guide[4 * hw + i] = (float)(c01 * id);
-  guide[5 * hw + i] = (float)(c02 * id);
-  guide[6 * hw + i] = (float)(c11 * id);
-  guide[7 * hw + i] = (float)(c12 * id);
-  guide[8 * hw + i] = (float)(c22 * id);
+  const size_t hw = (size_t)W * H, t = (size_t)u * H + v;
+  float4* g0 = reinterpret_cast<float4*>(guide);
+  float4* g1 = g0 + hw;
+  float* g2 = reinterpret_cast<float*>(g1 + hw);
+  g0[t] = make_float4((float)m0, (float)m1, (float)m2, (float)(c00 * id));
+  g1[t] = make_float4((float)(c01 * id), (float)(c02 * id), (float)(c11 * id), (float)(c12 * id));
+  g2[t] = (float)(c22 * id);
+}
+
+// The guide statistics as nine row-major planes (for inspection).
+__global__ void k_guide_planes(const float* __restrict__ guide, float* __restrict__ planes, int W, int H) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= W * H) return;
+  const int u = i % W, v = i / W;
+  const size_t hw = (size_t)W * H, t = (size_t)u * H + v;
+  const float4* g0 = reinterpret_cast<const float4*>(guide);
+  const float4 a = g0[t], b = g0[hw + t];
+  const float c = reinterpret_cast<const float*>(g0 + 2 * hw)[t];
+  const float vals[9] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c};
+  for (int q = 0; q < 9; ++q) planes[q * hw + i] = vals[q];
 }
 
 // Contrast weights w_pq = exp(-||I_L(p) - I_L(q)||_1 / gamma), Eq. (11), for
@@ -151,6 +167,21 @@ __device__ inline float wave_scan1(float v) {
 
 __device__ inline float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
 
+// Inclusive prefix sum inside each row of 16 lanes.
+__device__ inline float row_scan16(float v) {
+  v = dpp_add<0x111, 0xf>(v);
+  v = dpp_add<0x112, 0xf>(v);
+  v = dpp_add<0x114, 0xf>(v);
+  v = dpp_add<0x118, 0xf>(v);
+  return v;
+}
+
+// Number of set bits of a wave mask in lanes 0..lane (inclusive).
+__device__ inline float mask_prefix(uint64_t m, int lane) {
+  const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  return (float)(below + (uint32_t)((m >> lane) & 1ull));
+}
+
 // Ring slot of a row, given the slot of a base row no more than `ring` rows earlier.
 __device__ inline int slot_of(int y, int base_row, int base_slot, int ring) {
   const int s = base_slot + (y - base_row);
@@ -196,6 +227,7 @@ __device__ inline void load_row(RowTaps<NSEG>& tp, int y, int xm0, int wM, int W
 
 template <int MODE, int NSEG, int NC>
 __global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __restrict__ left4,
+                                               const float4* __restrict__ left4T,
                                                const float4* __restrict__ right4, const float* __restrict__ guide,
                                                const Item* __restrict__ items, const Tile* __restrict__ tiles,
                                                int n_tiles, const float4* __restrict__ label_field,
@@ -248,11 +280,11 @@ __global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __res
   float4* ring3v = coefv + (size_t)2 * kChunk * wp_cap;
   float4* scanv = ring3v + (size_t)ring * tw_cap;
   float4* car1v = scanv + (size_t)kWaves * ws_cap;
-  float4* car2v = car1v + (size_t)2 * wp_cap;
-  float* scanc = reinterpret_cast<float*>(car2v + (size_t)2 * tw_cap);
+  float4* car2v = car1v + (size_t)wp_cap;
+  float* scanc = reinterpret_cast<float*>(car2v + (size_t)tw_cap);
   float* car1c = scanc + (size_t)kWaves * ws_cap;
-  float* car2c = car1c + (size_t)2 * wp_cap;
-  uint8_t* ring1c = reinterpret_cast<uint8_t*>(car2c + (size_t)2 * tw_cap);
+  float* car2c = car1c + (size_t)wp_cap;
+  uint8_t* ring1c = reinterpret_cast<uint8_t*>(car2c + (size_t)tw_cap);
   uint8_t* coefc = ring1c + (size_t)ring * wp_cap;
   uint8_t* ring3c = coefc + (size_t)2 * kChunk * wp_cap;
 
@@ -274,34 +306,43 @@ __global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __res
   int kv_e = yp0;                        // R+ rows in ring3 (visible to G)
   int pv = tv0;                          // next R row to output
   int hi2_c = yp0 - 1, lo2_c = yp0;      // R+ rows in the carried vertical sum
-  int sb3 = 0;                           // ring3 slot of row lo2_c
-  int par1 = 0, par2 = 0, pc = 0;        // carry and coefficient buffer parities
+  int lo2_base = yp0, sb3 = 0;           // ring3 slot sb3 holds row lo2_base
+  int pc = 0;                            // coefficient buffer parity
 
   // first step's operands
   RowTaps<NSEG> taps;
   load_row<NSEG>(taps, produced + wave, xm0, wM, W, H, la, lb, lc, lane, left4, right4);
+  // vertical stages: lane (column wave*4 + lane/16 [+64], row lane%16)
+  // guide statistics, column-major: a lane group reads 16 consecutive rows
+  const float4* g0 = reinterpret_cast<const float4*>(guide);
+  const float4* g1 = g0 + hw;
+  const float* g2 = reinterpret_cast<const float*>(g1 + hw);
   float gs[NC][9];
-  auto load_guide = [&](int k) {
+  auto load_guide = [&](int kbase) {
+    const int k = kbase + (lane & 15);
     const int kc = k < yp1 - 1 ? k : yp1 - 1;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
-      const int xi = j * 64 + lane;
-      const size_t gi = (size_t)kc * W + xp0 + (xi < wP - 1 ? xi : wP - 1);
-#pragma unroll
-      for (int q = 0; q < 9; ++q) gs[j][q] = guide[q * hw + gi];
+      const int ci = j * 64 + wave * 4 + (lane >> 4);
+      const size_t gi = (size_t)(xp0 + (ci < wP - 1 ? ci : wP - 1)) * H + kc;
+      const float4 a = g0[gi], b = g1[gi];
+      gs[j][0] = a.x; gs[j][1] = a.y; gs[j][2] = a.z; gs[j][3] = a.w;
+      gs[j][4] = b.x; gs[j][5] = b.y; gs[j][6] = b.z; gs[j][7] = b.w;
+      gs[j][8] = g2[gi];
     }
   };
-  load_guide(kv + wave);
+  load_guide(kv);
   float4 lp[NC];
-  auto load_left = [&](int p) {
+  auto load_left = [&](int pbase) {
+    const int p = pbase + (lane & 15);
     const int pc_ = p < tv1 - 1 ? p : tv1 - 1;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
-      const int xi = j * 64 + lane;
-      lp[j] = left4[(size_t)pc_ * W + tu0 + (xi < tw - 1 ? xi : tw - 1)];
+      const int ci = j * 64 + wave * 4 + (lane >> 4);
+      lp[j] = left4T[(size_t)(tu0 + (ci < tw - 1 ? ci : tw - 1)) * H + pc_];
     }
   };
-  if (MODE != 1) load_left(pv + wave);
+  if (MODE != 1) load_left(pv);
   lds_barrier();
 
   for (;;) {
@@ -331,15 +372,16 @@ __global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __res
             nz = 1.f;
           }
         }
+        const uint64_t nzm = __ballot(nz != 0.f);
         val.x = wave_scan1(val.x) + carry.x;
         val.y = wave_scan1(val.y) + carry.y;
         val.z = wave_scan1(val.z) + carry.z;
         val.w = wave_scan1(val.w) + carry.w;
-        nz = wave_scan1(nz) + carryc;
+        nz = mask_prefix(nzm, lane) + carryc;
         if (xi < wM) { sv[xi] = val; sc[xi] = nz; }
         if (s + 1 < NSEG) {
           carry = make_float4(lane63(val.x), lane63(val.y), lane63(val.z), lane63(val.w));
-          carryc = lane63(nz);
+          carryc += (float)__popcll(nzm);
         }
       }
       // the scan row is private to this wave: its LDS writes precede these reads
@@ -364,64 +406,84 @@ __global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __res
     load_row<NSEG>(taps, produced + nA + wave, xm0, wM, W, H, la, lb, lc, lane, left4, right4);
 
     // ---- C: vertical sums over W'_k, linear coefficients -----------------
+    // Lane (column c, row q): 4 columns x 16 rows per wave.  Each lane sums
+    // the rows that entered and left the window between row k-1 and row k,
+    // a prefix over the 16 lanes of the row gives every row's change from the
+    // carried sum of the previous step's last row.
     int nC = 0;
     while (nC < kChunk && kv + nC < yp1) {
       const int k = kv + nC;
       if ((k + r < H - 1 ? k + r : H - 1) >= avail1) break;
       ++nC;
     }
-    if (wave < nC) {
-      const int k = kv + wave;
+    if (nC > 0) {
+      const int q = lane & 15;
+      const int k = kv + q;
+      const bool rowok = q < nC;
       const int hi_k = k + r < H - 1 ? k + r : H - 1;
       const int lo_k = k - r > 0 ? k - r : 0;
+      const int hi_p = q == 0 ? hi_c : (k - 1 + r < H - 1 ? k - 1 + r : H - 1);
+      const int lo_p = q == 0 ? lo_c : (k - 1 - r > 0 ? k - 1 - r : 0);
       const float rows = (float)(hi_k - lo_k + 1);
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
-        const int xi = j * 64 + lane;
-        if (xi >= wP) continue;
-        float4 V = car1v[(size_t)par1 * wp_cap + xi];
-        float Vc = car1c[(size_t)par1 * wp_cap + xi];
-        for (int y = hi_c + 1; y <= hi_k; ++y) {
-          const int sl = slot_of(y, lo_c, sb1, ring);
-          V = f4add(V, ring1v[(size_t)sl * wp_cap + xi]);
-          Vc += (float)ring1c[(size_t)sl * wp_cap + xi];
-        }
-        for (int y = lo_c; y < lo_k; ++y) {
-          const int sl = slot_of(y, lo_c, sb1, ring);
-          V = f4sub(V, ring1v[(size_t)sl * wp_cap + xi]);
-          Vc -= (float)ring1c[(size_t)sl * wp_cap + xi];
-        }
-        if (wave == nC - 1) {
-          car1v[(size_t)(par1 ^ 1) * wp_cap + xi] = V;
-          car1c[(size_t)(par1 ^ 1) * wp_cap + xi] = Vc;
-        }
-        const int x = xp0 + xi;
-        const int cx0 = x - r > 0 ? x - r : 0, cx1 = x + r < W - 1 ? x + r : W - 1;
-        const float inv_n = 1.0f / ((float)(cx1 - cx0 + 1) * rows);
-        float4 coef = make_float4(0.f, 0.f, 0.f, 0.f);
-        float z = 0.f;
-        if (Vc != 0.f) {
-          const float* g = gs[j];
-          const float m0 = V.x * inv_n;
-          const float c0 = V.y * inv_n - g[0] * m0;
-          const float c1 = V.z * inv_n - g[1] * m0;
-          const float c2 = V.w * inv_n - g[2] * m0;
-          const float a0 = g[3] * c0 + g[4] * c1 + g[5] * c2;
-          const float a1 = g[4] * c0 + g[6] * c1 + g[7] * c2;
-          const float a2 = g[5] * c0 + g[7] * c1 + g[8] * c2;
-          const float b = m0 - (a0 * g[0] + a1 * g[1] + a2 * g[2]);
-          coef = make_float4(a0, a1, a2, b);
-          z = 1.f;
-        }
-        if (MODE == 1) {
-          if (x >= own_u0 && x < own_u1 && k >= own_v0 && k < own_v1) {
-            // coefficients of rho itself: a is unchanged by the shift, b gains rho_max
-            float* o = out + (out_off + (long long)(k - rv0) * rw + (x - ru0)) * 4;
-            o[0] = coef.x; o[1] = coef.y; o[2] = coef.z; o[3] = coef.w + P.rho_max;
+        const int ci = j * 64 + wave * 4 + (lane >> 4);
+        const bool colok = ci < wP;
+        float4 D = make_float4(0.f, 0.f, 0.f, 0.f);
+        float Dc = 0.f;
+        if (colok && rowok) {
+          for (int y = hi_p + 1; y <= hi_k; ++y) {
+            const int sl = slot_of(y, lo_c, sb1, ring);
+            D = f4add(D, ring1v[(size_t)sl * wp_cap + ci]);
+            Dc += (float)ring1c[(size_t)sl * wp_cap + ci];
           }
-        } else {
-          coefv[((size_t)pc * kChunk + wave) * wp_cap + xi] = coef;
-          coefc[((size_t)pc * kChunk + wave) * wp_cap + xi] = (uint8_t)z;
+          for (int y = lo_p; y < lo_k; ++y) {
+            const int sl = slot_of(y, lo_c, sb1, ring);
+            D = f4sub(D, ring1v[(size_t)sl * wp_cap + ci]);
+            Dc -= (float)ring1c[(size_t)sl * wp_cap + ci];
+          }
+        }
+        D.x = row_scan16(D.x);
+        D.y = row_scan16(D.y);
+        D.z = row_scan16(D.z);
+        D.w = row_scan16(D.w);
+        Dc = row_scan16(Dc);
+        if (colok && rowok) {
+          const float4 V = f4add(car1v[ci], D);
+          const float Vc = car1c[ci] + Dc;
+          const int x = xp0 + ci;
+          const int cx0 = x - r > 0 ? x - r : 0, cx1 = x + r < W - 1 ? x + r : W - 1;
+          const float inv_n = 1.0f / ((float)(cx1 - cx0 + 1) * rows);
+          float4 coef = make_float4(0.f, 0.f, 0.f, 0.f);
+          float z = 0.f;
+          if (Vc != 0.f) {
+            const float* g = gs[j];
+            const float m0 = V.x * inv_n;
+            const float c0 = V.y * inv_n - g[0] * m0;
+            const float c1 = V.z * inv_n - g[1] * m0;
+            const float c2 = V.w * inv_n - g[2] * m0;
+            const float a0 = g[3] * c0 + g[4] * c1 + g[5] * c2;
+            const float a1 = g[4] * c0 + g[6] * c1 + g[7] * c2;
+            const float a2 = g[5] * c0 + g[7] * c1 + g[8] * c2;
+            const float b = m0 - (a0 * g[0] + a1 * g[1] + a2 * g[2]);
+            coef = make_float4(a0, a1, a2, b);
+            z = 1.f;
+          }
+          if (MODE == 1) {
+            if (x >= own_u0 && x < own_u1 && k >= own_v0 && k < own_v1) {
+              // coefficients of rho itself: a is unchanged by the shift, b gains rho_max
+              float* o = out + (out_off + (long long)(k - rv0) * rw + (x - ru0)) * 4;
+              o[0] = coef.x; o[1] = coef.y; o[2] = coef.z; o[3] = coef.w + P.rho_max;
+            }
+          } else {
+            coefv[((size_t)pc * kChunk + q) * wp_cap + ci] = coef;
+            coefc[((size_t)pc * kChunk + q) * wp_cap + ci] = (uint8_t)z;
+          }
+          // the carried sum of a column is read and written by its own wave only
+          if (q == nC - 1) {
+            car1v[ci] = V;
+            car1c[ci] = Vc;
+          }
         }
       }
     }
@@ -433,9 +495,8 @@ __global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __res
       lo_c = new_lo;
       hi_c = k + r < H - 1 ? k + r : H - 1;
       kv += nC;
-      par1 ^= 1;
     }
-    load_guide(kv + wave);
+    load_guide(kv);
 
     if (MODE != 1) {
       // ---- E: horizontal sums of (a, b) at the R columns ------------------
@@ -461,7 +522,7 @@ __global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __res
             carryc = lane63(z);
           }
         }
-        const int slot = slot_of(e_first + wave, lo2_c, sb3, ring);
+        const int slot = slot_of(e_first + wave, lo2_base, sb3, ring);
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
           const int xi = j * 64 + lane;
@@ -480,60 +541,81 @@ __global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __res
       }
 
       // ---- G: vertical sums over W'(p), output -----------------------------
+      // Same lane layout as C: 4 R columns x 16 output rows per wave.
       int nG = 0;
       while (pv + nG < tv1) {
         const int p = pv + nG;
         if ((p + r < H - 1 ? p + r : H - 1) >= avail3) break;
         ++nG;
       }
-      for (int q0 = 0; q0 < nG; q0 += kWaves) {
-        const int q = q0 + wave;
-        if (q >= nG) continue;
-        const int p = pv + q;
+      for (int q0 = 0; q0 < nG; q0 += kChunk) {
+        const int q = lane & 15;
+        const int p = pv + q0 + q;
+        const bool rowok = q0 + q < nG;
         const int hi2 = p + r < H - 1 ? p + r : H - 1;
         const int lo2 = p - r > 0 ? p - r : 0;
+        const int hi_p = q == 0 ? hi2_c : (p - 1 + r < H - 1 ? p - 1 + r : H - 1);
+        const int lo_p = q == 0 ? lo2_c : (p - 1 - r > 0 ? p - 1 - r : 0);
         const float rows = (float)(hi2 - lo2 + 1);
+        const int last = (nG - q0 < kChunk ? nG - q0 : kChunk) - 1;
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          const int xi = j * 64 + lane;
-          if (xi >= tw) continue;
-          float4 V2 = car2v[(size_t)par2 * tw_cap + xi];
-          float V2c = car2c[(size_t)par2 * tw_cap + xi];
-          for (int y = hi2_c + 1; y <= hi2; ++y) {
-            const int sl = slot_of(y, lo2_c, sb3, ring);
-            V2 = f4add(V2, ring3v[(size_t)sl * tw_cap + xi]);
-            V2c += (float)ring3c[(size_t)sl * tw_cap + xi];
+          const int ci = j * 64 + wave * 4 + (lane >> 4);
+          const bool colok = ci < tw;
+          float4 D = make_float4(0.f, 0.f, 0.f, 0.f);
+          float Dc = 0.f;
+          if (colok && rowok) {
+            for (int y = hi_p + 1; y <= hi2; ++y) {
+              const int sl = slot_of(y, lo2_base, sb3, ring);
+              D = f4add(D, ring3v[(size_t)sl * tw_cap + ci]);
+              Dc += (float)ring3c[(size_t)sl * tw_cap + ci];
+            }
+            for (int y = lo_p; y < lo2; ++y) {
+              const int sl = slot_of(y, lo2_base, sb3, ring);
+              D = f4sub(D, ring3v[(size_t)sl * tw_cap + ci]);
+              Dc -= (float)ring3c[(size_t)sl * tw_cap + ci];
+            }
           }
-          for (int y = lo2_c; y < lo2; ++y) {
-            const int sl = slot_of(y, lo2_c, sb3, ring);
-            V2 = f4sub(V2, ring3v[(size_t)sl * tw_cap + xi]);
-            V2c -= (float)ring3c[(size_t)sl * tw_cap + xi];
+          D.x = row_scan16(D.x);
+          D.y = row_scan16(D.y);
+          D.z = row_scan16(D.z);
+          D.w = row_scan16(D.w);
+          Dc = row_scan16(Dc);
+          if (colok && rowok) {
+            const float4 V2 = f4add(car2v[ci], D);
+            const float V2c = car2c[ci] + Dc;
+            const int x = tu0 + ci;
+            const int cx0 = x - r > 0 ? x - r : 0, cx1 = x + r < W - 1 ? x + r : W - 1;
+            const float np = (float)(cx1 - cx0 + 1) * rows;
+            float phi = 0.f;
+            if (V2c != 0.f) {
+              const float4 L = q0 == 0 ? lp[j] : left4T[(size_t)x * H + p];
+              phi = (V2.x * (L.x * inv255) + V2.y * (L.y * inv255) + V2.z * (L.z * inv255) + V2.w) / np;
+            }
+            out[out_off + (long long)(p - rv0) * rw + (x - ru0)] = phi + P.rho_max;
+            if (q == last) {
+              car2v[ci] = V2;
+              car2c[ci] = V2c;
+            }
           }
-          if (q == nG - 1) {
-            car2v[(size_t)(par2 ^ 1) * tw_cap + xi] = V2;
-            car2c[(size_t)(par2 ^ 1) * tw_cap + xi] = V2c;
-          }
-          const int x = tu0 + xi;
-          const int cx0 = x - r > 0 ? x - r : 0, cx1 = x + r < W - 1 ? x + r : W - 1;
-          const float np = (float)(cx1 - cx0 + 1) * rows;
-          float phi = 0.f;
-          if (V2c != 0.f) {
-            const float4 L = q0 == 0 ? lp[j] : left4[(size_t)p * W + x];
-            phi = (V2.x * (L.x * inv255) + V2.y * (L.y * inv255) + V2.z * (L.z * inv255) + V2.w) / np;
-          }
-          out[out_off + (long long)(p - rv0) * rw + (x - ru0)] = phi + P.rho_max;
+        }
+        if (q0 + kChunk < nG) {  // a later batch starts from this batch's last row
+          const int pl = pv + q0 + last;
+          hi2_c = pl + r < H - 1 ? pl + r : H - 1;
+          lo2_c = pl - r > 0 ? pl - r : 0;
         }
       }
       if (nG > 0) {
         const int p = pv + nG - 1;
         const int new_lo2 = p - r > 0 ? p - r : 0;
-        sb3 = slot_of(new_lo2, lo2_c, sb3, ring);
+        // (the ring base moves only here: batches above address rows from the old base)
+        sb3 = slot_of(new_lo2, lo2_base, sb3, ring);
+        lo2_base = new_lo2;
         lo2_c = new_lo2;
         hi2_c = p + r < H - 1 ? p + r : H - 1;
         pv += nG;
-        par2 ^= 1;
       }
-      load_left(pv + wave);
+      load_left(pv);
       kv_e = e_first + e_rows;  // rows E wrote this step become visible next step
       e_first = emitted_first;
       e_rows = nC;
@@ -545,8 +627,9 @@ __global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __res
 }
 
 #define LEXP_UNARY_INST(M, S, C)                                                                                    \
-  template __global__ void k_unary<M, S, C>(DevParams, const float4*, const float4*, const float*, const Item*,    \
-                                            const Tile*, int, const float4*, float*, int, int, int, int);
+  template __global__ void k_unary<M, S, C>(DevParams, const float4*, const float4*, const float4*, const float*,  \
+                                            const Item*, const Tile*, int, const float4*, float*, int, int, int,   \
+                                            int);
 LEXP_UNARY_INST(0, 1, 1)
 LEXP_UNARY_INST(0, 2, 1)
 LEXP_UNARY_INST(0, 2, 2)
