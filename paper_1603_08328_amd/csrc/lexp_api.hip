@@ -186,6 +186,18 @@ int max_tile_width(int r, size_t budget) {
 // kMinStripRows rows) so the launch fills the device; every strip recomputes
 // its own vertical margin.
 constexpr int kFillTiles = 256;
+
+// Column strips of a region rw wide: the fewest strips of width <= tw_lim,
+// or up to two more when narrower strips need fewer 32-column segments per
+// M row (the raw-cost stage's work per row grows with those segments).
+int column_strips(const lexp_ctx* c, int rw) {
+  const int n0 = (rw + c->tw_lim - 1) / c->tw_lim;
+  auto segs = [&](int n) { return ((rw + n - 1) / n + 4 * c->r + 31) / 32; };
+  int best = n0;
+  for (int n = n0 + 1; n <= n0 + 2 && n <= rw; ++n)
+    if (segs(n) < segs(best)) best = n;
+  return best;
+}
 constexpr int kMinStripRows = 16;
 
 void plan_tiles(const lexp_ctx* c, const Item* items, int n, std::vector<Tile>& tiles, TileCaps& caps) {
@@ -193,12 +205,12 @@ void plan_tiles(const lexp_ctx* c, const Item* items, int n, std::vector<Tile>& 
   caps = TileCaps{};
   int64_t col_tiles = 0;
   for (int i = 0; i < n; ++i)
-    if (items[i].rw > 0 && items[i].rh > 0) col_tiles += (items[i].rw + c->tw_lim - 1) / c->tw_lim;
+    if (items[i].rw > 0 && items[i].rh > 0) col_tiles += column_strips(c, items[i].rw);
   const int fill = col_tiles > 0 ? (int)std::max<int64_t>(1, kFillTiles / col_tiles) : 1;
   for (int i = 0; i < n; ++i) {
     const Item& it = items[i];
     if (it.rw <= 0 || it.rh <= 0) continue;
-    const int ncs = (it.rw + c->tw_lim - 1) / c->tw_lim;
+    const int ncs = column_strips(c, it.rw);
     const int nrs = std::max((it.rh + kMaxTileRows - 1) / kMaxTileRows,
                              std::min((it.rh + kMinStripRows - 1) / kMinStripRows, fill));
     for (int rs = 0; rs < nrs; ++rs) {
@@ -265,24 +277,45 @@ lexp_status launch_unary(lexp_ctx* c, const Item* d_items, const Tile* d_tiles, 
     eb = take_event(c);
     if (ea && eb) HIP_TRY(hipEventRecord(ea, s));
   }
-  // instance by the number of 64-lane segments of an M row and of an R+ row
-  const int nseg = (caps.ws + 63) / 64, nc = (std::max(caps.wp, caps.tw) + 63) / 64;
+  // instance by the 32-column segments of an M row (64-lane segments of a row
+  // pair) and of an R+ row
+  const int nseg = (caps.ws + 31) / 32, nc = (std::max(caps.wp, caps.tw) + 31) / 32;
 #define LEXP_LAUNCH(M, S, C)                                                                                       \
-  hipLaunchKernelGGL((lexp::k_unary<M, S, C>), dim3(grid), dim3(lexp::kWaves * 64), lds, s, c->dp, c->left4, c->left4T, c->right4, c->guide, \
-                     d_items, d_tiles, n_tiles, label_field, out, ring, caps.wp, caps.tw, caps.ws)
-  if constexpr (MODE == 1) {
-    LEXP_LAUNCH(1, 3, 2);
-  } else if (nseg <= 1 && nc <= 1) {
-    LEXP_LAUNCH(MODE, 1, 1);
-  } else if (nseg <= 2 && nc <= 1) {
-    LEXP_LAUNCH(MODE, 2, 1);
-  } else if (nseg <= 2) {
-    LEXP_LAUNCH(MODE, 2, 2);
-  } else if (nc <= 1) {
-    LEXP_LAUNCH(MODE, 3, 1);
-  } else {
-    LEXP_LAUNCH(MODE, 3, 2);
+  hipLaunchKernelGGL((lexp::k_unary<M, S, C>), dim3(grid), dim3(lexp::kWaves * 64), lds, s, c->dp, c->left4,       \
+                     c->left4T, c->right4, c->guide, d_items, d_tiles, n_tiles, label_field, out, ring, caps.wp,   \
+                     caps.tw, caps.ws)
+#define LEXP_LAUNCH_C(M, S)  \
+  if (nc <= 1) {             \
+    LEXP_LAUNCH(M, S, 1);    \
+  } else if (nc <= 2) {      \
+    LEXP_LAUNCH(M, S, 2);    \
+  } else if (nc <= 3) {      \
+    LEXP_LAUNCH(M, S, 3);    \
+  } else {                   \
+    LEXP_LAUNCH(M, S, 4);    \
   }
+  if constexpr (MODE == 1) {
+    LEXP_LAUNCH(1, 4, 4);
+  } else if (nseg <= 1) {
+    LEXP_LAUNCH(MODE, 1, 1);
+  } else if (nseg <= 2) {
+    if (nc <= 1) {
+      LEXP_LAUNCH(MODE, 2, 1);
+    } else {
+      LEXP_LAUNCH(MODE, 2, 2);
+    }
+  } else if (nseg <= 3) {
+    if (nc <= 1) {
+      LEXP_LAUNCH(MODE, 3, 1);
+    } else if (nc <= 2) {
+      LEXP_LAUNCH(MODE, 3, 2);
+    } else {
+      LEXP_LAUNCH(MODE, 3, 3);
+    }
+  } else {
+    LEXP_LAUNCH_C(MODE, 4)
+  }
+#undef LEXP_LAUNCH_C
 #undef LEXP_LAUNCH
   HIP_TRY(hipGetLastError());
   if (timed && ea && eb) {
@@ -545,7 +578,8 @@ lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const 
   c->lds_limit = (size_t)std::max(lds, 16384);
   // one 16-wave workgroup per CU: a tile may use all of the CU's LDS
   c->tw_lim = max_tile_width(c->r, c->lds_limit);
-  if (c->tw_lim < 1) return fail(LEXP_EINVAL, "gf_radius %d needs more LDS than the device has", c->r);
+  if (c->tw_lim < 1)
+    return fail(LEXP_EINVAL, "gf_radius %d exceeds the fused kernel's limits (LDS or row width)", c->r);
   const size_t n = (size_t)c->W * c->H;
   HIP_TRY(hipMalloc((void**)&c->left4, n * sizeof(float4)));
   HIP_TRY(hipMalloc((void**)&c->left4T, n * sizeof(float4)));

@@ -56,9 +56,9 @@ inline size_t unary_lds_bytes(int ring, int wp_cap, int tw_cap, int ws_cap) {
   return f4 * 16 + f1 * 4 + b1;
 }
 
-// Widths the fused kernel's register layout supports: an M row in up to
-// three 64-lane segments, R+ and R rows in up to two.
-constexpr int kMaxWM = 192;
+// Widths the fused kernel's register layout supports: a pair of M rows in up
+// to four 64-lane segments, R+ and R rows in up to two.
+constexpr int kMaxWM = 128;
 constexpr int kMaxWP = 128;
 constexpr int kMaxTW = 128;
 

@@ -125,16 +125,20 @@ __global__ void k_weights(const float* __restrict__ left, double* __restrict__ w
 // ---------------------------------------------------------------------------
 // Fused unary cost.  One workgroup (16 wave64) per tile: a sub-rectangle of
 // one item's region.  Rows stream top to bottom through four stages; in every
-// pipeline step each stage handles up to kChunk rows, one row per wave, and
-// each stage consumes what the previous stage produced in the previous step,
-// so one workgroup barrier per step suffices:
-//   A  raw cost rho' = rho - rho_max and rho' * I over one row of M, wave
-//      prefix scan (DPP), horizontal window sums at the R+ columns -> ring1
-//   C  one R+ row: vertical window sum (the carried sum of the previous row
-//      plus the rows that entered minus those that left) -> means over W'_k
+// pipeline step each stage handles up to kChunk rows and consumes what the
+// previous stage produced in the previous step, so one workgroup barrier per
+// step suffices:
+//   A  (waves 0-7, two M rows each) raw cost rho' = rho - rho_max and rho' * I
+//      over the pair's pixels, then an in-place prefix along each row (serial
+//      runs per lane, DPP scan over 32 lanes), then horizontal window sums at
+//      the R+ columns -> ring1
+//   C  (all waves, 4 columns x 16 rows each) vertical window sums (carried
+//      sum of the previous row, plus the row that entered, minus the row that
+//      left) -> means over W'_k
 //      -> a_k = (Sigma_k + eU)^-1 (mean(I rho) - mu mean(rho)), b_k
-//   E  one coefficient row: prefix scan, window sums at the R columns -> ring3
-//   G  one R row: vertical window sum -> phi = abar^T I_p + bbar + rho_max
+//   E  (waves 8-15, two coefficient rows each) in-place prefix of the rows,
+//      window sums at the R columns -> ring3
+//   G  (all waves, as C) vertical window sums -> phi = abar^T I_p + bbar + rho_max
 // Global operands of a step (image taps, guide statistics, I_p) are loaded
 // one step ahead with clamped, unconditional loads; barriers wait on LDS
 // traffic only.  A fifth channel counts samples with rho' != 0 exactly (a
@@ -153,19 +157,17 @@ __device__ inline float dpp_add(float v) {
   return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xf, false));
 }
 
-// Inclusive prefix sum over the 64 lanes of a wave: shifts by 1, 2, 4, 8
-// inside each row of 16 lanes, then row broadcasts of lane 15 and lane 31.
-__device__ inline float wave_scan1(float v) {
+// Inclusive prefix sums over lanes 0-31 and over lanes 32-63: shifts by 1, 2,
+// 4, 8 inside each row of 16 lanes, then lane 15 of rows 0 and 2 added to rows
+// 1 and 3.
+__device__ inline float half_scan(float v) {
   v = dpp_add<0x111, 0xf>(v);
   v = dpp_add<0x112, 0xf>(v);
   v = dpp_add<0x114, 0xf>(v);
   v = dpp_add<0x118, 0xf>(v);
   v = dpp_add<0x142, 0xa>(v);
-  v = dpp_add<0x143, 0xc>(v);
   return v;
 }
-
-__device__ inline float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
 
 // Inclusive prefix sum inside each row of 16 lanes.
 __device__ inline float row_scan16(float v) {
@@ -176,10 +178,9 @@ __device__ inline float row_scan16(float v) {
   return v;
 }
 
-// Number of set bits of a wave mask in lanes 0..lane (inclusive).
-__device__ inline float mask_prefix(uint64_t m, int lane) {
-  const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-  return (float)(below + (uint32_t)((m >> lane) & 1ull));
+// Value of lane 15 of this lane's row of 16 lanes.
+__device__ inline float row_last(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute((lane | 15) << 2, __float_as_int(v)));
 }
 
 // Ring slot of a row, given the slot of a base row no more than `ring` rows earlier.
@@ -188,25 +189,32 @@ __device__ inline int slot_of(int y, int base_row, int base_slot, int ring) {
   return s >= ring ? s - ring : s;
 }
 
+// A wave's pair of M rows, flattened: segment s, lane l holds pixel
+// t = 64 s + l of the two rows laid end to end (row t / wM, column t % wM).
 template <int NSEG>
-struct RowTaps {  // prefetched operands of one M row, per lane
+struct RowTaps {  // prefetched operands of the pair, per lane
   float4 L[NSEG], R0[NSEG], R1[NSEG];
   float t[NSEG];
   bool ok[NSEG];
 };
 
-// Loads of one M row: always issued (row and column indices clamped into the
-// image), so the number of loads in flight is known to the compiler.
+// Loads of a row pair starting at row y: always issued (row and column
+// indices clamped into the image), so the number of loads in flight is known
+// to the compiler.
 template <int NSEG>
-__device__ inline void load_row(RowTaps<NSEG>& tp, int y, int xm0, int wM, int W, int H, float la, float lb, float lc,
-                                int lane, const float4* __restrict__ left4, const float4* __restrict__ right4) {
+__device__ inline void load_rows2(RowTaps<NSEG>& tp, int y, int xm0, int wM, int W, int H, float la, float lb,
+                                  float lc, int lane, const float4* __restrict__ left4,
+                                  const float4* __restrict__ right4) {
   const float fW1 = (float)(W - 1);
-  const float vf = (float)y;
-  const int yc = y < H - 1 ? y : H - 1;
-  const size_t row = (size_t)yc * W;
 #pragma unroll
   for (int s = 0; s < NSEG; ++s) {
-    const int xi = s * 64 + lane;
+    const int t = s * 64 + lane;
+    const int h = t >= wM ? 1 : 0;
+    const int xi = t - h * wM;
+    const int yy = y + h;
+    const int yc = yy < H - 1 ? yy : H - 1;
+    const size_t row = (size_t)yc * W;
+    const float vf = (float)yy;
     const int x = xm0 + xi;
     const float uf = (float)x;
     const float d = fmaf(la, uf, fmaf(lb, vf, lc));
@@ -214,13 +222,13 @@ __device__ inline void load_row(RowTaps<NSEG>& tp, int y, int xm0, int wM, int W
     const bool ok = xi < wM && xs >= 0.f && xs <= fW1;
     const float xf = floorf(ok ? xs : 0.f);
     int i0 = (int)xf;
-    float t = (ok ? xs : 0.f) - xf;
+    float tt = (ok ? xs : 0.f) - xf;
     int i1 = i0 + 1;
-    if (i0 >= W - 1) { i0 = W - 1; i1 = W - 1; t = 0.f; }
+    if (i0 >= W - 1) { i0 = W - 1; i1 = W - 1; tt = 0.f; }
     tp.R0[s] = right4[row + i0];
     tp.R1[s] = right4[row + i1];
     tp.L[s] = left4[row + (x < W - 1 ? x : W - 1)];
-    tp.t[s] = t;
+    tp.t[s] = tt;
     tp.ok[s] = ok;
   }
 }
@@ -279,10 +287,10 @@ __global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __res
   float4* coefv = ring1v + (size_t)ring * wp_cap;
   float4* ring3v = coefv + (size_t)2 * kChunk * wp_cap;
   float4* scanv = ring3v + (size_t)ring * tw_cap;
-  float4* car1v = scanv + (size_t)kWaves * ws_cap;
+  float4* car1v = scanv + (size_t)kChunk * ws_cap;
   float4* car2v = car1v + (size_t)wp_cap;
   float* scanc = reinterpret_cast<float*>(car2v + (size_t)tw_cap);
-  float* car1c = scanc + (size_t)kWaves * ws_cap;
+  float* car1c = scanc + (size_t)kChunk * ws_cap;
   float* car2c = car1c + (size_t)wp_cap;
   uint8_t* ring1c = reinterpret_cast<uint8_t*>(car2c + (size_t)tw_cap);
   uint8_t* coefc = ring1c + (size_t)ring * wp_cap;
@@ -292,337 +300,447 @@ __global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __res
   const int wave = tid >> 6, lane = tid & 63;
   const float inv255 = 1.0f / 255.0f;
   const size_t hw = (size_t)W * H;
-  float4* sv = scanv + (size_t)wave * ws_cap;
-  float* sc = scanc + (size_t)wave * ws_cap;
 
   for (int i = tid; i < wp_cap; i += kWaves * 64) { car1v[i] = make_float4(0.f, 0.f, 0.f, 0.f); car1c[i] = 0.f; }
   for (int i = tid; i < tw_cap; i += kWaves * 64) { car2v[i] = make_float4(0.f, 0.f, 0.f, 0.f); car2c[i] = 0.f; }
 
-  int produced = ym0;                    // M rows handed to ring1 (visible after the step)
-  int kv = yp0;                          // next R+ row to emit
-  int hi_c = ym0 - 1, lo_c = ym0;        // M rows in the carried vertical sum
-  int sb1 = 0;                           // ring1 slot of row lo_c
-  int e_first = yp0, e_rows = 0;         // coefficient rows emitted in the previous step
-  int kv_e = yp0;                        // R+ rows in ring3 (visible to G)
-  int pv = tv0;                          // next R row to output
-  int hi2_c = yp0 - 1, lo2_c = yp0;      // R+ rows in the carried vertical sum
-  int lo2_base = yp0, sb3 = 0;           // ring3 slot sb3 holds row lo2_base
-  int pc = 0;                            // coefficient buffer parity
-
-  // first step's operands
-  RowTaps<NSEG> taps;
-  load_row<NSEG>(taps, produced + wave, xm0, wM, W, H, la, lb, lc, lane, left4, right4);
-  // vertical stages: lane (column wave*4 + lane/16 [+64], row lane%16)
-  // guide statistics, column-major: a lane group reads 16 consecutive rows
-  const float4* g0 = reinterpret_cast<const float4*>(guide);
-  const float4* g1 = g0 + hw;
-  const float* g2 = reinterpret_cast<const float*>(g1 + hw);
-  float gs[NC][9];
-  auto load_guide = [&](int kbase) {
-    const int k = kbase + (lane & 15);
-    const int kc = k < yp1 - 1 ? k : yp1 - 1;
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      const int ci = j * 64 + wave * 4 + (lane >> 4);
-      const size_t gi = (size_t)(xp0 + (ci < wP - 1 ? ci : wP - 1)) * H + kc;
-      const float4 a = g0[gi], b = g1[gi];
-      gs[j][0] = a.x; gs[j][1] = a.y; gs[j][2] = a.z; gs[j][3] = a.w;
-      gs[j][4] = b.x; gs[j][5] = b.y; gs[j][6] = b.z; gs[j][7] = b.w;
-      gs[j][8] = g2[gi];
-    }
+  // Pipeline schedule (wave-uniform scalars).  Both wave groups below run
+  // the same recurrence, so they meet the same barriers.  Rings hold M rows
+  // >= ym0 (ring1) and R+ rows >= yp0 (ring3); rows above those never enter
+  // a window of the rows this tile emits.
+  int produced = ym0;            // M rows handed to ring1 (visible after the step)
+  int kv = yp0;                  // next R+ row to emit
+  int lo_c = ym0, sb1 = 0;       // ring1 slot sb1 holds row lo_c
+  int e_first = yp0, e_rows = 0; // coefficient rows emitted in the previous step
+  int kv_e = yp0;                // R+ rows in ring3 (visible to G)
+  int pv = tv0;                  // next R row to output
+  int lo2_base = yp0, sb3 = 0;   // ring3 slot sb3 holds row lo2_base
+  int pc = 0;                    // coefficient buffer parity
+  int nA = 0, nC = 0, nG = 0;
+  auto finished = [&]() { return MODE == 1 ? (kv >= own_v1) : (pv >= tv1); };
+  auto count_rows = [&]() {
+    nA = min(kChunk, ym1 - produced);
+    nC = 0;  // R+ rows whose window rows are all in ring1
+    while (nC < kChunk && kv + nC < yp1 && (kv + nC + r < H - 1 ? kv + nC + r : H - 1) < produced) ++nC;
+    nG = 0;  // R rows whose window rows are all in ring3
+    if (MODE != 1)
+      while (pv + nG < tv1 && (pv + nG + r < H - 1 ? pv + nG + r : H - 1) < kv_e) ++nG;
   };
-  load_guide(kv);
-  float4 lp[NC];
-  auto load_left = [&](int pbase) {
-    const int p = pbase + (lane & 15);
-    const int pc_ = p < tv1 - 1 ? p : tv1 - 1;
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      const int ci = j * 64 + wave * 4 + (lane >> 4);
-      lp[j] = left4T[(size_t)(tu0 + (ci < tw - 1 ? ci : tw - 1)) * H + pc_];
-    }
-  };
-  if (MODE != 1) load_left(pv);
-  lds_barrier();
-
-  for (;;) {
-    if (MODE == 1 ? (kv >= own_v1) : (pv >= tv1)) break;
-    const int avail1 = produced;  // ring1 rows written in earlier steps
-    const int avail3 = kv_e;      // ring3 rows written in earlier steps
-
-    // ---- A: raw cost rows -> horizontal window sums ----------------------
-    const int nA = min(kChunk, ym1 - produced);
-    if (wave < nA) {
-      float4 carry = make_float4(0.f, 0.f, 0.f, 0.f);
-      float carryc = 0.f;
-#pragma unroll
-      for (int s = 0; s < NSEG; ++s) {
-        const int xi = s * 64 + lane;
-        float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-        float nz = 0.f;
-        if (taps.ok[s]) {
-          const float t = taps.t[s];
-          const float4 L = taps.L[s], R0 = taps.R0[s], R1 = taps.R1[s];
-          const float col = fabsf(L.x - fmaf(t, R1.x - R0.x, R0.x)) + fabsf(L.y - fmaf(t, R1.y - R0.y, R0.y)) +
-                            fabsf(L.z - fmaf(t, R1.z - R0.z, R0.z));
-          const float gr = fabsf(L.w - fmaf(t, R1.w - R0.w, R0.w));
-          const float rp = P.oma * (fminf(col, P.tc) - P.tc) + P.al * (fminf(gr, P.tg) - P.tg);
-          if (rp != 0.f) {
-            val = make_float4(rp, rp * (L.x * inv255), rp * (L.y * inv255), rp * (L.z * inv255));
-            nz = 1.f;
-          }
-        }
-        const uint64_t nzm = __ballot(nz != 0.f);
-        val.x = wave_scan1(val.x) + carry.x;
-        val.y = wave_scan1(val.y) + carry.y;
-        val.z = wave_scan1(val.z) + carry.z;
-        val.w = wave_scan1(val.w) + carry.w;
-        nz = mask_prefix(nzm, lane) + carryc;
-        if (xi < wM) { sv[xi] = val; sc[xi] = nz; }
-        if (s + 1 < NSEG) {
-          carry = make_float4(lane63(val.x), lane63(val.y), lane63(val.z), lane63(val.w));
-          carryc += (float)__popcll(nzm);
-        }
-      }
-      // the scan row is private to this wave: its LDS writes precede these reads
-      const int slot = slot_of(produced + wave, lo_c, sb1, ring);
-#pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        const int xi = j * 64 + lane;
-        if (xi < wP) {
-          const int x = xp0 + xi;
-          const int lo = (x - r > 0 ? x - r : 0) - xm0;
-          const int hi = (x + r < W - 1 ? x + r : W - 1) - xm0;
-          float4 h = sv[hi];
-          float hc = sc[hi];
-          if (lo > 0) { h = f4sub(h, sv[lo - 1]); hc -= sc[lo - 1]; }
-          if (hc == 0.f) h = make_float4(0.f, 0.f, 0.f, 0.f);
-          ring1v[(size_t)slot * wp_cap + xi] = h;
-          ring1c[(size_t)slot * wp_cap + xi] = (uint8_t)hc;
-        }
-      }
-    }
-    // next step's image taps, in flight from here
-    load_row<NSEG>(taps, produced + nA + wave, xm0, wM, W, H, la, lb, lc, lane, left4, right4);
-
-    // ---- C: vertical sums over W'_k, linear coefficients -----------------
-    // Lane (column c, row q): 4 columns x 16 rows per wave.  Each lane sums
-    // the rows that entered and left the window between row k-1 and row k,
-    // a prefix over the 16 lanes of the row gives every row's change from the
-    // carried sum of the previous step's last row.
-    int nC = 0;
-    while (nC < kChunk && kv + nC < yp1) {
-      const int k = kv + nC;
-      if ((k + r < H - 1 ? k + r : H - 1) >= avail1) break;
-      ++nC;
-    }
-    if (nC > 0) {
-      const int q = lane & 15;
-      const int k = kv + q;
-      const bool rowok = q < nC;
-      const int hi_k = k + r < H - 1 ? k + r : H - 1;
-      const int lo_k = k - r > 0 ? k - r : 0;
-      const int hi_p = q == 0 ? hi_c : (k - 1 + r < H - 1 ? k - 1 + r : H - 1);
-      const int lo_p = q == 0 ? lo_c : (k - 1 - r > 0 ? k - 1 - r : 0);
-      const float rows = (float)(hi_k - lo_k + 1);
-#pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        const int ci = j * 64 + wave * 4 + (lane >> 4);
-        const bool colok = ci < wP;
-        float4 D = make_float4(0.f, 0.f, 0.f, 0.f);
-        float Dc = 0.f;
-        if (colok && rowok) {
-          for (int y = hi_p + 1; y <= hi_k; ++y) {
-            const int sl = slot_of(y, lo_c, sb1, ring);
-            D = f4add(D, ring1v[(size_t)sl * wp_cap + ci]);
-            Dc += (float)ring1c[(size_t)sl * wp_cap + ci];
-          }
-          for (int y = lo_p; y < lo_k; ++y) {
-            const int sl = slot_of(y, lo_c, sb1, ring);
-            D = f4sub(D, ring1v[(size_t)sl * wp_cap + ci]);
-            Dc -= (float)ring1c[(size_t)sl * wp_cap + ci];
-          }
-        }
-        D.x = row_scan16(D.x);
-        D.y = row_scan16(D.y);
-        D.z = row_scan16(D.z);
-        D.w = row_scan16(D.w);
-        Dc = row_scan16(Dc);
-        if (colok && rowok) {
-          const float4 V = f4add(car1v[ci], D);
-          const float Vc = car1c[ci] + Dc;
-          const int x = xp0 + ci;
-          const int cx0 = x - r > 0 ? x - r : 0, cx1 = x + r < W - 1 ? x + r : W - 1;
-          const float inv_n = 1.0f / ((float)(cx1 - cx0 + 1) * rows);
-          float4 coef = make_float4(0.f, 0.f, 0.f, 0.f);
-          float z = 0.f;
-          if (Vc != 0.f) {
-            const float* g = gs[j];
-            const float m0 = V.x * inv_n;
-            const float c0 = V.y * inv_n - g[0] * m0;
-            const float c1 = V.z * inv_n - g[1] * m0;
-            const float c2 = V.w * inv_n - g[2] * m0;
-            const float a0 = g[3] * c0 + g[4] * c1 + g[5] * c2;
-            const float a1 = g[4] * c0 + g[6] * c1 + g[7] * c2;
-            const float a2 = g[5] * c0 + g[7] * c1 + g[8] * c2;
-            const float b = m0 - (a0 * g[0] + a1 * g[1] + a2 * g[2]);
-            coef = make_float4(a0, a1, a2, b);
-            z = 1.f;
-          }
-          if (MODE == 1) {
-            if (x >= own_u0 && x < own_u1 && k >= own_v0 && k < own_v1) {
-              // coefficients of rho itself: a is unchanged by the shift, b gains rho_max
-              float* o = out + (out_off + (long long)(k - rv0) * rw + (x - ru0)) * 4;
-              o[0] = coef.x; o[1] = coef.y; o[2] = coef.z; o[3] = coef.w + P.rho_max;
-            }
-          } else {
-            coefv[((size_t)pc * kChunk + q) * wp_cap + ci] = coef;
-            coefc[((size_t)pc * kChunk + q) * wp_cap + ci] = (uint8_t)z;
-          }
-          // the carried sum of a column is read and written by its own wave only
-          if (q == nC - 1) {
-            car1v[ci] = V;
-            car1c[ci] = Vc;
-          }
-        }
-      }
-    }
+  auto advance = [&]() {
     const int emitted_first = kv;
-    if (nC > 0) {
+    if (nC > 0) {  // the next step's leaving rows start at row kv+nC-r-1
       const int k = kv + nC - 1;
-      const int new_lo = k - r > 0 ? k - r : 0;
+      const int new_lo = k - r > ym0 ? k - r : ym0;
       sb1 = slot_of(new_lo, lo_c, sb1, ring);
       lo_c = new_lo;
-      hi_c = k + r < H - 1 ? k + r : H - 1;
       kv += nC;
     }
-    load_guide(kv);
-
-    if (MODE != 1) {
-      // ---- E: horizontal sums of (a, b) at the R columns ------------------
-      if (wave < e_rows) {
-        float4 carry = make_float4(0.f, 0.f, 0.f, 0.f);
-        float carryc = 0.f;
-        const float4* cv = coefv + ((size_t)(pc ^ 1) * kChunk + wave) * wp_cap;
-        const uint8_t* cc = coefc + ((size_t)(pc ^ 1) * kChunk + wave) * wp_cap;
-#pragma unroll
-        for (int j = 0; j < NC; ++j) {
-          const int xi = j * 64 + lane;
-          float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-          float z = 0.f;
-          if (xi < wP) { val = cv[xi]; z = (float)cc[xi]; }
-          val.x = wave_scan1(val.x) + carry.x;
-          val.y = wave_scan1(val.y) + carry.y;
-          val.z = wave_scan1(val.z) + carry.z;
-          val.w = wave_scan1(val.w) + carry.w;
-          z = wave_scan1(z) + carryc;
-          if (xi < wP) { sv[xi] = val; sc[xi] = z; }
-          if (j + 1 < NC) {
-            carry = make_float4(lane63(val.x), lane63(val.y), lane63(val.z), lane63(val.w));
-            carryc = lane63(z);
-          }
-        }
-        const int slot = slot_of(e_first + wave, lo2_base, sb3, ring);
-#pragma unroll
-        for (int j = 0; j < NC; ++j) {
-          const int xi = j * 64 + lane;
-          if (xi < tw) {
-            const int x = tu0 + xi;
-            const int lo = (x - r > 0 ? x - r : 0) - xp0;
-            const int hi = (x + r < W - 1 ? x + r : W - 1) - xp0;
-            float4 h = sv[hi];
-            float hc = sc[hi];
-            if (lo > 0) { h = f4sub(h, sv[lo - 1]); hc -= sc[lo - 1]; }
-            if (hc == 0.f) h = make_float4(0.f, 0.f, 0.f, 0.f);
-            ring3v[(size_t)slot * tw_cap + xi] = h;
-            ring3c[(size_t)slot * tw_cap + xi] = (uint8_t)hc;
-          }
-        }
-      }
-
-      // ---- G: vertical sums over W'(p), output -----------------------------
-      // Same lane layout as C: 4 R columns x 16 output rows per wave.
-      int nG = 0;
-      while (pv + nG < tv1) {
-        const int p = pv + nG;
-        if ((p + r < H - 1 ? p + r : H - 1) >= avail3) break;
-        ++nG;
-      }
-      for (int q0 = 0; q0 < nG; q0 += kChunk) {
-        const int q = lane & 15;
-        const int p = pv + q0 + q;
-        const bool rowok = q0 + q < nG;
-        const int hi2 = p + r < H - 1 ? p + r : H - 1;
-        const int lo2 = p - r > 0 ? p - r : 0;
-        const int hi_p = q == 0 ? hi2_c : (p - 1 + r < H - 1 ? p - 1 + r : H - 1);
-        const int lo_p = q == 0 ? lo2_c : (p - 1 - r > 0 ? p - 1 - r : 0);
-        const float rows = (float)(hi2 - lo2 + 1);
-        const int last = (nG - q0 < kChunk ? nG - q0 : kChunk) - 1;
-#pragma unroll
-        for (int j = 0; j < NC; ++j) {
-          const int ci = j * 64 + wave * 4 + (lane >> 4);
-          const bool colok = ci < tw;
-          float4 D = make_float4(0.f, 0.f, 0.f, 0.f);
-          float Dc = 0.f;
-          if (colok && rowok) {
-            for (int y = hi_p + 1; y <= hi2; ++y) {
-              const int sl = slot_of(y, lo2_base, sb3, ring);
-              D = f4add(D, ring3v[(size_t)sl * tw_cap + ci]);
-              Dc += (float)ring3c[(size_t)sl * tw_cap + ci];
-            }
-            for (int y = lo_p; y < lo2; ++y) {
-              const int sl = slot_of(y, lo2_base, sb3, ring);
-              D = f4sub(D, ring3v[(size_t)sl * tw_cap + ci]);
-              Dc -= (float)ring3c[(size_t)sl * tw_cap + ci];
-            }
-          }
-          D.x = row_scan16(D.x);
-          D.y = row_scan16(D.y);
-          D.z = row_scan16(D.z);
-          D.w = row_scan16(D.w);
-          Dc = row_scan16(Dc);
-          if (colok && rowok) {
-            const float4 V2 = f4add(car2v[ci], D);
-            const float V2c = car2c[ci] + Dc;
-            const int x = tu0 + ci;
-            const int cx0 = x - r > 0 ? x - r : 0, cx1 = x + r < W - 1 ? x + r : W - 1;
-            const float np = (float)(cx1 - cx0 + 1) * rows;
-            float phi = 0.f;
-            if (V2c != 0.f) {
-              const float4 L = q0 == 0 ? lp[j] : left4T[(size_t)x * H + p];
-              phi = (V2.x * (L.x * inv255) + V2.y * (L.y * inv255) + V2.z * (L.z * inv255) + V2.w) / np;
-            }
-            out[out_off + (long long)(p - rv0) * rw + (x - ru0)] = phi + P.rho_max;
-            if (q == last) {
-              car2v[ci] = V2;
-              car2c[ci] = V2c;
-            }
-          }
-        }
-        if (q0 + kChunk < nG) {  // a later batch starts from this batch's last row
-          const int pl = pv + q0 + last;
-          hi2_c = pl + r < H - 1 ? pl + r : H - 1;
-          lo2_c = pl - r > 0 ? pl - r : 0;
-        }
-      }
-      if (nG > 0) {
-        const int p = pv + nG - 1;
-        const int new_lo2 = p - r > 0 ? p - r : 0;
-        // (the ring base moves only here: batches above address rows from the old base)
-        sb3 = slot_of(new_lo2, lo2_base, sb3, ring);
-        lo2_base = new_lo2;
-        lo2_c = new_lo2;
-        hi2_c = p + r < H - 1 ? p + r : H - 1;
-        pv += nG;
-      }
-      load_left(pv);
-      kv_e = e_first + e_rows;  // rows E wrote this step become visible next step
-      e_first = emitted_first;
-      e_rows = nC;
-      pc ^= 1;
+    if (nG > 0) {
+      const int p = pv + nG - 1;
+      const int new_lo2 = p - r > yp0 ? p - r : yp0;
+      sb3 = slot_of(new_lo2, lo2_base, sb3, ring);
+      lo2_base = new_lo2;
+      pv += nG;
     }
+    kv_e = e_first + e_rows;  // rows E wrote this step become visible next step
+    e_first = emitted_first;
+    e_rows = nC;
+    pc ^= 1;
     produced += nA;
+  };
+
+  if (wave < kWaves / 2) {
+    // ======== waves 0-7: stage A, M rows 2w and 2w+1 of each step ========
+    const int w2 = 2 * wave;
+    RowTaps<NSEG> taps;
+    load_rows2<NSEG>(taps, produced + w2, xm0, wM, W, H, la, lb, lc, lane, left4, right4);
     lds_barrier();
+    while (!finished()) {
+      count_rows();
+      if (w2 < nA) {
+        // raw cost of the pair's pixels -> scan rows 2w, 2w+1 (private to this wave)
+#pragma unroll
+        for (int s = 0; s < NSEG; ++s) {
+          const int t = s * 64 + lane;
+          const int h = t >= wM ? 1 : 0;
+          const int xi = t - h * wM;
+          // out-of-view samples cost rho_max: rho' = 0
+          const float tt = taps.t[s];
+          const float4 L = taps.L[s], R0 = taps.R0[s], R1 = taps.R1[s];
+          const float col = fabsf(L.x - fmaf(tt, R1.x - R0.x, R0.x)) + fabsf(L.y - fmaf(tt, R1.y - R0.y, R0.y)) +
+                            fabsf(L.z - fmaf(tt, R1.z - R0.z, R0.z));
+          const float gr = fabsf(L.w - fmaf(tt, R1.w - R0.w, R0.w));
+          const float rp0 = P.oma * (fminf(col, P.tc) - P.tc) + P.al * (fminf(gr, P.tg) - P.tg);
+          const float rp = taps.ok[s] ? rp0 : 0.f;
+          const float q = rp * inv255;
+          const float4 val = make_float4(rp, q * L.x, q * L.y, q * L.z);
+          const float nz = rp != 0.f ? 1.f : 0.f;
+          if (xi < wM) {
+            const size_t o = (size_t)(w2 + h) * ws_cap + xi;
+            scanv[o] = val;
+            scanc[o] = nz;
+          }
+        }
+        // next step's image taps, in flight from here
+        if (produced + nA < ym1)
+          load_rows2<NSEG>(taps, produced + nA + w2, xm0, wM, W, H, la, lb, lc, lane, left4, right4);
+        // in-place prefix along each row: lane (h, l) runs over columns
+        // NSEG*l .. NSEG*l + NSEG-1 of row 2w+h (serial prefix of the run,
+        // scan of the run totals over the 32 lanes of the row, offset added)
+        {
+          const int h = lane >> 5, l = lane & 31;
+          float4* rv = scanv + (size_t)(w2 + h) * ws_cap;
+          float* rc = scanc + (size_t)(w2 + h) * ws_cap;
+          float4 v[NSEG];
+          float n[NSEG];
+#pragma unroll
+          for (int i = 0; i < NSEG; ++i) {
+            const int c = l * NSEG + i;
+            v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            n[i] = 0.f;
+            if (c < wM) { v[i] = rv[c]; n[i] = rc[c]; }
+          }
+#pragma unroll
+          for (int i = 1; i < NSEG; ++i) { v[i] = f4add(v[i - 1], v[i]); n[i] = n[i - 1] + n[i]; }
+          const float4 tot = v[NSEG - 1];
+          const float nt = n[NSEG - 1];
+          const float4 ex = make_float4(half_scan(tot.x) - tot.x, half_scan(tot.y) - tot.y, half_scan(tot.z) - tot.z,
+                                        half_scan(tot.w) - tot.w);
+          const float exn = half_scan(nt) - nt;
+#pragma unroll
+          for (int i = 0; i < NSEG; ++i) {
+            const int c = l * NSEG + i;
+            if (c < wM) { rv[c] = f4add(v[i], ex); rc[c] = n[i] + exn; }
+          }
+        }
+        // window sums at the R+ columns of both rows (pixel t of the pair's R+ rows)
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+          const int t = m * 64 + lane;
+          const int h = t >= wP ? 1 : 0;
+          const int xi = t - h * wP;
+          if (xi < wP && w2 + h < nA) {
+            const float4* rv = scanv + (size_t)(w2 + h) * ws_cap;
+            const float* rc = scanc + (size_t)(w2 + h) * ws_cap;
+            const int x = xp0 + xi;
+            const int lo = (x - r > 0 ? x - r : 0) - xm0;
+            const int hi = (x + r < W - 1 ? x + r : W - 1) - xm0;
+            const int lm = lo > 0 ? lo - 1 : 0;
+            const float4 a = rv[hi], b = rv[lm];
+            const float ac = rc[hi], bc = rc[lm];
+            float4 hs = lo > 0 ? f4sub(a, b) : a;
+            const float hc = lo > 0 ? ac - bc : ac;
+            if (hc == 0.f) hs = make_float4(0.f, 0.f, 0.f, 0.f);
+            const int slot = slot_of(produced + w2 + h, lo_c, sb1, ring);
+            ring1v[(size_t)slot * wp_cap + xi] = hs;
+            ring1c[(size_t)slot * wp_cap + xi] = (uint8_t)hc;
+          }
+        }
+      }
+      if (MODE != 1) {
+        // ---- E: horizontal sums of (a, b) at the R columns ----------------
+        // Rows 2e and 2e+1 of the previous step's coefficient rows: in-place
+        // prefix as in A, then window sums at the R columns -> ring3.
+        const int e = wave;
+        if (2 * e < e_rows) {
+          {
+            const int h = lane >> 5, l = lane & 31;
+            float4* cv = coefv + ((size_t)(pc ^ 1) * kChunk + 2 * e + h) * wp_cap;
+            uint8_t* cc = coefc + ((size_t)(pc ^ 1) * kChunk + 2 * e + h) * wp_cap;
+            float4 v[NC];
+            float n[NC];
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+              const int c = l * NC + i;
+              v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+              n[i] = 0.f;
+              if (c < wP) { v[i] = cv[c]; n[i] = (float)cc[c]; }
+            }
+#pragma unroll
+            for (int i = 1; i < NC; ++i) { v[i] = f4add(v[i - 1], v[i]); n[i] = n[i - 1] + n[i]; }
+            const float4 tot = v[NC - 1];
+            const float nt = n[NC - 1];
+            const float4 ex = make_float4(half_scan(tot.x) - tot.x, half_scan(tot.y) - tot.y,
+                                          half_scan(tot.z) - tot.z, half_scan(tot.w) - tot.w);
+            const float exn = half_scan(nt) - nt;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+              const int c = l * NC + i;
+              // prefix counts stay below 256: an R+ row is at most kMaxWP wide
+              if (c < wP) { cv[c] = f4add(v[i], ex); cc[c] = (uint8_t)(n[i] + exn); }
+            }
+          }
+#pragma unroll
+          for (int m = 0; m < NC; ++m) {
+            const int t = m * 64 + lane;
+            const int h = t >= tw ? 1 : 0;
+            const int xi = t - h * tw;
+            if (xi < tw && 2 * e + h < e_rows) {
+              const float4* cv = coefv + ((size_t)(pc ^ 1) * kChunk + 2 * e + h) * wp_cap;
+              const uint8_t* cc = coefc + ((size_t)(pc ^ 1) * kChunk + 2 * e + h) * wp_cap;
+              const int x = tu0 + xi;
+              const int lo = (x - r > 0 ? x - r : 0) - xp0;
+              const int hi = (x + r < W - 1 ? x + r : W - 1) - xp0;
+              const int lm = lo > 0 ? lo - 1 : 0;
+              const float4 a = cv[hi], b = cv[lm];
+              const float ac = (float)cc[hi], bc = (float)cc[lm];
+              float4 hs = lo > 0 ? f4sub(a, b) : a;
+              const float hc = lo > 0 ? ac - bc : ac;
+              if (hc == 0.f) hs = make_float4(0.f, 0.f, 0.f, 0.f);
+              const int slot = slot_of(e_first + 2 * e + h, lo2_base, sb3, ring);
+              ring3v[(size_t)slot * tw_cap + xi] = hs;
+              ring3c[(size_t)slot * tw_cap + xi] = (uint8_t)hc;
+            }
+          }
+        }
+      }
+      advance();
+      lds_barrier();
+    }
+  } else {
+    // ======== waves 8-15: stages C, E and G ========
+    // C and G lanes: column j*32 + 4*cw + lane/16, row lane%16 of the step.
+    const int cw = wave - kWaves / 2;
+    const int q16 = lane & 15;
+    int cl[NC];
+    float ncC[NC], ncG[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      cl[j] = j * 32 + cw * 4 + (lane >> 4);
+      const int x1 = xp0 + cl[j], x2 = tu0 + cl[j];
+      ncC[j] = (float)((x1 + r < W - 1 ? x1 + r : W - 1) - (x1 - r > 0 ? x1 - r : 0) + 1);
+      ncG[j] = (float)((x2 + r < W - 1 ? x2 + r : W - 1) - (x2 - r > 0 ? x2 - r : 0) + 1);
+    }
+    // guide statistics, column-major: a lane group reads 16 consecutive rows
+    const float4* g0 = reinterpret_cast<const float4*>(guide);
+    const float4* g1 = g0 + hw;
+    const float* g2 = reinterpret_cast<const float*>(g1 + hw);
+    float gs[NC][9];
+    auto load_guide = [&](int kbase) {
+      const int k = kbase + q16;
+      const int kc = k < yp1 - 1 ? k : yp1 - 1;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const int ci = cl[j];
+        const size_t gi = (size_t)(xp0 + (ci < wP - 1 ? ci : wP - 1)) * H + kc;
+        const float4 a = g0[gi], b = g1[gi];
+        gs[j][0] = a.x; gs[j][1] = a.y; gs[j][2] = a.z; gs[j][3] = a.w;
+        gs[j][4] = b.x; gs[j][5] = b.y; gs[j][6] = b.z; gs[j][7] = b.w;
+        gs[j][8] = g2[gi];
+      }
+    };
+    float4 lp[NC];
+    auto load_left = [&](int pbase) {
+      const int p = pbase + q16;
+      const int pc_ = p < tv1 - 1 ? p : tv1 - 1;
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        const int ci = cl[j];
+        lp[j] = left4T[(size_t)(tu0 + (ci < tw - 1 ? ci : tw - 1)) * H + pc_];
+      }
+    };
+    load_guide(kv);
+    if (MODE != 1) load_left(pv);
+    lds_barrier();
+    while (!finished()) {
+      count_rows();
+
+      // ---- C: vertical sums over W'_k, linear coefficients ---------------
+      // Row k's window differs from row k-1's by at most one entering row
+      // (k+r) and one leaving row (k-r-1); a prefix over the 16 lanes of a
+      // column gives every row's sum from the carried sum of the previous
+      // step's last row.  Before the first row the carried sum is that of the
+      // (possibly virtual) row yp0-1, summed here by the 16 lanes of the column.
+      // The column groups j are independent; each phase below runs over all of
+      // them without per-lane branches so their latencies overlap.
+      if (nC > 0) {
+        const int k = kv + q16;
+        const bool rowok = q16 < nC;
+        const int ent = k + r, lev = k - r - 1;
+        const bool has_ent = rowok && ent <= H - 1, has_lev = rowok && lev >= ym0;
+        // slots of rows outside the window are never used; read slot 0 there
+        const int sl_ent = has_ent ? slot_of(ent, lo_c, sb1, ring) : 0;
+        const int sl_lev = has_lev ? slot_of(lev, lo_c, sb1, ring) : 0;
+        const float rows = (float)((k + r < H - 1 ? k + r : H - 1) - (k - r > 0 ? k - r : 0) + 1);
+        float4 V[NC], Cv[NC];
+        float Vc[NC], Cc[NC];
+        int cr[NC];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const bool colok = cl[j] < wP;
+          cr[j] = colok ? cl[j] : 0;
+          Cv[j] = car1v[cr[j]];  // carried sums (zero before the first rows)
+          Cc[j] = car1c[cr[j]];
+          const float4 ev = ring1v[(size_t)sl_ent * wp_cap + cr[j]], lv = ring1v[(size_t)sl_lev * wp_cap + cr[j]];
+          const float ec = (float)ring1c[(size_t)sl_ent * wp_cap + cr[j]];
+          const float lcn = (float)ring1c[(size_t)sl_lev * wp_cap + cr[j]];
+          const bool ue = colok && has_ent, ul = colok && has_lev;
+          V[j] = make_float4((ue ? ev.x : 0.f) - (ul ? lv.x : 0.f), (ue ? ev.y : 0.f) - (ul ? lv.y : 0.f),
+                             (ue ? ev.z : 0.f) - (ul ? lv.z : 0.f), (ue ? ev.w : 0.f) - (ul ? lv.w : 0.f));
+          Vc[j] = (ue ? ec : 0.f) - (ul ? lcn : 0.f);
+        }
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          V[j].x = row_scan16(V[j].x);
+          V[j].y = row_scan16(V[j].y);
+          V[j].z = row_scan16(V[j].z);
+          V[j].w = row_scan16(V[j].w);
+          Vc[j] = row_scan16(Vc[j]);
+        }
+        if (kv == yp0) {  // first rows of the tile (uniform branch)
+          const int i_lo = yp0 - 1 - r > ym0 ? yp0 - 1 - r : ym0;
+          const int i_hi = yp0 - 1 + r < H - 1 ? yp0 - 1 + r : H - 1;
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            float4 I = make_float4(0.f, 0.f, 0.f, 0.f);
+            float Ic = 0.f;
+            if (cl[j] < wP)
+              for (int y = i_lo + q16; y <= i_hi; y += 16) {
+                const int sl = slot_of(y, lo_c, sb1, ring);
+                I = f4add(I, ring1v[(size_t)sl * wp_cap + cl[j]]);
+                Ic += (float)ring1c[(size_t)sl * wp_cap + cl[j]];
+              }
+            I.x = row_last(row_scan16(I.x), lane);
+            I.y = row_last(row_scan16(I.y), lane);
+            I.z = row_last(row_scan16(I.z), lane);
+            I.w = row_last(row_scan16(I.w), lane);
+            Ic = row_last(row_scan16(Ic), lane);
+            V[j] = f4add(I, V[j]);
+            Vc[j] = Ic + Vc[j];
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            V[j] = f4add(Cv[j], V[j]);
+            Vc[j] = Cc[j] + Vc[j];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const float inv_n = __builtin_amdgcn_rcpf(ncC[j] * rows);
+          const float* g = gs[j];
+          const float m0 = V[j].x * inv_n;
+          const float c0 = V[j].y * inv_n - g[0] * m0;
+          const float c1 = V[j].z * inv_n - g[1] * m0;
+          const float c2 = V[j].w * inv_n - g[2] * m0;
+          const float a0 = g[3] * c0 + g[4] * c1 + g[5] * c2;
+          const float a1 = g[4] * c0 + g[6] * c1 + g[7] * c2;
+          const float a2 = g[5] * c0 + g[7] * c1 + g[8] * c2;
+          const float b = m0 - (a0 * g[0] + a1 * g[1] + a2 * g[2]);
+          // a window without a nonzero sample has zero coefficients exactly
+          const bool nz = Vc[j] != 0.f;
+          const float4 coef = make_float4(nz ? a0 : 0.f, nz ? a1 : 0.f, nz ? a2 : 0.f, nz ? b : 0.f);
+          if (cl[j] < wP && rowok) {
+            const int ci = cl[j];
+            if (MODE == 1) {
+              const int x = xp0 + ci;
+              if (x >= own_u0 && x < own_u1 && k >= own_v0 && k < own_v1) {
+                // coefficients of rho itself: a is unchanged by the shift, b gains rho_max
+                float* o = out + (out_off + (long long)(k - rv0) * rw + (x - ru0)) * 4;
+                o[0] = coef.x; o[1] = coef.y; o[2] = coef.z; o[3] = coef.w + P.rho_max;
+              }
+            } else {
+              coefv[((size_t)pc * kChunk + q16) * wp_cap + ci] = coef;
+              coefc[((size_t)pc * kChunk + q16) * wp_cap + ci] = nz ? 1 : 0;
+            }
+            // the carried sum of a column is read and written by its own wave only
+            if (q16 == nC - 1) {
+              car1v[ci] = V[j];
+              car1c[ci] = Vc[j];
+            }
+          }
+        }
+      }
+      load_guide(kv + nC);
+
+      if (MODE != 1) {
+        // ---- G: vertical sums over W'(p), output ---------------------------
+        // Same lane layout and update rule as C, over the R+ rows in ring3.
+        for (int q0 = 0; q0 < nG; q0 += kChunk) {
+          if (q0 > 0) load_left(pv + q0);  // (rows were prefetched for the first batch only)
+          const int p = pv + q0 + q16;
+          const bool rowok = q0 + q16 < nG;
+          const int ent = p + r, lev = p - r - 1;
+          const bool has_ent = rowok && ent <= H - 1, has_lev = rowok && lev >= yp0;
+          const int sl_ent = has_ent ? slot_of(ent, lo2_base, sb3, ring) : 0;
+          const int sl_lev = has_lev ? slot_of(lev, lo2_base, sb3, ring) : 0;
+          const float rows = (float)((p + r < H - 1 ? p + r : H - 1) - (p - r > 0 ? p - r : 0) + 1);
+          const int last = (nG - q0 < kChunk ? nG - q0 : kChunk) - 1;
+          float4 V2[NC], Cv[NC];
+          float V2c[NC], Cc[NC];
+          int cr[NC];
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            const bool colok = cl[j] < tw;
+            cr[j] = colok ? cl[j] : 0;
+            Cv[j] = car2v[cr[j]];  // carried sums (zero before the first rows)
+            Cc[j] = car2c[cr[j]];
+            const float4 ev = ring3v[(size_t)sl_ent * tw_cap + cr[j]], lv = ring3v[(size_t)sl_lev * tw_cap + cr[j]];
+            const float ec = (float)ring3c[(size_t)sl_ent * tw_cap + cr[j]];
+            const float lcn = (float)ring3c[(size_t)sl_lev * tw_cap + cr[j]];
+            const bool ue = colok && has_ent, ul = colok && has_lev;
+            V2[j] = make_float4((ue ? ev.x : 0.f) - (ul ? lv.x : 0.f), (ue ? ev.y : 0.f) - (ul ? lv.y : 0.f),
+                                (ue ? ev.z : 0.f) - (ul ? lv.z : 0.f), (ue ? ev.w : 0.f) - (ul ? lv.w : 0.f));
+            V2c[j] = (ue ? ec : 0.f) - (ul ? lcn : 0.f);
+          }
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            V2[j].x = row_scan16(V2[j].x);
+            V2[j].y = row_scan16(V2[j].y);
+            V2[j].z = row_scan16(V2[j].z);
+            V2[j].w = row_scan16(V2[j].w);
+            V2c[j] = row_scan16(V2c[j]);
+          }
+          if (pv + q0 == tv0) {  // first rows of the tile (uniform branch)
+            const int i_lo = tv0 - 1 - r > yp0 ? tv0 - 1 - r : yp0;
+            const int i_hi = tv0 - 1 + r < H - 1 ? tv0 - 1 + r : H - 1;
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+              float4 I = make_float4(0.f, 0.f, 0.f, 0.f);
+              float Ic = 0.f;
+              if (cl[j] < tw)
+                for (int y = i_lo + q16; y <= i_hi; y += 16) {
+                  const int sl = slot_of(y, lo2_base, sb3, ring);
+                  I = f4add(I, ring3v[(size_t)sl * tw_cap + cl[j]]);
+                  Ic += (float)ring3c[(size_t)sl * tw_cap + cl[j]];
+                }
+              I.x = row_last(row_scan16(I.x), lane);
+              I.y = row_last(row_scan16(I.y), lane);
+              I.z = row_last(row_scan16(I.z), lane);
+              I.w = row_last(row_scan16(I.w), lane);
+              Ic = row_last(row_scan16(Ic), lane);
+              V2[j] = f4add(I, V2[j]);
+              V2c[j] = Ic + V2c[j];
+            }
+          } else {
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+              V2[j] = f4add(Cv[j], V2[j]);
+              V2c[j] = Cc[j] + V2c[j];
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            const float4 L = lp[j];
+            const float phi = (V2[j].x * (L.x * inv255) + V2[j].y * (L.y * inv255) + V2[j].z * (L.z * inv255) +
+                               V2[j].w) * __builtin_amdgcn_rcpf(ncG[j] * rows);
+            if (cl[j] < tw && rowok) {
+              const int ci = cl[j];
+              const int x = tu0 + ci;
+              // a window without a nonzero coefficient row costs rho_max exactly
+              out[out_off + (long long)(p - rv0) * rw + (x - ru0)] = (V2c[j] != 0.f ? phi : 0.f) + P.rho_max;
+              if (q16 == last) {
+                car2v[ci] = V2[j];
+                car2c[ci] = V2c[j];
+              }
+            }
+          }
+        }
+        load_left(pv + nG);
+      }
+      advance();
+      lds_barrier();
+    }
   }
 }
 
@@ -635,12 +753,22 @@ LEXP_UNARY_INST(0, 2, 1)
 LEXP_UNARY_INST(0, 2, 2)
 LEXP_UNARY_INST(0, 3, 1)
 LEXP_UNARY_INST(0, 3, 2)
-LEXP_UNARY_INST(1, 3, 2)
+LEXP_UNARY_INST(0, 3, 3)
+LEXP_UNARY_INST(0, 4, 1)
+LEXP_UNARY_INST(0, 4, 2)
+LEXP_UNARY_INST(0, 4, 3)
+LEXP_UNARY_INST(0, 4, 4)
 LEXP_UNARY_INST(2, 1, 1)
 LEXP_UNARY_INST(2, 2, 1)
 LEXP_UNARY_INST(2, 2, 2)
 LEXP_UNARY_INST(2, 3, 1)
 LEXP_UNARY_INST(2, 3, 2)
+LEXP_UNARY_INST(2, 3, 3)
+LEXP_UNARY_INST(2, 4, 1)
+LEXP_UNARY_INST(2, 4, 2)
+LEXP_UNARY_INST(2, 4, 3)
+LEXP_UNARY_INST(2, 4, 4)
+LEXP_UNARY_INST(1, 4, 4)
 #undef LEXP_UNARY_INST
 
 // ---------------------------------------------------------------------------
