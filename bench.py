@@ -235,6 +235,9 @@ def main():
         "host_threads": len(os.sched_getaffinity(0)), "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
         "host_cut_ms_per_step": g["stats"]["host_cut_ms"],
         "host_wait_ms_per_step": g["stats"]["host_wait_ms"],
+        "host_enqueue_ms_per_step": g["stats"]["host_enqueue_ms"],
+        "host_update_ms_per_step": g["stats"]["host_update_ms"],
+        "host_cut_level_ms_per_step": [round(x, 2) for x in g["stats"]["host_cut_level_ms"]],
     }
     print(json.dumps(out), flush=True)
 

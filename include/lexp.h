@@ -63,6 +63,11 @@ typedef struct {
  *                              epsilon and contrast gamma, Eqs. (5),(10),(11)
  *   neighbours               : 8 or 4
  *   host_threads             : threads of the host min-cut pool (0 = all cores, at most 64)
+ *   device_cut               : lexp_optimize: 1 = minimum cuts of the expansion
+ *                              moves by the device push-relabel kernel, any region
+ *                              it leaves unfinished is cut on the host; 0 = every
+ *                              cut on the host (Boykov-Kolmogorov).  Both return the
+ *                              same cut (the minimiser with the fewest ones).
  */
 typedef struct {
   int32_t width, height;
@@ -73,6 +78,7 @@ typedef struct {
   double lambda, tau_dis, w_floor, gamma;
   int32_t neighbours;
   int32_t host_threads;
+  int32_t device_cut;
 } lexp_params;
 
 /* Grid levels of the optimisation procedure (Alg. 2): cell size in pixels and
@@ -93,8 +99,13 @@ typedef struct {
   double unary_kernel_ms;   /* sum of kernel durations (HIP events on the launch stream) */
   double unary_alg_bytes;   /* algorithmic bytes: sum over items of 16|M| + 16|M| + 36|R+| + 4|R| */
   int64_t expand_calls;     /* group steps (one batch of disjoint expansions) */
-  double host_cut_ms;       /* host max-flow time (wall, summed over steps) */
+  double host_cut_ms;       /* host max-flow time, or with the device cut the host time after
+                               the cut (label mirror, candidates), wall, summed over steps */
   double host_wait_ms;      /* time the host waited for device terms */
+  double host_enqueue_ms;   /* lexp_optimize: host time queueing device work (copies, launches) */
+  double host_update_ms;    /* lexp_optimize: host time queueing label updates after the cuts */
+  double host_cut_level_ms[4]; /* lexp_optimize: host_cut_ms by grid level */
+  int64_t device_cut_fallbacks; /* lexp_optimize: regions the device max-flow left to the host */
 } lexp_stats;
 
 /* Creates a context for one stereo pair and runs the label-independent set-up
@@ -198,6 +209,18 @@ lexp_status lexp_reset_stats(lexp_ctx* ctx);
  * float64 (w_pq for the forward neighbours, 0 outside the image). */
 lexp_status lexp_debug_guide(lexp_ctx* ctx, float* left4, float* right4, float* guide, double* weights,
                              void* hip_stream);
+
+/* Exact minimisation on the device (the push-relabel kernel lexp_optimize
+ * uses) of n binary problems of the form lexp_solve_binary takes, on grids
+ * dims[2i] x dims[2i+1] (width, height), with the context's neighbourhood.
+ * terms: host, per problem w*h nodes of 5 int32 (U, then w_0..w_3 for the
+ * forward neighbours (1,0), (0,1), (1,1), (-1,1); |U| <= 2^30, 0 <= w_d <= 2^30,
+ * w_d = 0 where the neighbour is outside the grid), problems back to back.
+ * x: host, per problem w*h bytes (x = 1: the minimiser with the fewest ones).
+ * status[i] = 1 where the kernel finished problem i, 0 where it stopped at its
+ * round limit (x of that problem is then undefined).  Synchronises hip_stream. */
+lexp_status lexp_solve_binary_device(lexp_ctx* ctx, int32_t n, const int32_t* dims, const int32_t* terms, uint8_t* x,
+                                     int32_t* status, void* hip_stream);
 
 /* ---- host-side pieces, usable without a device ---------------------------- */
 

@@ -113,6 +113,8 @@ struct lexp_ctx {
   DevBuf<int> d_flag;
   DevBuf<double> d_partial;
   DevBuf<float4> d_labels_tmp;
+  DevBuf<int> d_status;
+  PinBuf<int> h_status;
   PinBuf<Item> h_items;
   PinBuf<Tile> h_tiles;
   PinBuf<int> h_terms;
@@ -130,18 +132,25 @@ struct lexp_ctx {
   std::vector<Pending> ev_pending;
   // two halves of a group step in flight at once (host cuts one half while
   // the device evaluates the other)
+  // Buffers of one part of a group in flight in lexp_optimize.  terms[0] is
+  // the overflow flag of the graph terms (cleared once per run, never reset by
+  // a step), the terms of the part follow from terms[1].  With the device cut
+  // the result buffer holds the flag, a status per region and the cut
+  // (x, one byte per pixel), and one copy brings them to the host; on the host
+  // path one copy brings the flag and the terms.
   struct PartBuf {
     DevBuf<Item> d_items;
     DevBuf<float> d_phi;
     DevBuf<int> d_terms;
     DevBuf<uint8_t> d_x;
-    DevBuf<int> d_flag;
+    DevBuf<unsigned char> d_res;
     PinBuf<Item> h_items;
     PinBuf<int> h_terms;
     PinBuf<uint8_t> h_x;
-    PinBuf<int> h_flag;
+    PinBuf<unsigned char> h_res;
     hipEvent_t ready = nullptr;
   } part[2];
+  size_t res_items = 0;  // status slots in the result buffers
 };
 
 namespace {
@@ -326,6 +335,39 @@ lexp_status launch_unary(lexp_ctx* c, const Item* d_items, const Tile* d_tiles, 
     c->stats.unary_evals += evals;
     c->stats.unary_items += n_items;
   }
+  return LEXP_OK;
+}
+
+// Rounds the device max-flow may take per region node before it leaves the
+// region to the host (the kernel adds 256); converged regions need far fewer.
+constexpr int kCutRoundFactor = 4;
+
+// Push-relabel rounds between global relabels: a global relabel costs about
+// one workgroup barrier per breadth-first level (up to the region's diameter),
+// a round two.
+int cut_relabel_every(int max_px) {
+  return max_px <= 512 ? 8 : 16;
+}
+
+// Whether the device max-flow holds a region of px nodes (its arrays live in LDS).
+bool cut_fits(const lexp_ctx* c, int64_t px) { return px * lexp::kCutBytesPerNode <= (int64_t)c->lds_limit; }
+
+// Device minimum cuts of n regions whose terms start at the items' aux_off;
+// x at the same offsets, one status per item.  Every region must fit.
+lexp_status launch_cut(lexp_ctx* c, const Item* d_items, int n, const int* d_terms, uint8_t* d_x, int* d_status,
+                       int max_px, hipStream_t s) {
+  if (n <= 0) return LEXP_OK;
+  if (!cut_fits(c, max_px)) return fail(LEXP_ESTATE, "region of %d pixels too large for the device max-flow", max_px);
+  const int nf = c->dp.nf;
+  const size_t lds = (size_t)max_px * lexp::kCutBytesPerNode;
+  const int every = cut_relabel_every(max_px);
+  if (max_px <= 512)
+    hipLaunchKernelGGL(lexp::k_cut_lds<256>, dim3(n), dim3(256), lds, s, d_items, d_terms, nf, d_x, d_status, max_px,
+                       kCutRoundFactor, every);
+  else
+    hipLaunchKernelGGL(lexp::k_cut_lds<1024>, dim3(n), dim3(1024), lds, s, d_items, d_terms, nf, d_x, d_status, max_px,
+                       kCutRoundFactor, every);
+  HIP_TRY(hipGetLastError());
   return LEXP_OK;
 }
 
@@ -557,6 +599,7 @@ lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const 
   if (p.lambda * p.tau_dis > 64.0 || p.tau_col > 1e4 || p.tau_grad > 1e4)
     return fail(LEXP_EINVAL, "lambda*tau_dis or truncations too large for 32-bit binary terms");
   if (p.host_threads < 0 || p.host_threads > 64) return fail(LEXP_EINVAL, "host_threads outside [0, 64]");
+  if (p.device_cut != 0 && p.device_cut != 1) return fail(LEXP_EINVAL, "device_cut must be 0 or 1");
   hipStream_t s = (hipStream_t)hip_stream;
   std::unique_ptr<lexp_ctx> c(new lexp_ctx());
   c->prm = p;
@@ -622,11 +665,12 @@ lexp_status lexp_destroy(lexp_ctx* c) {
   (void)hipFree(c->wts);
   c->d_items.release(); c->d_tiles.release(); c->d_phi.release(); c->d_terms.release(); c->d_x.release();
   c->d_flag.release(); c->d_partial.release(); c->d_labels_tmp.release();
+  c->d_status.release(); c->h_status.release();
   c->h_items.release(); c->h_tiles.release(); c->h_terms.release(); c->h_x.release(); c->h_flag.release();
   c->h_partial.release(); c->h_labels4.release();
   for (auto& b : c->part) {
-    b.d_items.release(); b.d_phi.release(); b.d_terms.release(); b.d_x.release(); b.d_flag.release();
-    b.h_items.release(); b.h_terms.release(); b.h_x.release(); b.h_flag.release();
+    b.d_items.release(); b.d_phi.release(); b.d_terms.release(); b.d_x.release(); b.d_res.release();
+    b.h_items.release(); b.h_terms.release(); b.h_x.release(); b.h_res.release();
     if (b.ready) (void)hipEventDestroy(b.ready);
   }
   delete c;
@@ -792,6 +836,7 @@ struct Part {
   size_t tile_off = 0, n_tiles = 0;
   TileCaps caps;
   double bytes = 0.0;
+  bool device_cut = false;  // minimum cuts by the device max-flow
 };
 
 struct StepArgs {
@@ -801,66 +846,119 @@ struct StepArgs {
   const float* mirror;
 };
 
-// Proposals of one step for a part, then its cost kernel, graph terms and the
-// copy of the terms to the host, all queued on the stream.
-lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const Tile* d_tiles, const StepArgs& a,
-                         int step, const float* labels, const float* cur_cost, hipStream_t s) {
+// Alg. 1 candidate of region q of a part for a step, into its item.
+void propose_item(const lexp_ctx* c, Part& P, const StepArgs& a, int q, int step) {
+  float al[3];
+  lexp::propose(c->W, c->H, a.mirror, 3, a.seed, a.it, a.level, a.cell, P.ci[q], P.cj[q], step, a.kp, a.r_d, a.r_n,
+                al);
+  P.items[q].a = al[0];
+  P.items[q].b = al[1];
+  P.items[q].c = al[2];
+}
+
+// A part's items (with their candidates already proposed), cost kernel, graph
+// terms and the copy of the terms to the host, all queued on the stream.
+lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const Tile* d_tiles, const float* labels,
+                         const float* cur_cost, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
   const int n = (int)P.items.size();
-  c->pool->parallel_for(n, [&](int q, int) {
-    float al[3];
-    lexp::propose(c->W, c->H, a.mirror, 3, a.seed, a.it, a.level, a.cell, P.ci[q], P.cj[q], step, a.kp, a.r_d, a.r_n,
-                  al);
-    P.items[q].a = al[0];
-    P.items[q].b = al[1];
-    P.items[q].c = al[2];
-  });
   std::copy(P.items.begin(), P.items.end(), B.h_items.p);
   HIP_TRY(hipMemcpyAsync(B.d_items.p, B.h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
   lexp_status st = launch_unary<0>(c, B.d_items.p, d_tiles + P.tile_off, (int)P.n_tiles, P.caps, nullptr, B.d_phi.p, s,
                                    P.bytes, P.n_px, n);
   if (st) return st;
-  HIP_TRY(hipMemsetAsync(B.d_flag.p, 0, sizeof(int), s));
-  hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, c->dp, B.d_items.p,
-                     (const float4*)labels, cur_cost, B.d_phi.p, c->wts, B.d_terms.p, B.d_flag.p);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(B.h_terms.p, B.d_terms.p, sizeof(int) * 5 * P.n_px, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(B.h_flag.p, B.d_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  if (P.device_cut) {
+    int* flag = reinterpret_cast<int*>(B.d_res.p);
+    hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, c->dp, B.d_items.p,
+                       (const float4*)labels, cur_cost, B.d_phi.p, c->wts, B.d_terms.p + 1, flag);
+    HIP_TRY(hipGetLastError());
+    if ((st = launch_cut(c, B.d_items.p, n, B.d_terms.p + 1, B.d_res.p + 4 + 4 * c->res_items, flag + 1, P.max_px, s)))
+      return st;
+    HIP_TRY(hipMemcpyAsync(B.h_res.p, B.d_res.p, 4 + 4 * c->res_items + (size_t)P.n_px, hipMemcpyDeviceToHost, s));
+  } else {
+    hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, c->dp, B.d_items.p,
+                       (const float4*)labels, cur_cost, B.d_phi.p, c->wts, B.d_terms.p + 1, B.d_terms.p);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(B.h_terms.p, B.d_terms.p, sizeof(int) * (1 + 5 * P.n_px), hipMemcpyDeviceToHost, s));
+  }
   HIP_TRY(hipEventRecord(B.ready, s));
+  c->stats.host_enqueue_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return LEXP_OK;
 }
 
-// Waits for a part's terms, solves its regions on the host pool, updates the
-// host label mirror and queues the label update on the device.
-lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, float* mirror, float* labels, float* cur_cost,
-                        hipStream_t s) {
+// Waits for a part's cut (device path) or terms (host path), completes the
+// cut on the host pool (every region on the host path; on the device path
+// only the regions the kernel left unfinished, whose terms are fetched then),
+// updates the host label mirror and queues the label update on the device.
+// With next_step >= 0, each worker then proposes its region's candidate for
+// that step: a candidate reads labels of the region's own centre cell only,
+// which no other region of the group changes (Lemma 3).
+lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepArgs& a, int next_step, float* mirror,
+                        float* labels, float* cur_cost, hipStream_t s) {
   const int n = (int)P.items.size();
+  const bool dev = P.device_cut;
   const auto t0 = std::chrono::steady_clock::now();
   HIP_TRY(hipEventSynchronize(B.ready));
   const auto t1 = std::chrono::steady_clock::now();
-  if (B.h_flag.p[0]) return fail(LEXP_EINVAL, "binary-problem term exceeds 2^30 quanta (parameters too large)");
+  const int flag = dev ? reinterpret_cast<const int*>(B.h_res.p)[0] : B.h_terms.p[0];
+  if (flag) return fail(LEXP_EINVAL, "binary-problem term exceeds 2^30 quanta (parameters too large)");
   const int nf = c->dp.nf;
-  c->pool->parallel_for(n, [&](int i, int worker) {
+  const int* terms = B.h_terms.p + 1;
+  uint8_t* xs = dev ? B.h_res.p + 4 + 4 * c->res_items : B.h_x.p;
+  uint8_t* d_xs = dev ? B.d_res.p + 4 + 4 * c->res_items : B.d_x.p;
+  std::vector<int> host_cut;  // device path: regions the kernel left to the host
+  if (dev) {
+    const int* status = reinterpret_cast<const int*>(B.h_res.p) + 1;
+    for (int i = 0; i < n; ++i)
+      if (!status[i]) host_cut.push_back(i);
+    for (int i : host_cut) {
+      const Item& it = P.items[i];
+      HIP_TRY(hipMemcpyAsync(B.h_terms.p + 1 + (size_t)it.aux_off * 5, B.d_terms.p + 1 + (size_t)it.aux_off * 5,
+                             sizeof(int) * 5 * (size_t)it.rw * it.rh, hipMemcpyDeviceToHost, s));
+    }
+    if (!host_cut.empty()) HIP_TRY(hipStreamSynchronize(s));
+    c->stats.device_cut_fallbacks += (int64_t)host_cut.size();
+  }
+  auto host_solve = [&](int i, int worker) {
     const Item& it = P.items[i];
-    if (it.rw <= 0 || it.rh <= 0) return;
-    const int* t = B.h_terms.p + (size_t)it.aux_off * 5;
-    uint8_t* x = B.h_x.p + it.aux_off;
+    const int* t = terms + (size_t)it.aux_off * 5;
     lexp::BKSolver& bk = *c->solvers[worker];
     bk.load<int32_t>(it.rw, it.rh, nf, t, 5, t + 1, 5);
-    bk.solve(x);
-    for (int q = 0; q < it.rw * it.rh; ++q) {
-      if (!x[q]) continue;
-      float* m = mirror + ((size_t)(it.rv0 + q / it.rw) * c->W + (it.ru0 + q % it.rw)) * 3;
-      m[0] = it.a; m[1] = it.b; m[2] = it.c;
+    bk.solve(xs + it.aux_off);
+  };
+  if (dev && !host_cut.empty())
+    c->pool->parallel_for((int)host_cut.size(), [&](int q, int worker) { host_solve(host_cut[q], worker); });
+  c->pool->parallel_for(n, [&](int i, int worker) {
+    const Item& it = P.items[i];
+    if (it.rw > 0 && it.rh > 0) {
+      if (!dev) host_solve(i, worker);
+      const uint8_t* x = xs + it.aux_off;
+      for (int q = 0; q < it.rw * it.rh; ++q) {
+        if (!x[q]) continue;
+        float* m = mirror + ((size_t)(it.rv0 + q / it.rw) * c->W + (it.ru0 + q % it.rw)) * 3;
+        m[0] = it.a; m[1] = it.b; m[2] = it.c;
+      }
     }
+    if (next_step >= 0) propose_item(c, P, a, i, next_step);
   });
   const auto t2 = std::chrono::steady_clock::now();
-  HIP_TRY(hipMemcpyAsync(B.d_x.p, B.h_x.p, (size_t)P.n_px, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(lexp::k_apply, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, c->W, B.d_items.p, B.d_x.p,
+  if (!dev) {
+    HIP_TRY(hipMemcpyAsync(B.d_x.p, B.h_x.p, (size_t)P.n_px, hipMemcpyHostToDevice, s));
+  } else {
+    for (int i : host_cut) {
+      const Item& it = P.items[i];
+      HIP_TRY(hipMemcpyAsync(d_xs + it.aux_off, xs + it.aux_off, (size_t)it.rw * it.rh, hipMemcpyHostToDevice, s));
+    }
+  }
+  hipLaunchKernelGGL(lexp::k_apply, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, c->W, B.d_items.p, d_xs,
                      B.d_phi.p, (float4*)labels, cur_cost);
   HIP_TRY(hipGetLastError());
+  const auto t3 = std::chrono::steady_clock::now();
   c->stats.expand_calls += 1;
   c->stats.host_wait_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
   c->stats.host_cut_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
+  c->stats.host_cut_level_ms[a.level] += std::chrono::duration<double, std::milli>(t2 - t1).count();
+  c->stats.host_update_ms += std::chrono::duration<double, std::milli>(t3 - t2).count();
   return LEXP_OK;
 }
 
@@ -880,8 +978,14 @@ extern "C" lexp_status lexp_optimize(lexp_ctx* c, const lexp_schedule* sch, uint
   lexp_status st = wait_staging(c);
   if (st) return st;
 
-  // Per (level, group, half): cells (Eq. (15): group 4 (j mod 4) + (i mod 4)),
-  // clipped 3x3-cell regions, compact offsets and tiles.
+  // Per (level, group, part): cells (Eq. (15): group 4 (j mod 4) + (i mod 4)),
+  // clipped 3x3-cell regions, compact offsets and tiles.  A group with more
+  // than four regions per host thread is split in two parts that overlap:
+  // one is cut while the device evaluates the other's next candidate, and
+  // with the device max-flow enabled (and regions that fit it) part 0 is cut
+  // on the device while the host cuts part 1.  Smaller groups are one part
+  // cut on the host, so that all threads cut at once.  Regions are ordered
+  // largest first for the host pool's dynamic schedule.
   std::vector<Part> parts((size_t)sch->n_levels * 16 * 2);
   std::vector<Tile> all_tiles;
   int64_t max_px = 1;
@@ -893,11 +997,29 @@ extern "C" lexp_status lexp_optimize(lexp_ctx* c, const lexp_schedule* sch, uint
       std::vector<std::pair<int, int>> cells;
       for (int j = k / 4; j < ncj; j += 4)
         for (int i = k % 4; i < nci; i += 4) cells.emplace_back(i, j);
-      const size_t half = (cells.size() + 1) / 2;
+      std::stable_sort(cells.begin(), cells.end(), [&](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+        auto area = [&](const std::pair<int, int>& q) {
+          lexp_rect rr{(q.first - 1) * cell, (q.second - 1) * cell, (q.first + 2) * cell, (q.second + 2) * cell};
+          int u0, v0, u1, v1;
+          clip_rect(c, rr, &u0, &v0, &u1, &v1);
+          return (int64_t)(u1 - u0) * (v1 - v0);
+        };
+        return area(x) > area(y);
+      });
+      int64_t max_area = 0;
+      for (const auto& q : cells) {
+        lexp_rect rr{(q.first - 1) * cell, (q.second - 1) * cell, (q.first + 2) * cell, (q.second + 2) * cell};
+        int u0, v0, u1, v1;
+        clip_rect(c, rr, &u0, &v0, &u1, &v1);
+        max_area = std::max<int64_t>(max_area, (int64_t)(u1 - u0) * (v1 - v0));
+      }
+      const bool split = cells.size() > (size_t)4 * c->pool->size();
+      const bool dev_part = split && c->prm.device_cut != 0 && cut_fits(c, max_area);
       for (int hp = 0; hp < 2; ++hp) {
         Part& P = parts[((size_t)h * 16 + k) * 2 + hp];
-        const size_t b0 = hp == 0 ? 0 : half, b1 = hp == 0 ? half : cells.size();
-        for (size_t q = b0; q < b1; ++q) {
+        P.device_cut = dev_part && hp == 0;
+        // split: alternate cells between the parts (both keep largest first)
+        for (size_t q = split ? (size_t)hp : 0; q < (split || hp == 0 ? cells.size() : 0); q += split ? 2 : 1) {
           const int i = cells[q].first, j = cells[q].second;
           lexp_rect rr{(i - 1) * cell, (j - 1) * cell, (i + 2) * cell, (j + 2) * cell};
           int u0, v0, u1, v1;
@@ -928,17 +1050,21 @@ extern "C" lexp_status lexp_optimize(lexp_ctx* c, const lexp_schedule* sch, uint
   std::copy(all_tiles.begin(), all_tiles.end(), c->h_tiles.p);
   if (!all_tiles.empty())
     HIP_TRY(hipMemcpyAsync(c->d_tiles.p, c->h_tiles.p, sizeof(Tile) * all_tiles.size(), hipMemcpyHostToDevice, s));
+  c->res_items = max_items;
+
   for (auto& B : c->part) {
     HIP_TRY(B.d_items.ensure(max_items));
     HIP_TRY(B.d_phi.ensure((size_t)max_px));
-    HIP_TRY(B.d_terms.ensure((size_t)max_px * 5));
+    HIP_TRY(B.d_terms.ensure(1 + (size_t)max_px * 5));
     HIP_TRY(B.d_x.ensure((size_t)max_px));
-    HIP_TRY(B.d_flag.ensure(1));
+    HIP_TRY(B.d_res.ensure(4 + 4 * max_items + (size_t)max_px));
     HIP_TRY(B.h_items.ensure(max_items));
-    HIP_TRY(B.h_terms.ensure((size_t)max_px * 5));
+    HIP_TRY(B.h_terms.ensure(1 + (size_t)max_px * 5));
     HIP_TRY(B.h_x.ensure((size_t)max_px));
-    HIP_TRY(B.h_flag.ensure(1));
+    HIP_TRY(B.h_res.ensure(4 + 4 * max_items + (size_t)max_px));
     if (!B.ready) HIP_TRY(hipEventCreateWithFlags(&B.ready, hipEventDisableTiming));
+    HIP_TRY(hipMemsetAsync(B.d_terms.p, 0, sizeof(int), s));  // overflow flags
+    HIP_TRY(hipMemsetAsync(B.d_res.p, 0, sizeof(int), s));
   }
 
   // Alg. 2 line 2: random initial labels and their per-pixel costs.
@@ -962,15 +1088,18 @@ extern "C" lexp_status lexp_optimize(lexp_ctx* c, const lexp_schedule* sch, uint
         // (Lemma 3), so the two halves run staggered: while the host cuts
         // one half, the device evaluates the other half's next candidate.
         for (int hp = 0; hp < 2; ++hp)
-          if (!P[hp]->items.empty() && K > 0)
-            if ((st = enqueue_part(c, *P[hp], c->part[hp], c->d_tiles.p, a, 0, labels, cur_cost, s))) return st;
+          if (!P[hp]->items.empty() && K > 0) {
+            Part& Q = *P[hp];
+            c->pool->parallel_for((int)Q.items.size(), [&](int q, int) { propose_item(c, Q, a, q, 0); });
+            if ((st = enqueue_part(c, Q, c->part[hp], c->d_tiles.p, labels, cur_cost, s))) return st;
+          }
         for (int step = 0; step < K; ++step)
           for (int hp = 0; hp < 2; ++hp) {
             if (P[hp]->items.empty()) continue;
-            if ((st = finish_part(c, *P[hp], c->part[hp], mirror.data(), labels, cur_cost, s))) return st;
-            if (step + 1 < K)
-              if ((st = enqueue_part(c, *P[hp], c->part[hp], c->d_tiles.p, a, step + 1, labels, cur_cost, s)))
-                return st;
+            const int next = step + 1 < K ? step + 1 : -1;
+            if ((st = finish_part(c, *P[hp], c->part[hp], a, next, mirror.data(), labels, cur_cost, s))) return st;
+            if (next >= 0)
+              if ((st = enqueue_part(c, *P[hp], c->part[hp], c->d_tiles.p, labels, cur_cost, s))) return st;
           }
       }
     }
@@ -1027,6 +1156,60 @@ lexp_status lexp_debug_guide(lexp_ctx* c, float* left4, float* right4, float* gu
 }
 
 // ---- host-side pieces ------------------------------------------------------
+lexp_status lexp_solve_binary_device(lexp_ctx* c, int32_t n, const int32_t* dims, const int32_t* terms, uint8_t* x,
+                                     int32_t* status, void* hip_stream) {
+  if (!c || n < 0) return fail(LEXP_EINVAL, "bad argument");
+  if (n == 0) return LEXP_OK;
+  if (!dims || !terms || !x || !status) return fail(LEXP_EINVAL, "null argument");
+  // problems whose arrays do not fit in LDS get status 0 and are not run
+  std::vector<Item> items;
+  std::vector<int> run;
+  int64_t tot = 0;
+  int max_px = 1;
+  for (int i = 0; i < n; ++i) {
+    const int w = dims[2 * i], h = dims[2 * i + 1];
+    if (w < 0 || h < 0 || (int64_t)w * h > (1 << 24)) return fail(LEXP_EINVAL, "bad grid size of problem %d", i);
+    status[i] = 0;
+    if (cut_fits(c, (int64_t)w * h)) {
+      Item it{};
+      it.rw = w; it.rh = h; it.aux_off = tot;
+      items.push_back(it);
+      run.push_back(i);
+      max_px = std::max(max_px, w * h);
+    }
+    tot += (int64_t)w * h;
+  }
+  const int64_t lim = (int64_t)1 << 30;
+  for (int64_t q = 0; q < tot; ++q) {
+    if (terms[q * 5] > lim || terms[q * 5] < -lim) return fail(LEXP_EINVAL, "unary term exceeds 2^30 in magnitude");
+    for (int d = 0; d < 4; ++d)
+      if (terms[q * 5 + 1 + d] < 0 || terms[q * 5 + 1 + d] > lim)
+        return fail(LEXP_EINVAL, "pairwise weight outside [0, 2^30]");
+  }
+  const int m = (int)items.size();
+  if (m == 0 || tot == 0) {
+    for (int i : run) status[i] = 1;
+    return LEXP_OK;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  lexp_status st = wait_staging(c);
+  if (st) return st;
+  HIP_TRY(c->d_items.ensure((size_t)m));
+  HIP_TRY(c->d_terms.ensure((size_t)tot * 5));
+  HIP_TRY(c->d_x.ensure((size_t)tot));
+  HIP_TRY(c->d_status.ensure((size_t)m));
+  HIP_TRY(c->h_status.ensure((size_t)m));
+  HIP_TRY(hipMemcpyAsync(c->d_items.p, items.data(), sizeof(Item) * m, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->d_terms.p, terms, sizeof(int) * 5 * tot, hipMemcpyHostToDevice, s));
+  if ((st = launch_cut(c, c->d_items.p, m, c->d_terms.p, c->d_x.p, c->d_status.p, max_px, s))) return st;
+  HIP_TRY(hipMemcpyAsync(x, c->d_x.p, (size_t)tot, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(c->h_status.p, c->d_status.p, sizeof(int) * m, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int k = 0; k < m; ++k) status[run[k]] = c->h_status.p[k];
+  HIP_TRY(hipEventRecord(c->staging_done, s));
+  return LEXP_OK;
+}
+
 lexp_status lexp_solve_binary(int32_t w, int32_t h, int32_t neighbours, const int64_t* U, const int64_t* w4,
                               uint8_t* x) {
   if (w < 0 || h < 0 || (neighbours != 4 && neighbours != 8)) return fail(LEXP_EINVAL, "bad grid");

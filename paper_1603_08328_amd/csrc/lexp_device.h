@@ -78,6 +78,10 @@ __global__ void k_apply(int W, const Item* items, const uint8_t* x, const float*
                         float* cur_cost);
 __global__ void k_energy(DevParams P, const float4* labels, const float* cur_cost, const double* wts,
                          double* partial);
+template <int BLOCK>
+__global__ void k_cut_lds(const Item* items, const int* terms, int nf, uint8_t* x, int* status, int max_nodes,
+                          int round_factor, int relabel_every);
+constexpr int kCutBytesPerNode = 52;  // device max-flow arrays per node (LDS)
 __global__ void k_pair1(DevParams P, const double* wts, int pu, int pv, int qu, int qv, float4 fp, float4 fq,
                         double* out);
 

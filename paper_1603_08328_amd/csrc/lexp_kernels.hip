@@ -7,6 +7,7 @@
 //   k_graph_terms                              : binary problem of one local
 //                                                expansion (Eq. 13, Lemma 2)
 //   k_apply, k_energy, k_pair1                 : label update, Eq. (5), Eq. (10)
+// (the device max-flow of the binary problems is in lexp_cut.hip)
 //
 // Built with -ffp-contract=off: products and sums are rounded as written and
 // fused multiply-adds appear only where fmaf() is called explicitly.
@@ -903,5 +904,6 @@ __global__ void k_pair1(DevParams P, const double* __restrict__ wts, int pu, int
   }
   out[0] = psi(P, w, fp, fq, pu, pv, qu, qv);
 }
+
 
 }  // namespace lexp

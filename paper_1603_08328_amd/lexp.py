@@ -31,7 +31,8 @@ class lexp_params(C.Structure):
                 ("alpha", C.c_double), ("tau_col", C.c_double), ("tau_grad", C.c_double),
                 ("gf_radius", C.c_int32), ("gf_eps", C.c_double),
                 ("lam", C.c_double), ("tau_dis", C.c_double), ("w_floor", C.c_double),
-                ("gamma", C.c_double), ("neighbours", C.c_int32), ("host_threads", C.c_int32)]
+                ("gamma", C.c_double), ("neighbours", C.c_int32), ("host_threads", C.c_int32),
+                ("device_cut", C.c_int32)]
 
 
 class lexp_plane(C.Structure):
@@ -50,10 +51,14 @@ class lexp_schedule(C.Structure):
 class lexp_stats(C.Structure):
     _fields_ = [("unary_launches", C.c_int64), ("unary_items", C.c_int64), ("unary_evals", C.c_int64),
                 ("unary_kernel_ms", C.c_double), ("unary_alg_bytes", C.c_double),
-                ("expand_calls", C.c_int64), ("host_cut_ms", C.c_double), ("host_wait_ms", C.c_double)]
+                ("expand_calls", C.c_int64), ("host_cut_ms", C.c_double), ("host_wait_ms", C.c_double),
+                ("host_enqueue_ms", C.c_double), ("host_update_ms", C.c_double),
+                ("host_cut_level_ms", C.c_double * 4), ("device_cut_fallbacks", C.c_int64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["host_cut_level_ms"] = list(d["host_cut_level_ms"])
+        return d
 
 
 # Every symbol the header declares, with (restype, argtypes).
@@ -76,6 +81,7 @@ _SIGS = {
     "lexp_reset_stats": (_i32, [_vp]),
     "lexp_debug_guide": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "lexp_solve_binary": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp]),
+    "lexp_solve_binary_device": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "lexp_rng_key": (_u64, [_u64, _vp, _i32]),
     "lexp_init_labels_host": (_i32, [_i32, _i32, _f64, _u64, _vp]),
     "lexp_propose": (_i32, [_i32, _i32, _vp, _u64, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _f64, _f64,
@@ -191,7 +197,8 @@ def lexp_create(params: dict, left, right, stream=None) -> LexpContext:
     P = lexp_params(w, h, float(params["disp_max"]), float(params["alpha"]), float(params["tau_col"]),
                     float(params["tau_grad"]), int(params["gf_radius"]), float(params["gf_eps"]),
                     float(params["lam"]), float(params["tau_dis"]), float(params["w_floor"]),
-                    float(params["gamma"]), int(params["neighbours"]), int(params.get("host_threads", 0)))
+                    float(params["gamma"]), int(params["neighbours"]), int(params.get("host_threads", 0)),
+                    int(params.get("device_cut", 1)))
     lp = _dev(left, torch.float32, (h, w, 3), name="left")
     rp = _dev(right, torch.float32, (h, w, 3), name="right")
     out = C.c_void_p()
@@ -353,6 +360,31 @@ def lexp_solve_binary(U, w4, neighbours=8):
     x = np.zeros((h, w), np.uint8)
     _check(load_library().lexp_solve_binary(w, h, int(neighbours), U.ctypes.data, w4.ctypes.data, x.ctypes.data))
     return x
+
+
+def lexp_solve_binary_device(ctx, problems, stream=None):
+    """problems: list of (U [h, w], w4 [h, w, 4]) integer arrays.  Returns
+    (list of x [h, w] uint8, status int32 [n])."""
+    n = len(problems)
+    dims = np.zeros(2 * max(n, 1), np.int32)
+    parts, sizes = [], []
+    for i, (U, w4) in enumerate(problems):
+        U = np.asarray(U, dtype=np.int64)
+        h, w = U.shape
+        dims[2 * i], dims[2 * i + 1] = w, h
+        t = np.concatenate([U.reshape(h * w, 1), np.asarray(w4, dtype=np.int64).reshape(h * w, 4)], axis=1)
+        parts.append(t.astype(np.int32).reshape(-1))
+        sizes.append((h, w))
+    terms = np.ascontiguousarray(np.concatenate(parts) if parts else np.zeros(5, np.int32))
+    x = np.zeros(max(1, sum(h * w for h, w in sizes)), np.uint8)
+    status = np.zeros(max(n, 1), np.int32)
+    _check(load_library().lexp_solve_binary_device(ctx.handle, n, dims.ctypes.data, terms.ctypes.data, x.ctypes.data,
+                                                   status.ctypes.data, _stream_ptr(stream)))
+    out, o = [], 0
+    for h, w in sizes:
+        out.append(x[o:o + h * w].reshape(h, w).copy())
+        o += h * w
+    return out, status[:n]
 
 
 def lexp_rng_key(seed, fields) -> int:

@@ -408,3 +408,124 @@ def test_optimize_tiny_bit_identical_to_oracle(tiny):
     cost2 = torch.zeros_like(cost)
     L.lexp_optimize(P.ctx, [(5, 1, 3)], 2, 0, lab2, cost2)
     assert torch.equal(lab, lab2) and torch.equal(cost, cost2)
+
+
+# ---------------------------------------------------------------------------
+# Device max-flow (push-relabel kernel) against the host max-flow and the
+# oracle: the cut of the fewest ones is unique, so the comparison is bitwise.
+def _binary_problems(rng, shapes, kind, reps):
+    probs = []
+    for h, w in shapes:
+        for _ in range(reps):
+            if kind == "generic":
+                U = rng.integers(-60, 61, (h, w))
+                w4 = rng.integers(0, 41, (h, w, 4))
+            elif kind == "ties":
+                U = rng.integers(-2, 3, (h, w))
+                w4 = rng.integers(0, 3, (h, w, 4))
+            elif kind == "sparse":
+                U = rng.integers(-5, 6, (h, w)) * (rng.random((h, w)) < 0.3)
+                w4 = rng.integers(0, 9, (h, w, 4)) * (rng.random((h, w, 4)) < 0.5)
+            else:  # large values near the documented limit
+                U = rng.integers(-(2 ** 30), 2 ** 30 + 1, (h, w))
+                w4 = rng.integers(0, 2 ** 30 + 1, (h, w, 4))
+            # no weight towards neighbours outside the grid
+            w4[:, -1, 0] = 0
+            w4[-1, :, 1:] = 0
+            w4[:, -1, 2] = 0
+            w4[:, 0, 3] = 0
+            probs.append((U.astype(np.int64), w4.astype(np.int64)))
+    return probs
+
+
+@pytest.mark.parametrize("kind", ["generic", "ties", "sparse", "huge"])
+def test_device_cut_equals_host_cut(tiny, kind):
+    rng = np.random.default_rng({"generic": 1, "ties": 2, "sparse": 3, "huge": 4}[kind])
+    shapes = [(1, 1), (1, 7), (6, 1), (3, 5), (15, 15), (9, 23), (22, 22)]
+    probs = _binary_problems(rng, shapes, kind, 6)
+    xs, status = L.lexp_solve_binary_device(tiny.ctx, probs)
+    assert status.all()
+    for (U, w4), x in zip(probs, xs):
+        assert np.array_equal(x, L.lexp_solve_binary(U, w4)), (U.shape, kind)
+
+
+@pytest.mark.parametrize("shape", [(45, 45), (31, 64), (75, 75), (40, 120)])
+def test_device_cut_large_regions(tiny, shape):
+    """Regions whose arrays fit in LDS run on 1024 threads; larger ones are
+    not run (status 0, left to the host max-flow)."""
+    rng = np.random.default_rng(sum(shape))
+    probs = _binary_problems(rng, [shape], "generic", 2) + _binary_problems(rng, [shape], "sparse", 2)
+    xs, status = L.lexp_solve_binary_device(tiny.ctx, probs)
+    fits = shape[0] * shape[1] * 52 <= 160 * 1024
+    assert (status == (1 if fits else 0)).all()
+    if fits:
+        for (U, w4), x in zip(probs, xs):
+            assert np.array_equal(x, L.lexp_solve_binary(U, w4))
+
+
+def test_device_cut_of_real_expansion_problems(tiny):
+    """Binary problems of actual expansions (oracle terms) against the
+    oracle's own max-flow."""
+    P = tiny
+    rng = np.random.default_rng(11)
+    lab = P.ora.init_labels(5)
+    costs = P.ora.pixel_costs(lab, np.ones((P.H, P.W), np.uint8))
+    probs = []
+    for _ in range(12):
+        ci, cj = int(rng.integers(0, 13)), int(rng.integers(0, 10))
+        rect = ((ci - 1) * 5, (cj - 1) * 5, (ci + 2) * 5, (cj + 2) * 5)
+        a = P.ora.propose(lab, 3, 0, 0, 5, ci, cj, int(rng.integers(0, 4)), 1, 8.0, 1.0)
+        phi = P.ora.unary_region(rect, a)
+        probs.append(P.ora.expand_problem(lab, costs, phi, rect, a))
+    xs, status = L.lexp_solve_binary_device(P.ctx, probs)
+    assert status.all()
+    for (U, w4), x in zip(probs, xs):
+        assert np.array_equal(x, P.ora.solve_maxflow(U, w4))
+
+
+def test_device_cut_rejects_bad_terms(tiny):
+    U = np.zeros((2, 2), np.int64)
+    w4 = np.zeros((2, 2, 4), np.int64)
+    w4[0, 0, 0] = -1
+    with pytest.raises(L.LexpError):
+        L.lexp_solve_binary_device(tiny.ctx, [(U, w4)])
+    U[0, 0] = 2 ** 30 + 1
+    w4[0, 0, 0] = 0
+    with pytest.raises(L.LexpError):
+        L.lexp_solve_binary_device(tiny.ctx, [(U, w4)])
+
+
+def test_device_cut_four_neighbourhood():
+    rng = np.random.default_rng(9)
+    p = base_params(20, 16, neighbours=4)
+    left, right = texture(rng, 16, 20), texture(rng, 16, 20)
+    ctx = L.lexp_create(p, _cuda(left), _cuda(right))
+    probs = _binary_problems(rng, [(16, 20), (7, 9)], "generic", 4)
+    for U, w4 in probs:
+        w4[..., 2:] = 0
+    xs, status = L.lexp_solve_binary_device(ctx, probs)
+    assert status.all()
+    for (U, w4), x in zip(probs, xs):
+        assert np.array_equal(x, L.lexp_solve_binary(U, w4, neighbours=4))
+
+
+def test_optimize_device_and_host_cuts_identical(lowres):
+    """One iteration of the plain method at 450x375 with the device max-flow
+    enabled (5 px cells: one part of each group cut on the device) and with
+    every cut on the host: identical labels and costs, bit for bit."""
+    P = lowres
+    out = []
+    for dc in (1, 0):
+        p = dict(P.p, device_cut=dc)
+        ctx = L.lexp_create(p, _cuda(P.left), _cuda(P.right))
+        L.lexp_set_timing(ctx, True)
+        lab = torch.zeros((P.H, P.W, 4), device="cuda")
+        cost = torch.zeros((P.H, P.W), device="cuda")
+        e, _ = L.lexp_optimize(ctx, [(5, 1, 7), (15, 1, 7), (25, 1, 7)], 1, 0, lab, cost)
+        if dc:
+            assert L.lexp_get_stats(ctx)["expand_calls"] > 0
+        out.append((lab.cpu().numpy(), cost.cpu().numpy(), e))
+        ctx.close()
+    assert np.array_equal(out[0][0].view(np.uint32), out[1][0].view(np.uint32))
+    assert np.array_equal(out[0][1].view(np.uint32), out[1][1].view(np.uint32))
+    assert out[0][2][-1] == out[1][2][-1]
