@@ -105,10 +105,11 @@ def run_gpu(steps: int, warmup: int, seed: int = 0):
 
 def run_cpu_baseline():
     """The oracle on a bounded sample of the same workload: initial per-pixel
-    costs of the regions of the first 16/8/4 cells of group 0 at grid levels
-    5/15/25 px, and the 8 proposer steps of those cells at iteration 0 (cells
-    in parallel on all host threads).  The per-eval times of the two parts are
-    weighted by the full run's counts to give evals/s in the metric's unit."""
+    costs of the regions of a sample of group-0 cells at grid levels 5/15/25 px
+    (every 4th, every 2nd and every cell of the group), and the 8 proposer
+    steps of those cells at iteration 0 (cells in parallel on all host
+    threads).  The per-eval times of the two parts are weighted by the full
+    run's counts to give evals/s in the metric's unit."""
     from concurrent.futures import ThreadPoolExecutor
 
     from oracle import Oracle
@@ -122,14 +123,16 @@ def run_cpu_baseline():
     h, w = pair.left.shape[:2]
     labels = ora.init_labels(0)
     costs = np.zeros((h, w))
-    n_cells = {5: 16, 15: 8, 25: 4}
+    stride = {5: 4, 15: 2, 25: 1}
     t_a5 = 0.0
     n_a5 = 0
     t_exp = {}
     n_exp = {}
     for level, (cell, kp, kr) in enumerate(wl["grids"]):
         nci = -(-w // cell)
-        cells = [(i, 0) for i in range(0, nci, 4)][: n_cells[cell]]
+        ncj = -(-h // cell)
+        group0 = [(i, j) for j in range(0, ncj, 4) for i in range(0, nci, 4)]
+        cells = group0[::stride[cell]]
         rects = [((i - 1) * cell, (j - 1) * cell, (i + 2) * cell, (j + 2) * cell) for i, j in cells]
         mask = np.zeros((h, w), np.uint8)
         for u0, v0, u1, v1 in rects:
@@ -168,8 +171,8 @@ def run_cpu_baseline():
     full_time = h * w * (t_a5 / n_a5) + sum(full[c] * t_exp[c] / n_exp[c] for c in full)
     sample_time = t_a5 + sum(t_exp.values())
     return dict(value=full_evals / full_time / 1e9, cores=threads, sample_s=sample_time,
-                sample=(f"oracle FP64: initial costs of {n_a5} px and 8 proposer steps of the first 16/8/4 "
-                        f"cells of group 0 at levels 5/15/25 px ({sum(n_exp.values())} evals); per-eval times "
+                sample=(f"oracle FP64: initial costs of {n_a5} px and 8 proposer steps of every 4th/2nd/1st cell "
+                        f"of group 0 at levels 5/15/25 px ({sum(n_exp.values())} evals); per-eval times "
                         f"weighted by the full run's counts ({full_evals} evals)"))
 
 
