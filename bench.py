@@ -103,6 +103,77 @@ def run_gpu(steps: int, warmup: int, seed: int = 0):
                 final_energy=e_final, stats=results[-1][2], final_labels=labels.cpu().numpy())
 
 
+def run_many_pairs(n_pairs: int, iterations: int, seed: int = 0):
+    """The uneven-size many-pair workload (width ~ U[320,1500], height 0.67 w
+    rounded to 8, disparity range 0.13 w, scenes as the 450x375 one, r = 20,
+    cells 5/15/25): the plain method run pair by pair (lexp_optimize in a loop)
+    and batched (lexp_optimize_batch: every group step of all pairs in shared
+    launches).  Both runs must return the same labels bit for bit."""
+    import torch
+
+    import paper_1603_08328_amd.lexp as L
+    from synth import PAPER_PARAMS, make_pair, workload
+    from synth.workloads import many_pair_scenes
+
+    grids = workload(WORKLOAD)["grids"]
+    scenes = many_pair_scenes(n_pairs)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    ctxs, shapes = [], []
+    for sc in scenes:
+        pair = make_pair(**sc)
+        prm = dict(PAPER_PARAMS, width=sc["width"], height=sc["height"], disp_max=sc["disp_max"], gf_radius=20)
+        ctxs.append(L.lexp_create(prm, torch.from_numpy(pair.left).to(dev), torch.from_numpy(pair.right).to(dev),
+                                  stream))
+        shapes.append((sc["height"], sc["width"]))
+    px = sum(h * w for h, w in shapes)
+
+    def buffers():
+        return ([torch.zeros((h, w, 4), device=dev) for h, w in shapes],
+                [torch.zeros((h, w), device=dev) for h, w in shapes])
+
+    seeds = [seed] * n_pairs
+    lab_a, cost_a = buffers()
+    torch.cuda.synchronize()
+    for c in ctxs:
+        L.lexp_set_timing(c, True)
+        L.lexp_reset_stats(c)
+    t0 = time.perf_counter()
+    loop_e = []
+    for c, sd, lab, cost in zip(ctxs, seeds, lab_a, cost_a):
+        e, _ = L.lexp_optimize(c, grids, iterations, sd, lab, cost, stream)
+        loop_e.append(e)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    loop_stats = [L.lexp_get_stats(c) for c in ctxs]
+    evals = sum(s["unary_evals"] for s in loop_stats) + px
+    loop_kernel_ms = sum(s["unary_kernel_ms"] for s in loop_stats)
+
+    lab_b, cost_b = buffers()
+    torch.cuda.synchronize()
+    L.lexp_reset_stats(ctxs[0])
+    t0 = time.perf_counter()
+    batch_e, batch_t = L.lexp_optimize_batch(ctxs, grids, iterations, seeds, lab_b, cost_b, stream)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    bst = L.lexp_get_stats(ctxs[0])
+    same = all(torch.equal(a, b) for a, b in zip(lab_a, lab_b)) and \
+        all(np.array_equal(a, b) for a, b in zip(loop_e, batch_e))
+    for c in ctxs:
+        c.close()
+    return dict(n_pairs=n_pairs, megapixels=px / 1e6, iterations=iterations, evals=evals,
+                loop_s=t_loop, batch_s=t_batch, loop_value=evals / t_loop / 1e9, batch_value=evals / t_batch / 1e9,
+                identical=bool(same), energy_total_trace=[round(float(x), 3) for x in np.sum(batch_e, axis=0)],
+                batch_time_trace=[round(float(x), 3) for x in batch_t],
+                loop_kernel_ms=loop_kernel_ms, batch_kernel_ms=bst["unary_kernel_ms"],
+                batch_launches=bst["unary_launches"], batch_host_cut_ms=bst["host_cut_ms"],
+                batch_host_wait_ms=bst["host_wait_ms"], batch_host_enqueue_ms=bst["host_enqueue_ms"],
+                batch_host_cut_level_ms=[round(x, 2) for x in bst["host_cut_level_ms"]],
+                batch_device_cut_fallbacks=bst["device_cut_fallbacks"],
+                batch_device_cut_share=[round(x, 3) for x in bst["device_cut_share"]],
+                batch_alg_gbps=bst["unary_alg_bytes"] / max(bst["unary_kernel_ms"], 1e-9) / 1e6)
+
+
 def run_cpu_baseline():
     """The oracle on a bounded sample of the same workload: initial per-pixel
     costs of the regions of a sample of group-0 cells at grid levels 5/15/25 px
@@ -184,11 +255,26 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for counter calibration)")
+    ap.add_argument("--many-pairs", type=int, default=0,
+                    help="instead: the uneven-size many-pair workload with this many pairs, pair by pair and "
+                         "batched (one JSON line with both)")
+    ap.add_argument("--iterations", type=int, default=10, help="iterations of the many-pair runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path runs on a single "
               "MI355X; see the design notes for how it would shard)", file=sys.stderr)
         sys.exit(2)
+    if args.many_pairs:
+        m = run_many_pairs(args.many_pairs, args.iterations)
+        out = {"metric": METRIC, "value": m["batch_value"], "unit": "Gpix*labels/s", "n_gpus": 1, "steps": 1,
+               "warmup": 0, "ms_per_step": m["batch_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": f"{m['n_pairs']} uneven pairs of the many-pair recipe "
+                                      f"({m['megapixels']:.2f} Mpx), r=20, cells 5/15/25, "
+                                      f"{m['iterations']} iterations, {{K_prop,K_rand}}={{1,7}}"},
+               "many_pairs": m}
+        print(json.dumps(out), flush=True)
+        return
     if args.copy_calibration_mib:
         import torch
         n = args.copy_calibration_mib * (1 << 20) // 4
@@ -241,6 +327,7 @@ def main():
         "host_enqueue_ms_per_step": g["stats"]["host_enqueue_ms"],
         "host_update_ms_per_step": g["stats"]["host_update_ms"],
         "host_cut_level_ms_per_step": [round(x, 2) for x in g["stats"]["host_cut_level_ms"]],
+        "device_cut_share": [round(x, 3) for x in g["stats"]["device_cut_share"]],
     }
     print(json.dumps(out), flush=True)
 

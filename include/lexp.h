@@ -106,6 +106,8 @@ typedef struct {
   double host_update_ms;    /* lexp_optimize: host time queueing label updates after the cuts */
   double host_cut_level_ms[4]; /* lexp_optimize: host_cut_ms by grid level */
   int64_t device_cut_fallbacks; /* lexp_optimize: regions the device max-flow left to the host */
+  double device_cut_share[4];   /* lexp_optimize: share of each level's device-sized regions cut on
+                                   the device in the last iteration (0 with device_cut off) */
 } lexp_stats;
 
 /* Creates a context for one stereo pair and runs the label-independent set-up
@@ -195,6 +197,24 @@ lexp_status lexp_init_labels(lexp_ctx* ctx, uint64_t seed, float* labels, void* 
  *   seconds since the call started at those points.  Synchronous. */
 lexp_status lexp_optimize(lexp_ctx* ctx, const lexp_schedule* schedule, uint64_t seed, float* labels,
                           float* cur_cost, double* energy_trace, double* time_trace, void* hip_stream);
+
+/* lexp_optimize for n_pairs stereo pairs at once, each with its own context
+ * (sizes and disparity ranges may differ; gf_radius and neighbours must be the
+ * same, and every context must live on the current device).  Every group step
+ * of Alg. 2 (Eq. (15)) is evaluated for all pairs together: one fused cost
+ * launch, one graph-term launch, one device max-flow launch and one host-pool
+ * pass cover the regions of that step in every pair.  Pair i's labels,
+ * cur_cost and energy trace equal, bit for bit, what lexp_optimize returns for
+ * (ctxs[i], seeds[i]) alone.
+ *   ctxs, seeds, labels, cur_cost: host arrays [n_pairs] (distinct contexts
+ *   and buffers); labels[i] device HxWx4 and cur_cost[i] device HxW of pair i.
+ *   energy_traces: NULL, or host array [n_pairs] of per-pair traces
+ *   (iterations+1 values each, entries may be NULL).  time_trace: as in
+ *   lexp_optimize, for the whole batch.  The scratch, host threads, device_cut
+ *   setting and statistics of ctxs[0] serve the run.  Synchronous. */
+lexp_status lexp_optimize_batch(int32_t n_pairs, lexp_ctx* const* ctxs, const lexp_schedule* schedule,
+                                const uint64_t* seeds, float* const* labels, float* const* cur_cost,
+                                double* const* energy_traces, double* time_trace, void* hip_stream);
 
 /* Timing of the fused cost kernel (HIP events around each launch on its
  * stream) and host phases.  enable != 0 turns it on; reset clears counters. */

@@ -22,6 +22,7 @@
 
 using lexp::DevParams;
 using lexp::Item;
+using lexp::PairDev;
 using lexp::Tile;
 
 namespace {
@@ -105,6 +106,12 @@ struct lexp_ctx {
   float4* right4 = nullptr;
   float* guide = nullptr;
   double* wts = nullptr;
+  // the context's own entry of a pair table (labels and costs of the call)
+  DevBuf<PairDev> d_pair;
+  PinBuf<PairDev> h_pair;
+  // pair table of an optimisation run (one entry per pair of the run)
+  DevBuf<PairDev> d_run_pairs;
+  PinBuf<PairDev> h_run_pairs;
   DevBuf<Item> d_items;
   DevBuf<Tile> d_tiles;
   DevBuf<float> d_phi;
@@ -123,6 +130,7 @@ struct lexp_ctx {
   PinBuf<double> h_partial;
   PinBuf<float> h_labels4;
   hipEvent_t staging_done = nullptr;  // host staging buffers may be rewritten once this has completed
+  int n_threads = 1;  // host threads of the min-cut pool (started on first use)
   std::unique_ptr<lexp::ThreadPool> pool;
   std::vector<std::unique_ptr<lexp::BKSolver>> solvers;
   bool timing = false;
@@ -154,6 +162,19 @@ struct lexp_ctx {
 };
 
 namespace {
+
+PairDev pair_entry(const lexp_ctx* c, float* labels, float* cur_cost) {
+  PairDev e{};
+  e.P = c->dp;
+  e.left4 = c->left4;
+  e.left4T = c->left4T;
+  e.right4 = c->right4;
+  e.guide = c->guide;
+  e.wts = c->wts;
+  e.labels = reinterpret_cast<float4*>(labels);
+  e.cur_cost = cur_cost;
+  return e;
+}
 
 bool finite_plane(const lexp_plane& p) { return std::isfinite(p.a) && std::isfinite(p.b) && std::isfinite(p.c); }
 
@@ -268,8 +289,11 @@ void collect_timing(lexp_ctx* c) {
   c->ev_pending.clear();
 }
 
+// Fused cost kernel over n_tiles tiles of the items (pairs: the table the
+// items' pair indices refer to; MODE 2 covers every pixel of pairs[0]).
 template <int MODE>
-lexp_status launch_unary(lexp_ctx* c, const Item* d_items, const Tile* d_tiles, int n_tiles, const TileCaps& caps,
+lexp_status launch_unary(lexp_ctx* c, const PairDev* d_pairs, const Item* d_items, const Tile* d_tiles, int n_tiles,
+                         const TileCaps& caps,
                          const float4* label_field, float* out, hipStream_t s, double alg_bytes, int64_t evals,
                          int64_t n_items) {
   if (n_tiles <= 0) return LEXP_OK;
@@ -290,9 +314,8 @@ lexp_status launch_unary(lexp_ctx* c, const Item* d_items, const Tile* d_tiles, 
   // pair) and of an R+ row
   const int nseg = (caps.ws + 31) / 32, nc = (std::max(caps.wp, caps.tw) + 31) / 32;
 #define LEXP_LAUNCH(M, S, C)                                                                                       \
-  hipLaunchKernelGGL((lexp::k_unary<M, S, C>), dim3(grid), dim3(lexp::kWaves * 64), lds, s, c->dp, c->left4,       \
-                     c->left4T, c->right4, c->guide, d_items, d_tiles, n_tiles, label_field, out, ring, caps.wp,   \
-                     caps.tw, caps.ws)
+  hipLaunchKernelGGL((lexp::k_unary<M, S, C>), dim3(grid), dim3(lexp::kWaves * 64), lds, s, d_pairs, d_items,      \
+                     d_tiles, n_tiles, label_field, out, ring, caps.wp, caps.tw, caps.ws)
 #define LEXP_LAUNCH_C(M, S)  \
   if (nc <= 1) {             \
     LEXP_LAUNCH(M, S, 1);    \
@@ -376,6 +399,14 @@ lexp_status wait_staging(lexp_ctx* c) {
   return LEXP_OK;
 }
 
+// Writes the context's pair entry with the call's label field and costs
+// (after wait_staging: the pinned entry is staging memory).
+lexp_status stage_pair(lexp_ctx* c, float* labels, float* cur_cost, hipStream_t s) {
+  c->h_pair.p[0] = pair_entry(c, labels, cur_cost);
+  HIP_TRY(hipMemcpyAsync(c->d_pair.p, c->h_pair.p, sizeof(PairDev), hipMemcpyHostToDevice, s));
+  return LEXP_OK;
+}
+
 // Builds the item table for (rects, labels) on the host staging buffer.
 lexp_status stage_items(lexp_ctx* c, int n, const lexp_rect* rects, const lexp_plane* labels, const int64_t* offsets,
                         const int64_t* aux) {
@@ -385,7 +416,7 @@ lexp_status stage_items(lexp_ctx* c, int n, const lexp_rect* rects, const lexp_p
     clip_rect(c, rects[i], &u0, &v0, &u1, &v1);
     Item& it = c->h_items.p[i];
     it.ru0 = u0; it.rv0 = v0; it.rw = u1 - u0; it.rh = v1 - v0;
-    it.a = labels[i].a; it.b = labels[i].b; it.c = labels[i].c; it.pad = 0.f;
+    it.a = labels[i].a; it.b = labels[i].b; it.c = labels[i].c; it.pair = 0;
     it.out_off = offsets ? offsets[i] : 0;
     it.aux_off = aux ? aux[i] : 0;
   }
@@ -445,6 +476,8 @@ int64_t cut_energy(int w, int h, int nf, const int* terms, const uint8_t* x) {
   return e;
 }
 
+lexp::ThreadPool& pool_of(lexp_ctx* c);
+
 // Graph terms on the device, host max-flow per item, label update on the
 // device.  Items are staged in c->h_items (aux_off = compact pixel offset,
 // total pixels n_px).  mirror (optional): host HxWx3 labels to update.
@@ -465,8 +498,10 @@ lexp_status expand_batch(lexp_ctx* c, int n, int64_t n_px, const float* alpha_co
   int max_px = 1;
   for (int i = 0; i < n; ++i) max_px = std::max(max_px, c->h_items.p[i].rw * c->h_items.p[i].rh);
   HIP_TRY(hipMemsetAsync(c->d_flag.p, 0, sizeof(int), s));
-  hipLaunchKernelGGL(lexp::k_graph_terms, dim3((max_px + 255) / 256, n), dim3(256), 0, s, c->dp, c->d_items.p,
-                     (const float4*)labels, cur_cost, alpha_cost, c->wts, c->d_terms.p, c->d_flag.p);
+  lexp_status st = stage_pair(c, labels, cur_cost, s);
+  if (st) return st;
+  hipLaunchKernelGGL(lexp::k_graph_terms, dim3((max_px + 255) / 256, n), dim3(256), 0, s, c->d_pair.p,
+                     c->d_items.p, alpha_cost, c->d_terms.p, c->d_flag.p);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(c->h_terms.p, c->d_terms.p, sizeof(int) * 5 * n_px, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(c->h_flag.p, c->d_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -478,7 +513,7 @@ lexp_status expand_batch(lexp_ctx* c, int n, int64_t n_px, const float* alpha_co
   std::vector<int64_t> de(n, 0);
   std::vector<int32_t> nc(n, 0);
   const Item* items = c->h_items.p;
-  c->pool->parallel_for(n, [&](int i, int worker) {
+  pool_of(c).parallel_for(n, [&](int i, int worker) {
     const Item& it = items[i];
     if (it.rw <= 0 || it.rh <= 0) return;
     const int* t = c->h_terms.p + (size_t)it.aux_off * 5;
@@ -500,8 +535,8 @@ lexp_status expand_batch(lexp_ctx* c, int n, int64_t n_px, const float* alpha_co
   });
   const auto t2 = std::chrono::steady_clock::now();
   HIP_TRY(hipMemcpyAsync(c->d_x.p, c->h_x.p, (size_t)n_px, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(lexp::k_apply, dim3((max_px + 255) / 256, n), dim3(256), 0, s, c->W, c->d_items.p, c->d_x.p,
-                     alpha_cost, (float4*)labels, cur_cost);
+  hipLaunchKernelGGL(lexp::k_apply, dim3((max_px + 255) / 256, n), dim3(256), 0, s, c->d_pair.p, c->d_items.p,
+                     c->d_x.p, alpha_cost);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(c->staging_done, s));
   int64_t sum = 0;
@@ -527,6 +562,17 @@ int default_threads() {
   cpu_set_t set;
   if (sched_getaffinity(0, sizeof(set), &set) == 0) return std::max(1, CPU_COUNT(&set));
   return (int)std::max(1u, std::thread::hardware_concurrency());
+}
+
+// The context's min-cut pool and one max-flow solver per thread, started on
+// first use (a context used only for costs, or as a non-first pair of a batched
+// run, starts no threads).
+lexp::ThreadPool& pool_of(lexp_ctx* c) {
+  if (!c->pool) {
+    c->pool.reset(new lexp::ThreadPool(c->n_threads));
+    for (int i = 0; i < c->pool->size(); ++i) c->solvers.emplace_back(new lexp::BKSolver());
+  }
+  return *c->pool;
 }
 
 lexp_status energy_impl(lexp_ctx* c, const float* labels, const float* cur_cost, double* total, double* unary,
@@ -556,7 +602,7 @@ lexp_status pixel_costs_impl(lexp_ctx* c, const float* labels, float* out, hipSt
   caps.tw = 1;
   caps.wp = std::min(2 * c->r + 1, c->W);
   caps.ws = std::max(std::min(4 * c->r + 1, c->W), caps.wp);
-  return launch_unary<2>(c, nullptr, nullptr, c->W * c->H, caps, (const float4*)labels, out, s, 0.0,
+  return launch_unary<2>(c, c->d_pair.p, nullptr, nullptr, c->W * c->H, caps, (const float4*)labels, out, s, 0.0,
                          (int64_t)c->W * c->H, (int64_t)c->W * c->H);
 }
 
@@ -642,12 +688,15 @@ lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const 
   (void)hipFree(tmp);
   if (e != hipSuccess || e2 != hipSuccess)
     return fail(LEXP_EDEVICE, "set-up kernels: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  HIP_TRY(c->d_pair.ensure(1));
+  HIP_TRY(c->h_pair.ensure(1));
+  c->h_pair.p[0] = pair_entry(c.get(), nullptr, nullptr);
+  HIP_TRY(hipMemcpy(c->d_pair.p, c->h_pair.p, sizeof(PairDev), hipMemcpyHostToDevice));
   HIP_TRY(hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming));
   HIP_TRY(hipEventRecord(c->staging_done, s));
   int nt = p.host_threads;
   if (nt == 0) nt = std::min(default_threads(), 64);
-  c->pool.reset(new lexp::ThreadPool(nt));
-  for (int i = 0; i < c->pool->size(); ++i) c->solvers.emplace_back(new lexp::BKSolver());
+  c->n_threads = nt;
   *out = c.release();
   return LEXP_OK;
 }
@@ -666,6 +715,7 @@ lexp_status lexp_destroy(lexp_ctx* c) {
   c->d_items.release(); c->d_tiles.release(); c->d_phi.release(); c->d_terms.release(); c->d_x.release();
   c->d_flag.release(); c->d_partial.release(); c->d_labels_tmp.release();
   c->d_status.release(); c->h_status.release();
+  c->d_pair.release(); c->h_pair.release(); c->d_run_pairs.release(); c->h_run_pairs.release();
   c->h_items.release(); c->h_tiles.release(); c->h_terms.release(); c->h_x.release(); c->h_flag.release();
   c->h_partial.release(); c->h_labels4.release();
   for (auto& b : c->part) {
@@ -702,7 +752,8 @@ lexp_status lexp_unary_cost(lexp_ctx* c, int32_t n, const lexp_rect* rects, cons
     bytes += item_alg_bytes(c, c->h_items.p[i]);
     evals += (int64_t)c->h_items.p[i].rw * c->h_items.p[i].rh;
   }
-  st = launch_unary<0>(c, c->d_items.p, c->d_tiles.p, (int)tiles.size(), caps, nullptr, out_cost, s, bytes, evals, n);
+  st = launch_unary<0>(c, c->d_pair.p, c->d_items.p, c->d_tiles.p, (int)tiles.size(), caps, nullptr, out_cost, s,
+                       bytes, evals, n);
   if (st) return st;
   HIP_TRY(hipEventRecord(c->staging_done, s));
   return LEXP_OK;
@@ -727,7 +778,8 @@ lexp_status lexp_guided_coeffs(lexp_ctx* c, int32_t n, const lexp_rect* rects, c
   HIP_TRY(hipMemcpyAsync(c->d_items.p, c->h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
   if (!tiles.empty())
     HIP_TRY(hipMemcpyAsync(c->d_tiles.p, c->h_tiles.p, sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, s));
-  st = launch_unary<1>(c, c->d_items.p, c->d_tiles.p, (int)tiles.size(), caps, nullptr, out_ab, s, 0.0, 0, n);
+  st = launch_unary<1>(c, c->d_pair.p, c->d_items.p, c->d_tiles.p, (int)tiles.size(), caps, nullptr, out_ab, s, 0.0,
+                       0, n);
   if (st) return st;
   HIP_TRY(hipEventRecord(c->staging_done, s));
   return LEXP_OK;
@@ -785,8 +837,9 @@ lexp_status lexp_graph_terms(lexp_ctx* c, int32_t n, const lexp_rect* rects, con
   HIP_TRY(c->d_flag.ensure(1));
   HIP_TRY(hipMemcpyAsync(c->d_items.p, c->h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(c->d_flag.p, 0, sizeof(int), s));
-  hipLaunchKernelGGL(lexp::k_graph_terms, dim3((max_px + 255) / 256, n), dim3(256), 0, s, c->dp, c->d_items.p,
-                     (const float4*)labels, cur_cost, alpha_cost, c->wts, out_terms, c->d_flag.p);
+  if ((st = stage_pair(c, const_cast<float*>(labels), const_cast<float*>(cur_cost), s))) return st;
+  hipLaunchKernelGGL(lexp::k_graph_terms, dim3((max_px + 255) / 256, n), dim3(256), 0, s, c->d_pair.p,
+                     c->d_items.p, alpha_cost, out_terms, c->d_flag.p);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(c->staging_done, s));
   return LEXP_OK;
@@ -827,7 +880,18 @@ lexp_status lexp_init_labels(lexp_ctx* c, uint64_t seed, float* labels, void* hi
 
 namespace {
 
-// One half of a group: its cells, clipped regions (compact offsets) and tiles.
+// One stereo pair of an optimisation run.
+struct RunPair {
+  lexp_ctx* c = nullptr;
+  uint64_t seed = 0;
+  float* labels = nullptr;
+  float* cur_cost = nullptr;
+  double* energy_trace = nullptr;
+  std::vector<float> mirror;  // host copy of the labels (HxWx3) for the proposers
+};
+
+// One part of a group step: regions of one or more pairs (Item::pair), their
+// cells, compact offsets and tiles.
 struct Part {
   std::vector<int> ci, cj;
   std::vector<Item> items;
@@ -839,45 +903,79 @@ struct Part {
   bool device_cut = false;  // minimum cuts by the device max-flow
 };
 
+// Split of each grid level's cuts between the device max-flow and the host
+// pool.  Per group step the device evaluates and cuts part 0 while the host
+// cuts part 1 (whose costs the device evaluates too); part 0 takes a share
+// `share` of the regions the device can hold.  A level whose groups have more
+// than four regions per host thread starts at an even split and is tuned by
+// hill climbing on the wall time per region pixel of its group steps: the
+// share keeps moving while that time falls, and turns back with half the
+// step when it rises.  A level of smaller groups is cut on the host only (one
+// part, all threads).  Any split gives the same labels: every cut is exact.
+struct CutBalance {
+  bool tune = false;
+  double share = 0.0, step = 0.125;
+  int dir = 1;
+  double prev = -1.0;  // previous group step's milliseconds per region pixel
+
+  void update(double ms_per_px) {
+    if (!tune) return;
+    if (prev >= 0.0) {
+      if (ms_per_px > prev) {
+        dir = -dir;
+        step *= 0.5;
+      } else {
+        step *= 1.25;
+      }
+      step = std::min(0.25, std::max(1.0 / 64, step));
+    }
+    prev = ms_per_px;
+    share = std::min(1.0, std::max(0.0, share + dir * step));
+  }
+};
+
 struct StepArgs {
-  uint64_t seed;
   int it, level, cell, kp;
-  double r_d, r_n;
-  const float* mirror;
+  double scale;  // 0.5^it: the iteration's perturbation sizes relative to the first (Alg. 2)
+  RunPair* pairs;
 };
 
 // Alg. 1 candidate of region q of a part for a step, into its item.
-void propose_item(const lexp_ctx* c, Part& P, const StepArgs& a, int q, int step) {
+void propose_item(Part& P, const StepArgs& a, int q, int step) {
+  Item& item = P.items[q];
+  const RunPair& rp = a.pairs[item.pair];
+  const lexp_ctx* c = rp.c;
   float al[3];
-  lexp::propose(c->W, c->H, a.mirror, 3, a.seed, a.it, a.level, a.cell, P.ci[q], P.cj[q], step, a.kp, a.r_d, a.r_n,
-                al);
-  P.items[q].a = al[0];
-  P.items[q].b = al[1];
-  P.items[q].c = al[2];
+  lexp::propose(c->W, c->H, rp.mirror.data(), 3, rp.seed, a.it, a.level, a.cell, P.ci[q], P.cj[q], step, a.kp,
+                c->prm.disp_max / 2.0 * a.scale, a.scale, al);
+  item.a = al[0];
+  item.b = al[1];
+  item.c = al[2];
 }
 
 // A part's items (with their candidates already proposed), cost kernel, graph
-// terms and the copy of the terms to the host, all queued on the stream.
-lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const Tile* d_tiles, const float* labels,
-                         const float* cur_cost, hipStream_t s) {
+// terms and the copy of the terms (or of the device cut) to the host, all
+// queued on the stream.
+lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairDev* d_pairs, const Tile* d_tiles,
+                         hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
   const int n = (int)P.items.size();
   std::copy(P.items.begin(), P.items.end(), B.h_items.p);
   HIP_TRY(hipMemcpyAsync(B.d_items.p, B.h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
-  lexp_status st = launch_unary<0>(c, B.d_items.p, d_tiles + P.tile_off, (int)P.n_tiles, P.caps, nullptr, B.d_phi.p, s,
-                                   P.bytes, P.n_px, n);
+  lexp_status st = launch_unary<0>(c, d_pairs, B.d_items.p, d_tiles + P.tile_off, (int)P.n_tiles, P.caps, nullptr,
+                                   B.d_phi.p, s, P.bytes, P.n_px, n);
   if (st) return st;
   if (P.device_cut) {
     int* flag = reinterpret_cast<int*>(B.d_res.p);
-    hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, c->dp, B.d_items.p,
-                       (const float4*)labels, cur_cost, B.d_phi.p, c->wts, B.d_terms.p + 1, flag);
+    hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, d_pairs, B.d_items.p,
+                       B.d_phi.p, B.d_terms.p + 1, flag);
     HIP_TRY(hipGetLastError());
     if ((st = launch_cut(c, B.d_items.p, n, B.d_terms.p + 1, B.d_res.p + 4 + 4 * c->res_items, flag + 1, P.max_px, s)))
       return st;
     HIP_TRY(hipMemcpyAsync(B.h_res.p, B.d_res.p, 4 + 4 * c->res_items + (size_t)P.n_px, hipMemcpyDeviceToHost, s));
   } else {
-    hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, c->dp, B.d_items.p,
-                       (const float4*)labels, cur_cost, B.d_phi.p, c->wts, B.d_terms.p + 1, B.d_terms.p);
+    hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, d_pairs, B.d_items.p,
+                       B.d_phi.p, B.d_terms.p + 1, B.d_terms.p);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(B.h_terms.p, B.d_terms.p, sizeof(int) * (1 + 5 * P.n_px), hipMemcpyDeviceToHost, s));
   }
@@ -889,14 +987,15 @@ lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const Tile*
 // Waits for a part's cut (device path) or terms (host path), completes the
 // cut on the host pool (every region on the host path; on the device path
 // only the regions the kernel left unfinished, whose terms are fetched then),
-// updates the host label mirror and queues the label update on the device.
+// updates the host label mirrors and queues the label update on the device.
 // With next_step >= 0, each worker then proposes its region's candidate for
 // that step: a candidate reads labels of the region's own centre cell only,
 // which no other region of the group changes (Lemma 3).
-lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepArgs& a, int next_step, float* mirror,
-                        float* labels, float* cur_cost, hipStream_t s) {
+lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepArgs& a, int next_step,
+                        const PairDev* d_pairs, hipStream_t s) {
   const int n = (int)P.items.size();
   const bool dev = P.device_cut;
+  lexp::ThreadPool& pool = pool_of(c);
   const auto t0 = std::chrono::steady_clock::now();
   HIP_TRY(hipEventSynchronize(B.ready));
   const auto t1 = std::chrono::steady_clock::now();
@@ -927,19 +1026,21 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
     bk.solve(xs + it.aux_off);
   };
   if (dev && !host_cut.empty())
-    c->pool->parallel_for((int)host_cut.size(), [&](int q, int worker) { host_solve(host_cut[q], worker); });
-  c->pool->parallel_for(n, [&](int i, int worker) {
+    pool.parallel_for((int)host_cut.size(), [&](int q, int worker) { host_solve(host_cut[q], worker); });
+  pool.parallel_for(n, [&](int i, int worker) {
     const Item& it = P.items[i];
     if (it.rw > 0 && it.rh > 0) {
       if (!dev) host_solve(i, worker);
       const uint8_t* x = xs + it.aux_off;
+      RunPair& rp = a.pairs[it.pair];
+      const int W = rp.c->W;
       for (int q = 0; q < it.rw * it.rh; ++q) {
         if (!x[q]) continue;
-        float* m = mirror + ((size_t)(it.rv0 + q / it.rw) * c->W + (it.ru0 + q % it.rw)) * 3;
+        float* m = rp.mirror.data() + ((size_t)(it.rv0 + q / it.rw) * W + (it.ru0 + q % it.rw)) * 3;
         m[0] = it.a; m[1] = it.b; m[2] = it.c;
       }
     }
-    if (next_step >= 0) propose_item(c, P, a, i, next_step);
+    if (next_step >= 0) propose_item(P, a, i, next_step);
   });
   const auto t2 = std::chrono::steady_clock::now();
   if (!dev) {
@@ -950,8 +1051,8 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
       HIP_TRY(hipMemcpyAsync(d_xs + it.aux_off, xs + it.aux_off, (size_t)it.rw * it.rh, hipMemcpyHostToDevice, s));
     }
   }
-  hipLaunchKernelGGL(lexp::k_apply, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, c->W, B.d_items.p, d_xs,
-                     B.d_phi.p, (float4*)labels, cur_cost);
+  hipLaunchKernelGGL(lexp::k_apply, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, d_pairs, B.d_items.p, d_xs,
+                     B.d_phi.p);
   HIP_TRY(hipGetLastError());
   const auto t3 = std::chrono::steady_clock::now();
   c->stats.expand_calls += 1;
@@ -962,94 +1063,219 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
   return LEXP_OK;
 }
 
-}  // namespace
+// Clipped 3x3-cell region of cell (i, j).
+void cell_region(const lexp_ctx* c, int cell, int i, int j, int* u0, int* v0, int* u1, int* v1) {
+  lexp_rect rr{(i - 1) * cell, (j - 1) * cell, (i + 2) * cell, (j + 2) * cell};
+  clip_rect(c, rr, u0, v0, u1, v1);
+}
 
-extern "C" lexp_status lexp_optimize(lexp_ctx* c, const lexp_schedule* sch, uint64_t seed, float* labels,
-                                     float* cur_cost, double* energy_trace, double* time_trace, void* hip_stream) {
-  if (!c || !sch || !labels || !cur_cost) return fail(LEXP_EINVAL, "null argument");
+// All regions of one group step of a run (every pair), largest first, each
+// with its tiles.
+struct GroupPlan {
+  std::vector<Item> items;               // pair, region and size (offsets set per part)
+  std::vector<int> ci, cj, pair_part;    // cell of each region; its part in the pair's own split
+  std::vector<std::vector<Tile>> tiles;  // tiles of each region (Tile::item unset)
+  std::vector<TileCaps> caps;            // their widths
+  size_t tile_off = 0, n_tiles = 0;      // the group's range in the run's tile table
+  int64_t n_px = 0;
+  double share = -2.0;                   // share of its current split (-2: not split yet)
+};
+
+// Appends one pair's regions of group k at grid level `cell` to a group plan.
+// The pair's cells (Eq. (15): group 4 (j mod 4) + (i mod 4)) are ordered
+// largest region first; when the pair has more than four regions per host
+// thread in the group they alternate between two parts, otherwise all are in
+// part 0.  Tiles are planned per pair and part, so a region gets the same
+// tiles (and the same rounding) whether its pair runs alone or batched, and
+// whichever part of the run's group step it is put in.
+void plan_pair_group(const lexp_ctx* c, int pair, int cell, int k, GroupPlan& g) {
+  const int nci = (c->W + cell - 1) / cell, ncj = (c->H + cell - 1) / cell;
+  std::vector<std::pair<int, int>> cells;
+  for (int j = k / 4; j < ncj; j += 4)
+    for (int i = k % 4; i < nci; i += 4) cells.emplace_back(i, j);
+  auto area = [&](const std::pair<int, int>& q) {
+    int u0, v0, u1, v1;
+    cell_region(c, cell, q.first, q.second, &u0, &v0, &u1, &v1);
+    return (int64_t)(u1 - u0) * (v1 - v0);
+  };
+  std::stable_sort(cells.begin(), cells.end(),
+                   [&](const std::pair<int, int>& x, const std::pair<int, int>& y) { return area(x) > area(y); });
+  const bool split = cells.size() > (size_t)4 * c->n_threads;
+  for (int hp = 0; hp < 2; ++hp) {
+    std::vector<Item> mine;
+    std::vector<std::pair<int, int>> mine_cells;
+    for (size_t q = split ? (size_t)hp : 0; q < (split || hp == 0 ? cells.size() : 0); q += split ? 2 : 1) {
+      int u0, v0, u1, v1;
+      cell_region(c, cell, cells[q].first, cells[q].second, &u0, &v0, &u1, &v1);
+      Item it{};
+      it.ru0 = u0; it.rv0 = v0; it.rw = u1 - u0; it.rh = v1 - v0;
+      it.pair = pair;
+      mine.push_back(it);
+      mine_cells.push_back(cells[q]);
+    }
+    std::vector<Tile> t;
+    TileCaps unused;
+    plan_tiles(c, mine.data(), (int)mine.size(), t, unused);
+    const size_t base = g.items.size();
+    for (size_t q = 0; q < mine.size(); ++q) {
+      g.items.push_back(mine[q]);
+      g.ci.push_back(mine_cells[q].first);
+      g.cj.push_back(mine_cells[q].second);
+      g.pair_part.push_back(hp);
+      g.tiles.emplace_back();
+      g.caps.emplace_back();
+      g.n_px += (int64_t)mine[q].rw * mine[q].rh;
+    }
+    for (Tile tl : t) {
+      const size_t q = base + (size_t)tl.item;
+      tl.item = 0;
+      TileCaps& cp = g.caps[q];
+      cp.wp = std::max(cp.wp, std::min(tl.tu1 + c->r, c->W) - std::max(tl.tu0 - c->r, 0));
+      cp.tw = std::max(cp.tw, tl.tu1 - tl.tu0);
+      const int wm = std::min(tl.tu1 + 2 * c->r, c->W) - std::max(tl.tu0 - 2 * c->r, 0);
+      cp.ws = std::max(cp.ws, std::max(wm, cp.wp));
+      g.tiles[q].push_back(tl);
+      g.n_tiles += 1;
+    }
+  }
+}
+
+// Orders a group plan largest region first (stable: ties keep pair order).
+void sort_group(GroupPlan& g) {
+  std::vector<size_t> ord(g.items.size());
+  for (size_t q = 0; q < ord.size(); ++q) ord[q] = q;
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
+    return (int64_t)g.items[x].rw * g.items[x].rh > (int64_t)g.items[y].rw * g.items[y].rh;
+  });
+  GroupPlan o;
+  o.n_px = g.n_px;
+  o.n_tiles = g.n_tiles;
+  for (size_t q : ord) {
+    o.items.push_back(g.items[q]);
+    o.ci.push_back(g.ci[q]);
+    o.cj.push_back(g.cj[q]);
+    o.pair_part.push_back(g.pair_part[q]);
+    o.tiles.push_back(std::move(g.tiles[q]));
+    o.caps.push_back(g.caps[q]);
+  }
+  g = std::move(o);
+}
+
+// Splits a group step into its two parts and writes their tiles (part 0 then
+// part 1) to the group's range of the tile table.  share < 0: every cut on
+// the host, the parts being the pairs' own splits.  Otherwise part 0 takes
+// that share of the regions the device max-flow can hold (every region of
+// part 0 is cut on the device) and part 1 the rest.
+void assign_parts(const RunPair* pairs, const GroupPlan& g, double share, Part* P, Tile* table) {
+  const lexp_ctx* c = pairs[0].c;
+  for (int hp = 0; hp < 2; ++hp) P[hp] = Part{};
+  std::vector<int> which(g.items.size());
+  double acc = 0.5;
+  for (size_t q = 0; q < g.items.size(); ++q) {
+    const Item& it = g.items[q];
+    if (share < 0) {
+      which[q] = g.pair_part[q];
+    } else if (cut_fits(c, (int64_t)it.rw * it.rh)) {
+      acc += share;
+      which[q] = acc >= 1.0 ? 0 : 1;
+      if (acc >= 1.0) acc -= 1.0;
+    } else {
+      which[q] = 1;
+    }
+  }
+  size_t t_at = g.tile_off;
+  for (int hp = 0; hp < 2; ++hp) {
+    Part& Q = P[hp];
+    Q.tile_off = t_at;
+    for (size_t q = 0; q < g.items.size(); ++q) {
+      if (which[q] != hp) continue;
+      Item it = g.items[q];
+      it.out_off = Q.n_px;
+      it.aux_off = Q.n_px;
+      Q.n_px += (int64_t)it.rw * it.rh;
+      Q.max_px = std::max(Q.max_px, it.rw * it.rh);
+      Q.bytes += item_alg_bytes(pairs[it.pair].c, it);
+      Q.caps.wp = std::max(Q.caps.wp, g.caps[q].wp);
+      Q.caps.tw = std::max(Q.caps.tw, g.caps[q].tw);
+      Q.caps.ws = std::max(Q.caps.ws, g.caps[q].ws);
+      const int idx = (int)Q.items.size();
+      for (Tile tl : g.tiles[q]) {
+        tl.item = idx;
+        table[t_at++] = tl;
+      }
+      Q.items.push_back(it);
+      Q.ci.push_back(g.ci[q]);
+      Q.cj.push_back(g.cj[q]);
+    }
+    Q.n_tiles = t_at - Q.tile_off;
+  }
+  P[0].device_cut = share >= 0 && !P[0].items.empty();
+}
+
+// Alg. 2 for the pairs of a run, with one set of launches per group step for
+// all pairs (the scratch, host pool and statistics of pairs[0]'s context).
+lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, double* time_trace, hipStream_t s) {
   if (sch->n_levels < 1 || sch->n_levels > 4 || sch->iterations < 0) return fail(LEXP_EINVAL, "bad schedule");
   for (int h = 0; h < sch->n_levels; ++h)
     if (sch->cell[h] < 1 || sch->k_prop[h] < 0 || sch->k_rand[h] < 0 || sch->k_prop[h] + sch->k_rand[h] > 64)
       return fail(LEXP_EINVAL, "bad grid level %d", h);
-  hipStream_t s = (hipStream_t)hip_stream;
+  lexp_ctx* c = pairs[0].c;
   const auto t_start = std::chrono::steady_clock::now();
   auto now_s = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(); };
-  const int W = c->W, H = c->H;
-  lexp_status st = wait_staging(c);
-  if (st) return st;
+  lexp_status st;
+  for (int p = 0; p < np; ++p)
+    if ((st = wait_staging(pairs[p].c))) return st;
+  HIP_TRY(c->d_run_pairs.ensure((size_t)np));
+  HIP_TRY(c->h_run_pairs.ensure((size_t)np));
+  for (int p = 0; p < np; ++p) c->h_run_pairs.p[p] = pair_entry(pairs[p].c, pairs[p].labels, pairs[p].cur_cost);
+  HIP_TRY(hipMemcpyAsync(c->d_run_pairs.p, c->h_run_pairs.p, sizeof(PairDev) * np, hipMemcpyHostToDevice, s));
+  const PairDev* d_pairs = c->d_run_pairs.p;
 
-  // Per (level, group, part): cells (Eq. (15): group 4 (j mod 4) + (i mod 4)),
-  // clipped 3x3-cell regions, compact offsets and tiles.  A group with more
-  // than four regions per host thread is split in two parts that overlap:
-  // one is cut while the device evaluates the other's next candidate, and
-  // with the device max-flow enabled (and regions that fit it) part 0 is cut
-  // on the device while the host cuts part 1.  Smaller groups are one part
-  // cut on the host, so that all threads cut at once.  Regions are ordered
-  // largest first for the host pool's dynamic schedule.
+  // Per (level, group): the regions of every pair and their tiles, split in
+  // two parts that overlap: one is cut while the device evaluates the other's
+  // next candidate.  With the device max-flow enabled, part 0 is cut on the
+  // device and part 1 on the host, in a proportion balanced per level after
+  // every iteration; otherwise both are cut on the host.
+  const bool dev_cut = c->prm.device_cut != 0;
+  std::vector<GroupPlan> groups((size_t)sch->n_levels * 16);
   std::vector<Part> parts((size_t)sch->n_levels * 16 * 2);
-  std::vector<Tile> all_tiles;
+  std::vector<CutBalance> balance((size_t)sch->n_levels);
+  size_t n_tiles = 0;
   int64_t max_px = 1;
   size_t max_items = 1;
-  for (int h = 0; h < sch->n_levels; ++h) {
-    const int cell = sch->cell[h];
-    const int nci = (W + cell - 1) / cell, ncj = (H + cell - 1) / cell;
+  for (int h = 0; h < sch->n_levels; ++h)
     for (int k = 0; k < 16; ++k) {
-      std::vector<std::pair<int, int>> cells;
-      for (int j = k / 4; j < ncj; j += 4)
-        for (int i = k % 4; i < nci; i += 4) cells.emplace_back(i, j);
-      std::stable_sort(cells.begin(), cells.end(), [&](const std::pair<int, int>& x, const std::pair<int, int>& y) {
-        auto area = [&](const std::pair<int, int>& q) {
-          lexp_rect rr{(q.first - 1) * cell, (q.second - 1) * cell, (q.first + 2) * cell, (q.second + 2) * cell};
-          int u0, v0, u1, v1;
-          clip_rect(c, rr, &u0, &v0, &u1, &v1);
-          return (int64_t)(u1 - u0) * (v1 - v0);
-        };
-        return area(x) > area(y);
-      });
-      int64_t max_area = 0;
-      for (const auto& q : cells) {
-        lexp_rect rr{(q.first - 1) * cell, (q.second - 1) * cell, (q.first + 2) * cell, (q.second + 2) * cell};
-        int u0, v0, u1, v1;
-        clip_rect(c, rr, &u0, &v0, &u1, &v1);
-        max_area = std::max<int64_t>(max_area, (int64_t)(u1 - u0) * (v1 - v0));
-      }
-      const bool split = cells.size() > (size_t)4 * c->pool->size();
-      const bool dev_part = split && c->prm.device_cut != 0 && cut_fits(c, max_area);
-      for (int hp = 0; hp < 2; ++hp) {
-        Part& P = parts[((size_t)h * 16 + k) * 2 + hp];
-        P.device_cut = dev_part && hp == 0;
-        // split: alternate cells between the parts (both keep largest first)
-        for (size_t q = split ? (size_t)hp : 0; q < (split || hp == 0 ? cells.size() : 0); q += split ? 2 : 1) {
-          const int i = cells[q].first, j = cells[q].second;
-          lexp_rect rr{(i - 1) * cell, (j - 1) * cell, (i + 2) * cell, (j + 2) * cell};
-          int u0, v0, u1, v1;
-          clip_rect(c, rr, &u0, &v0, &u1, &v1);
-          Item it{};
-          it.ru0 = u0; it.rv0 = v0; it.rw = u1 - u0; it.rh = v1 - v0;
-          it.out_off = P.n_px;
-          it.aux_off = P.n_px;
-          P.n_px += (int64_t)it.rw * it.rh;
-          P.max_px = std::max(P.max_px, it.rw * it.rh);
-          P.ci.push_back(i);
-          P.cj.push_back(j);
-          P.items.push_back(it);
-          P.bytes += item_alg_bytes(c, it);
-        }
-        std::vector<Tile> t;
-        plan_tiles(c, P.items.data(), (int)P.items.size(), t, P.caps);
-        P.tile_off = all_tiles.size();
-        P.n_tiles = t.size();
-        all_tiles.insert(all_tiles.end(), t.begin(), t.end());
-        max_px = std::max(max_px, P.n_px);
-        max_items = std::max(max_items, P.items.size());
-      }
+      GroupPlan& g = groups[(size_t)h * 16 + k];
+      for (int p = 0; p < np; ++p) plan_pair_group(pairs[p].c, p, sch->cell[h], k, g);
+      sort_group(g);
+      g.tile_off = n_tiles;
+      n_tiles += g.n_tiles;
+      max_px = std::max(max_px, g.n_px);
+      max_items = std::max(max_items, g.items.size());
     }
+  for (int h = 0; h < sch->n_levels; ++h) {
+    size_t regions = 0;
+    for (int k = 0; k < 16; ++k) regions += groups[(size_t)h * 16 + k].items.size();
+    balance[h].tune = dev_cut && regions > (size_t)16 * 4 * c->n_threads;
+    balance[h].share = balance[h].tune ? 0.5 : 0.0;
   }
-  HIP_TRY(c->d_tiles.ensure(all_tiles.size()));
-  HIP_TRY(c->h_tiles.ensure(all_tiles.size()));
-  std::copy(all_tiles.begin(), all_tiles.end(), c->h_tiles.p);
-  if (!all_tiles.empty())
-    HIP_TRY(hipMemcpyAsync(c->d_tiles.p, c->h_tiles.p, sizeof(Tile) * all_tiles.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(c->d_tiles.ensure(n_tiles));
+  HIP_TRY(c->h_tiles.ensure(n_tiles));
+  // Splits group step (h, k) with its level's current share unless it is
+  // split that way already, and uploads its tiles (the range was last read by
+  // the group's previous step, queued earlier on the same stream, and last
+  // copied before that step).
+  auto split_group = [&](int h, int k) -> lexp_status {
+    GroupPlan& g = groups[(size_t)h * 16 + k];
+    const double share = dev_cut ? balance[h].share : -1.0;
+    if (g.share == share) return LEXP_OK;
+    g.share = share;
+    assign_parts(pairs, g, share, &parts[((size_t)h * 16 + k) * 2], c->h_tiles.p);
+    if (g.n_tiles > 0)
+      HIP_TRY(hipMemcpyAsync(c->d_tiles.p + g.tile_off, c->h_tiles.p + g.tile_off, sizeof(Tile) * g.n_tiles,
+                             hipMemcpyHostToDevice, s));
+    return LEXP_OK;
+  };
   c->res_items = max_items;
 
   for (auto& B : c->part) {
@@ -1068,52 +1294,100 @@ extern "C" lexp_status lexp_optimize(lexp_ctx* c, const lexp_schedule* sch, uint
   }
 
   // Alg. 2 line 2: random initial labels and their per-pixel costs.
-  std::vector<float> mirror((size_t)W * H * 3);
-  if ((st = lexp_init_labels_host(W, H, c->prm.disp_max, seed, mirror.data()))) return st;
-  if ((st = upload_labels(c, mirror.data(), labels, s))) return st;
-  if ((st = pixel_costs_impl(c, labels, cur_cost, s))) return st;
-  if (energy_trace) {
-    if ((st = energy_impl(c, labels, cur_cost, &energy_trace[0], nullptr, nullptr, s))) return st;
+  for (int p = 0; p < np; ++p) {
+    RunPair& rp = pairs[p];
+    lexp_ctx* pc = rp.c;
+    rp.mirror.assign((size_t)pc->W * pc->H * 3, 0.f);
+    if ((st = lexp_init_labels_host(pc->W, pc->H, pc->prm.disp_max, rp.seed, rp.mirror.data()))) return st;
+    if ((st = upload_labels(pc, rp.mirror.data(), rp.labels, s))) return st;
+    if ((st = pixel_costs_impl(pc, rp.labels, rp.cur_cost, s))) return st;
+    if (rp.energy_trace)
+      if ((st = energy_impl(pc, rp.labels, rp.cur_cost, &rp.energy_trace[0], nullptr, nullptr, s))) return st;
   }
   if (time_trace) time_trace[0] = now_s();
 
-  double r_d = c->prm.disp_max / 2.0, r_n = 1.0;  // Alg. 2 line 3
+  double scale = 1.0;  // Alg. 2 line 3: (r_d, r_n) = (disp_max / 2, 1) times scale
   for (int it = 0; it < sch->iterations; ++it) {
     for (int h = 0; h < sch->n_levels; ++h) {
       const int K = sch->k_prop[h] + sch->k_rand[h];
-      const StepArgs a{seed, it, h, sch->cell[h], sch->k_prop[h], r_d, r_n, mirror.data()};
+      const StepArgs a{it, h, sch->cell[h], sch->k_prop[h], scale, pairs};
       for (int k = 0; k < 16; ++k) {
+        const auto g0 = std::chrono::steady_clock::now();
+        if ((st = split_group(h, k))) return st;
         Part* P[2] = {&parts[((size_t)h * 16 + k) * 2], &parts[((size_t)h * 16 + k) * 2 + 1]};
         // Alg. 1 for every cell of the group.  The cells are independent
-        // (Lemma 3), so the two halves run staggered: while the host cuts
-        // one half, the device evaluates the other half's next candidate.
+        // (Lemma 3), so the two parts run staggered: while the host cuts
+        // one part, the device evaluates the other part's next candidate.
         for (int hp = 0; hp < 2; ++hp)
           if (!P[hp]->items.empty() && K > 0) {
             Part& Q = *P[hp];
-            c->pool->parallel_for((int)Q.items.size(), [&](int q, int) { propose_item(c, Q, a, q, 0); });
-            if ((st = enqueue_part(c, Q, c->part[hp], c->d_tiles.p, labels, cur_cost, s))) return st;
+            pool_of(c).parallel_for((int)Q.items.size(), [&](int q, int) { propose_item(Q, a, q, 0); });
+            if ((st = enqueue_part(c, Q, c->part[hp], d_pairs, c->d_tiles.p, s))) return st;
           }
         for (int step = 0; step < K; ++step)
           for (int hp = 0; hp < 2; ++hp) {
             if (P[hp]->items.empty()) continue;
             const int next = step + 1 < K ? step + 1 : -1;
-            if ((st = finish_part(c, *P[hp], c->part[hp], a, next, mirror.data(), labels, cur_cost, s))) return st;
+            if ((st = finish_part(c, *P[hp], c->part[hp], a, next, d_pairs, s))) return st;
             if (next >= 0)
-              if ((st = enqueue_part(c, *P[hp], c->part[hp], c->d_tiles.p, labels, cur_cost, s))) return st;
+              if ((st = enqueue_part(c, *P[hp], c->part[hp], d_pairs, c->d_tiles.p, s))) return st;
           }
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - g0).count();
+        balance[h].update(ms / (double)std::max<int64_t>(1, groups[(size_t)h * 16 + k].n_px));
       }
     }
-    r_d *= 0.5;  // Alg. 2 line 12
-    r_n *= 0.5;
-    if (energy_trace) {
-      if ((st = energy_impl(c, labels, cur_cost, &energy_trace[it + 1], nullptr, nullptr, s))) return st;
+    scale *= 0.5;  // Alg. 2 line 12
+    for (int p = 0; p < np; ++p) {
+      RunPair& rp = pairs[p];
+      if (rp.energy_trace)
+        if ((st = energy_impl(rp.c, rp.labels, rp.cur_cost, &rp.energy_trace[it + 1], nullptr, nullptr, s)))
+          return st;
     }
     if (time_trace) time_trace[it + 1] = now_s();
   }
   HIP_TRY(hipStreamSynchronize(s));
-  HIP_TRY(hipEventRecord(c->staging_done, s));
+  for (int h = 0; h < 4; ++h) c->stats.device_cut_share[h] = dev_cut && h < sch->n_levels ? balance[h].share : 0.0;
+  for (int p = 0; p < np; ++p) HIP_TRY(hipEventRecord(pairs[p].c->staging_done, s));
   if (c->timing) collect_timing(c);
   return LEXP_OK;
+}
+
+}  // namespace
+
+extern "C" lexp_status lexp_optimize(lexp_ctx* c, const lexp_schedule* sch, uint64_t seed, float* labels,
+                                     float* cur_cost, double* energy_trace, double* time_trace, void* hip_stream) {
+  if (!c || !sch || !labels || !cur_cost) return fail(LEXP_EINVAL, "null argument");
+  RunPair rp;
+  rp.c = c;
+  rp.seed = seed;
+  rp.labels = labels;
+  rp.cur_cost = cur_cost;
+  rp.energy_trace = energy_trace;
+  return optimize_run(&rp, 1, sch, time_trace, (hipStream_t)hip_stream);
+}
+
+extern "C" lexp_status lexp_optimize_batch(int32_t n_pairs, lexp_ctx* const* ctxs, const lexp_schedule* sch,
+                                           const uint64_t* seeds, float* const* labels, float* const* cur_cost,
+                                           double* const* energy_traces, double* time_trace, void* hip_stream) {
+  if (n_pairs < 1) return fail(LEXP_EINVAL, "n_pairs must be at least 1");
+  if (!ctxs || !sch || !seeds || !labels || !cur_cost) return fail(LEXP_EINVAL, "null argument");
+  std::vector<RunPair> pairs((size_t)n_pairs);
+  for (int p = 0; p < n_pairs; ++p) {
+    if (!ctxs[p] || !labels[p] || !cur_cost[p]) return fail(LEXP_EINVAL, "null entry for pair %d", p);
+    const lexp_ctx* c0 = ctxs[0];
+    const lexp_ctx* c = ctxs[p];
+    if (c->r != c0->r || c->dp.nf != c0->dp.nf || c->lds_limit != c0->lds_limit)
+      return fail(LEXP_EINVAL, "pair %d: every context of a batch needs the same gf_radius and neighbourhood", p);
+    for (int q = 0; q < p; ++q)
+      if (ctxs[q] == c || labels[q] == labels[p] || cur_cost[q] == cur_cost[p])
+        return fail(LEXP_EINVAL, "pairs %d and %d share a context or an output buffer", q, p);
+    pairs[p].c = ctxs[p];
+    pairs[p].seed = seeds[p];
+    pairs[p].labels = labels[p];
+    pairs[p].cur_cost = cur_cost[p];
+    pairs[p].energy_trace = energy_traces ? energy_traces[p] : nullptr;
+  }
+  return optimize_run(pairs.data(), n_pairs, sch, time_trace, (hipStream_t)hip_stream);
 }
 
 extern "C" {

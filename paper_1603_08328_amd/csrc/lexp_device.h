@@ -23,10 +23,26 @@ struct DevParams {
   double lam, tau_dis, w_floor;    // smoothness term (FP64)
 };
 
-// One (region, label) item: clipped region, candidate label, output offset.
+// What the kernels read of one stereo pair: sizes and parameters, packed
+// images, guide statistics, contrast weights, and the label field and current
+// costs the expansion kernels update.  Kernels index a table of these by the
+// item's pair, so one launch can cover many pairs of different sizes.
+struct PairDev {
+  DevParams P;
+  const float4* left4;
+  const float4* left4T;
+  const float4* right4;
+  const float* guide;
+  const double* wts;
+  float4* labels;
+  float* cur_cost;
+};
+
+// One (region, label) item: pair, clipped region, candidate label, output offset.
 struct Item {
   int ru0, rv0, rw, rh;
-  float a, b, c, pad;
+  float a, b, c;
+  int pair;           // index into the launch's pair table
   long long out_off;  // first phi value of the item (caller layout)
   long long aux_off;  // first pixel of the item in the graph-term / cut buffers
 };
@@ -63,19 +79,16 @@ constexpr int kMaxWP = 128;
 constexpr int kMaxTW = 128;
 
 template <int MODE, int NSEG, int NC>
-__global__ void k_unary(DevParams P, const float4* left4, const float4* left4T, const float4* right4,
-                        const float* guide,
-                        const Item* items, const Tile* tiles, int n_tiles, const float4* label_field, float* out,
-                        int ring, int wp_cap, int tw_cap, int ws_cap);
+__global__ void k_unary(const PairDev* pairs, const Item* items, const Tile* tiles, int n_tiles,
+                        const float4* label_field, float* out, int ring, int wp_cap, int tw_cap, int ws_cap);
 __global__ void k_pack(const float* img, float4* out, float4* outT, int W, int H);
 __global__ void k_guide_h(const float4* left4, double* tmp, int W, int H, int r);
 __global__ void k_guide_v(const double* tmp, float* guide, int W, int H, int r, double eps);
 __global__ void k_guide_planes(const float* guide, float* planes, int W, int H);
 __global__ void k_weights(const float* left, double* wts, int W, int H, double gamma);
-__global__ void k_graph_terms(DevParams P, const Item* items, const float4* labels, const float* cur_cost,
-                              const float* phi_alpha, const double* wts, int* terms, int* flag);
-__global__ void k_apply(int W, const Item* items, const uint8_t* x, const float* phi_alpha, float4* labels,
-                        float* cur_cost);
+__global__ void k_graph_terms(const PairDev* pairs, const Item* items, const float* phi_alpha, int* terms,
+                              int* flag);
+__global__ void k_apply(const PairDev* pairs, const Item* items, const uint8_t* x, const float* phi_alpha);
 __global__ void k_energy(DevParams P, const float4* labels, const float* cur_cost, const double* wts,
                          double* partial);
 template <int BLOCK>

@@ -234,14 +234,23 @@ __device__ inline void load_rows2(RowTaps<NSEG>& tp, int y, int xm0, int wM, int
   }
 }
 
+// Entry i of a pair table, read through the constant address space: the
+// compiler then takes the pointers it holds for global memory and loads
+// through them with global (not flat) instructions.  The table is not written
+// while a kernel runs.  (The host pass only type-checks kernel bodies.)
+__device__ inline PairDev pair_of(const PairDev* pairs, int i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((const __attribute__((address_space(4))) PairDev*)pairs)[i];
+#else
+  return pairs[i];
+#endif
+}
+
 template <int MODE, int NSEG, int NC>
-__global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __restrict__ left4,
-                                               const float4* __restrict__ left4T,
-                                               const float4* __restrict__ right4, const float* __restrict__ guide,
-                                               const Item* __restrict__ items, const Tile* __restrict__ tiles,
-                                               int n_tiles, const float4* __restrict__ label_field,
-                                               float* __restrict__ out, int ring, int wp_cap, int tw_cap,
-                                               int ws_cap) {
+__global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pairs, const Item* __restrict__ items,
+                                               const Tile* __restrict__ tiles, int n_tiles,
+                                               const float4* __restrict__ label_field, float* __restrict__ out,
+                                               int ring, int wp_cap, int tw_cap, int ws_cap) {
   extern __shared__ float4 smem4[];
   // blocks are dispatched round-robin over the 8 XCDs; give every XCD a
   // contiguous run of tiles so neighbouring tiles share its L2
@@ -249,6 +258,19 @@ __global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __res
   const int t_id = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
   if (t_id >= n_tiles) return;
 
+  // MODE 2 covers every pixel of pair 0 (one 1x1 region per tile)
+  Tile tl{};
+  Item it{};
+  if (MODE != 2) {
+    tl = tiles[t_id];
+    it = items[tl.item];
+  }
+  const PairDev pd = pair_of(pairs, MODE == 2 ? 0 : it.pair);
+  const DevParams P = pd.P;
+  const float4* __restrict__ left4 = pd.left4;
+  const float4* __restrict__ left4T = pd.left4T;
+  const float4* __restrict__ right4 = pd.right4;
+  const float* __restrict__ guide = pd.guide;
   const int W = P.W, H = P.H, r = P.r;
   int tu0, tv0, tu1, tv1, ru0 = 0, rv0 = 0, rw = 1, flags = 15;
   float la, lb, lc;
@@ -260,8 +282,6 @@ __global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __res
     ru0 = tu0; rv0 = tv0; rw = 1;
     out_off = t_id;
   } else {
-    const Tile tl = tiles[t_id];
-    const Item it = items[tl.item];
     tu0 = tl.tu0; tv0 = tl.tv0; tu1 = tl.tu1; tv1 = tl.tv1; flags = tl.flags;
     la = it.a; lb = it.b; lc = it.c;
     ru0 = it.ru0; rv0 = it.rv0; rw = it.rw;
@@ -746,9 +766,8 @@ __global__ __launch_bounds__(1024) void k_unary(DevParams P, const float4* __res
 }
 
 #define LEXP_UNARY_INST(M, S, C)                                                                                    \
-  template __global__ void k_unary<M, S, C>(DevParams, const float4*, const float4*, const float4*, const float*,  \
-                                            const Item*, const Tile*, int, const float4*, float*, int, int, int,   \
-                                            int);
+  template __global__ void k_unary<M, S, C>(const PairDev*, const Item*, const Tile*, int, const float4*, float*, \
+                                            int, int, int, int);
 LEXP_UNARY_INST(0, 1, 1)
 LEXP_UNARY_INST(0, 2, 1)
 LEXP_UNARY_INST(0, 2, 2)
@@ -800,12 +819,15 @@ __device__ inline bool same_label(float4 a, float4 b) {
 
 // Binary problem of one local expansion per item: for every p in the region,
 // U_p (cost of taking alpha) and w_d (cost of x_p = 0, x_{p+fwd_d} = 1).
-__global__ void k_graph_terms(DevParams P, const Item* __restrict__ items, const float4* __restrict__ labels,
-                              const float* __restrict__ cur_cost, const float* __restrict__ phi_alpha,
-                              const double* __restrict__ wts, int* __restrict__ terms, int* __restrict__ flag) {
+__global__ void k_graph_terms(const PairDev* __restrict__ pairs, const Item* __restrict__ items,
+                              const float* __restrict__ phi_alpha, int* __restrict__ terms, int* __restrict__ flag) {
   const Item it = items[blockIdx.y];
   const int li = blockIdx.x * blockDim.x + threadIdx.x;
   if (li >= it.rw * it.rh) return;
+  const PairDev pd = pair_of(pairs, it.pair);
+  const DevParams P = pd.P;
+  const float4* __restrict__ labels = pd.labels;
+  const double* __restrict__ wts = pd.wts;
   const int W = P.W, H = P.H;
   const int pu = it.ru0 + li % it.rw, pv = it.rv0 + li / it.rw;
   const float4 fp = labels[(size_t)pv * W + pu];
@@ -815,7 +837,7 @@ __global__ void k_graph_terms(DevParams P, const Item* __restrict__ items, const
     o[0] = 0; o[1] = 0; o[2] = 0; o[3] = 0; o[4] = 0;
     return;
   }
-  long long U = qceil((double)phi_alpha[it.out_off + li]) - qceil((double)cur_cost[(size_t)pv * W + pu]);
+  long long U = qceil((double)phi_alpha[it.out_off + li]) - qceil((double)pd.cur_cost[(size_t)pv * W + pu]);
   long long wf[4] = {0, 0, 0, 0};
   const int nf = P.nf;
   for (int q = 0; q < 2 * nf; ++q) {
@@ -850,15 +872,17 @@ __global__ void k_graph_terms(DevParams P, const Item* __restrict__ items, const
 }
 
 // labels[p] = alpha and cur_cost[p] = phi_p(alpha) where the cut took alpha.
-__global__ void k_apply(int W, const Item* __restrict__ items, const uint8_t* __restrict__ x,
-                        const float* __restrict__ phi_alpha, float4* __restrict__ labels, float* __restrict__ cur_cost) {
+__global__ void k_apply(const PairDev* __restrict__ pairs, const Item* __restrict__ items,
+                        const uint8_t* __restrict__ x, const float* __restrict__ phi_alpha) {
   const Item it = items[blockIdx.y];
   const int li = blockIdx.x * blockDim.x + threadIdx.x;
   if (li >= it.rw * it.rh) return;
   if (!x[it.aux_off + li]) return;
+  const PairDev pd = pair_of(pairs, it.pair);
+  const int W = pd.P.W;
   const int pu = it.ru0 + li % it.rw, pv = it.rv0 + li / it.rw;
-  labels[(size_t)pv * W + pu] = make_float4(it.a, it.b, it.c, 0.f);
-  cur_cost[(size_t)pv * W + pu] = phi_alpha[it.out_off + li];
+  pd.labels[(size_t)pv * W + pu] = make_float4(it.a, it.b, it.c, 0.f);
+  pd.cur_cost[(size_t)pv * W + pu] = phi_alpha[it.out_off + li];
 }
 
 // Eq. (5): per-block partial sums (FP64) of the unary and pairwise parts.

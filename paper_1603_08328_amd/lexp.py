@@ -53,11 +53,13 @@ class lexp_stats(C.Structure):
                 ("unary_kernel_ms", C.c_double), ("unary_alg_bytes", C.c_double),
                 ("expand_calls", C.c_int64), ("host_cut_ms", C.c_double), ("host_wait_ms", C.c_double),
                 ("host_enqueue_ms", C.c_double), ("host_update_ms", C.c_double),
-                ("host_cut_level_ms", C.c_double * 4), ("device_cut_fallbacks", C.c_int64)]
+                ("host_cut_level_ms", C.c_double * 4), ("device_cut_fallbacks", C.c_int64),
+                ("device_cut_share", C.c_double * 4)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["host_cut_level_ms"] = list(d["host_cut_level_ms"])
+        d["device_cut_share"] = list(d["device_cut_share"])
         return d
 
 
@@ -76,6 +78,7 @@ _SIGS = {
     "lexp_energy": (_i32, [_vp, _vp, _vp, C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64), _vp]),
     "lexp_init_labels": (_i32, [_vp, _u64, _vp, _vp]),
     "lexp_optimize": (_i32, [_vp, C.POINTER(lexp_schedule), _u64, _vp, _vp, _vp, _vp, _vp]),
+    "lexp_optimize_batch": (_i32, [_i32, _vp, C.POINTER(lexp_schedule), _vp, _vp, _vp, _vp, _vp, _vp]),
     "lexp_set_timing": (_i32, [_vp, _i32]),
     "lexp_get_stats": (_i32, [_vp, C.POINTER(lexp_stats)]),
     "lexp_reset_stats": (_i32, [_vp]),
@@ -320,6 +323,28 @@ def lexp_optimize(ctx, grids, iterations, seed, labels, cur_cost, stream=None):
     t = np.zeros(iterations + 1)
     _check(load_library().lexp_optimize(ctx.handle, C.byref(sch), C.c_uint64(seed), lp, cp, e.ctypes.data,
                                         t.ctypes.data, _stream_ptr(stream)))
+    return e, t
+
+
+def lexp_optimize_batch(ctxs, grids, iterations, seeds, labels, cur_costs, stream=None):
+    """Alg. 2 for several pairs at once (one launch per group step for all of
+    them); returns (energy traces [n_pairs, iterations+1], time_trace)."""
+    torch = _torch()
+    n = len(ctxs)
+    if not (len(seeds) == len(labels) == len(cur_costs) == n):
+        raise ValueError("ctxs, seeds, labels and cur_costs need one entry per pair")
+    hs = (C.c_void_p * n)(*[c.handle for c in ctxs])
+    lp = (C.c_void_p * n)(*[_dev(l, torch.float32, (c.height, c.width, 4), name="labels")
+                            for c, l in zip(ctxs, labels)])
+    cp = (C.c_void_p * n)(*[_dev(q, torch.float32, (c.height, c.width), name="cur_cost")
+                            for c, q in zip(ctxs, cur_costs)])
+    sd = (C.c_uint64 * n)(*[int(x) for x in seeds])
+    sch = make_schedule(grids, iterations)
+    e = np.zeros((n, iterations + 1))
+    ep = (C.c_void_p * n)(*[e[i].ctypes.data for i in range(n)])
+    t = np.zeros(iterations + 1)
+    _check(load_library().lexp_optimize_batch(n, hs, C.byref(sch), sd, lp, cp, ep, t.ctypes.data,
+                                              _stream_ptr(stream)))
     return e, t
 
 

@@ -529,3 +529,101 @@ def test_optimize_device_and_host_cuts_identical(lowres):
     assert np.array_equal(out[0][0].view(np.uint32), out[1][0].view(np.uint32))
     assert np.array_equal(out[0][1].view(np.uint32), out[1][1].view(np.uint32))
     assert out[0][2][-1] == out[1][2][-1]
+
+
+# ---------------------------------------------------------------------------
+# Many pairs in one run: every group step of every pair in shared launches.
+def _scene(width, height, disp_max, seed, r, n_planar=4, n_quadric=0, holes=0.0):
+    from synth import make_pair, PAPER_PARAMS
+    sc = dict(width=width, height=height, n_planar=n_planar, n_quadric=n_quadric, disp_max=disp_max,
+              c_range=(disp_max / 8.0, 7.0 * disp_max / 8.0), hole_frac=holes, seed=seed)
+    pair = make_pair(**sc)
+    p = dict(PAPER_PARAMS, width=width, height=height, disp_max=disp_max, gf_radius=r)
+    return p, pair
+
+
+def _alone_and_batched(scenes, grids, iterations, seeds, **ctx_kw):
+    ctxs, alone = [], []
+    for (p, pair), sd in zip(scenes, seeds):
+        ctx = L.lexp_create(dict(p, **ctx_kw), _cuda(pair.left), _cuda(pair.right))
+        lab = torch.zeros((p["height"], p["width"], 4), device="cuda")
+        cost = torch.zeros((p["height"], p["width"]), device="cuda")
+        e, _ = L.lexp_optimize(ctx, grids, iterations, sd, lab, cost)
+        alone.append((lab.cpu().numpy(), cost.cpu().numpy(), e))
+        ctxs.append(ctx)
+    labs = [torch.full((p["height"], p["width"], 4), float("nan"), device="cuda") for p, _ in scenes]
+    costs = [torch.full((p["height"], p["width"]), float("nan"), device="cuda") for p, _ in scenes]
+    L.lexp_set_timing(ctxs[0], True)
+    L.lexp_reset_stats(ctxs[0])
+    es, ts = L.lexp_optimize_batch(ctxs, grids, iterations, seeds, labs, costs)
+    stats = L.lexp_get_stats(ctxs[0])
+    batched = [(l.cpu().numpy(), c.cpu().numpy(), e) for l, c, e in zip(labs, costs, es)]
+    for c in ctxs:
+        c.close()
+    assert np.all(np.diff(ts) >= 0)
+    return alone, batched, stats
+
+
+def _assert_same_runs(alone, batched):
+    for i, (a, b) in enumerate(zip(alone, batched)):
+        assert np.array_equal(a[0].view(np.uint32), b[0].view(np.uint32)), \
+            f"pair {i}: {np.any(a[0] != b[0], axis=-1).sum()} labels differ"
+        assert np.array_equal(a[1].view(np.uint32), b[1].view(np.uint32)), f"pair {i}: costs differ"
+        assert np.array_equal(a[2], b[2]), f"pair {i}: energy traces differ"
+
+
+@pytest.mark.parametrize("device_cut", [0, 1])
+def test_optimize_batch_equals_per_pair_runs_small_pairs(device_cut):
+    """Three pairs of uneven sizes (ragged cells, different disparity ranges),
+    r = 5, the tiny schedule, every cut on the host or part of them on the
+    device: each pair's labels, costs and energies in the batched run equal
+    its run alone, bit for bit; the 64x48 pair also equals the oracle's run."""
+    scenes = [_scene(64, 48, 16.0, 0, 5), _scene(97, 61, 20.0, 11, 5), _scene(37, 29, 9.0, 12, 5)]
+    tiny_p = params_for("tiny-64x48")
+    tiny_pair = make_workload_pair("tiny-64x48")
+    scenes[0] = (tiny_p, tiny_pair)
+    seeds = [0, 7, 2 ** 40 + 3]
+    # one host thread: groups of more than four regions are split and the
+    # device max-flow takes a tuned share of them
+    alone, batched, stats = _alone_and_batched(scenes, [(5, 1, 3)], 2, seeds, device_cut=device_cut,
+                                               host_threads=1 if device_cut else 0)
+    _assert_same_runs(alone, batched)
+    # one cost launch per group step and part, for all three pairs
+    if device_cut:
+        assert 16 * 4 * 2 <= stats["unary_launches"] <= 2 * 16 * 4 * 2
+        assert stats["device_cut_share"][0] > 0
+    else:
+        assert stats["unary_launches"] == 16 * 4 * 2
+    olab, _, oe, _ = Oracle(tiny_p, tiny_pair.left, tiny_pair.right).optimize(0, [(5, 1, 3)], 2)
+    assert np.array_equal(batched[0][0][..., :3].view(np.uint32), olab.view(np.uint32))
+    assert np.allclose(batched[0][2], oe, rtol=1e-5)
+    for e in (b[2] for b in batched):
+        assert np.all(np.diff(e) <= 0)
+
+
+def test_optimize_batch_with_device_cuts_equals_per_pair_runs(lowres):
+    """The 450x375 pair together with two smaller pairs of the many-pair
+    recipe (r = 20, three grid levels, one iteration): the level-1 groups are
+    split and cut partly on the device, the small pairs' groups are not; every
+    pair equals its run alone."""
+    from synth.workloads import many_pair_scenes
+    scenes = [(lowres.p, make_workload_pair("lowres-450x375"))]
+    for sc in many_pair_scenes(2, seed0=3000):
+        w = 320 + (sc["width"] - 320) // 8   # a smaller member of the same recipe
+        h = int(round(0.67 * w / 8.0)) * 8
+        scenes.append(_scene(w, h, float(round(0.13 * w)), sc["seed"], 20, 12, 2, 0.02))
+    alone, batched, stats = _alone_and_batched(scenes, [(5, 1, 7), (15, 1, 7), (25, 1, 7)], 1, [0, 1, 2])
+    _assert_same_runs(alone, batched)
+    assert stats["unary_launches"] > 0
+
+
+def test_optimize_batch_rejects_mixed_radius_and_shared_buffers(tiny):
+    p2, pair2 = _scene(40, 32, 10.0, 3, 4)
+    ctx2 = L.lexp_create(p2, _cuda(pair2.left), _cuda(pair2.right))
+    lab = [torch.zeros((tiny.H, tiny.W, 4), device="cuda"), torch.zeros((32, 40, 4), device="cuda")]
+    cost = [torch.zeros((tiny.H, tiny.W), device="cuda"), torch.zeros((32, 40), device="cuda")]
+    with pytest.raises(L.LexpError):
+        L.lexp_optimize_batch([tiny.ctx, ctx2], [(5, 1, 3)], 1, [0, 0], lab, cost)
+    with pytest.raises(L.LexpError):
+        L.lexp_optimize_batch([tiny.ctx, tiny.ctx], [(5, 1, 3)], 1, [0, 0], [lab[0], lab[0]], [cost[0], cost[0]])
+    ctx2.close()
