@@ -372,8 +372,11 @@ int cut_relabel_every(int max_px) {
   return max_px <= 512 ? 8 : 16;
 }
 
-// Whether the device max-flow holds a region of px nodes (its arrays live in LDS).
-bool cut_fits(const lexp_ctx* c, int64_t px) { return px * lexp::kCutBytesPerNode <= (int64_t)c->lds_limit; }
+// Whether the device max-flow holds a region of px nodes (its arrays live in
+// LDS, in the compact layout when the full one does not fit).
+bool cut_fits(const lexp_ctx* c, int64_t px) {
+  return px * lexp::kCutBytesCompact <= (int64_t)c->lds_limit - 64;
+}
 
 // Device minimum cuts of n regions whose terms start at the items' aux_off;
 // x at the same offsets, one status per item.  Every region must fit.
@@ -382,13 +385,17 @@ lexp_status launch_cut(lexp_ctx* c, const Item* d_items, int n, const int* d_ter
   if (n <= 0) return LEXP_OK;
   if (!cut_fits(c, max_px)) return fail(LEXP_ESTATE, "region of %d pixels too large for the device max-flow", max_px);
   const int nf = c->dp.nf;
-  const size_t lds = (size_t)max_px * lexp::kCutBytesPerNode;
   const int every = cut_relabel_every(max_px);
+  const size_t full = (size_t)max_px * lexp::kCutBytesFull;
   if (max_px <= 512)
-    hipLaunchKernelGGL(lexp::k_cut_lds<256>, dim3(n), dim3(256), lds, s, d_items, d_terms, nf, d_x, d_status, max_px,
-                       kCutRoundFactor, every);
+    hipLaunchKernelGGL((lexp::k_cut_lds<lexp::FullLayout, 256>), dim3(n), dim3(256), full, s, d_items, d_terms, nf,
+                       d_x, d_status, max_px, kCutRoundFactor, every);
+  else if (full + 64 <= c->lds_limit)
+    hipLaunchKernelGGL((lexp::k_cut_lds<lexp::FullLayout, 1024>), dim3(n), dim3(1024), full, s, d_items, d_terms,
+                       nf, d_x, d_status, max_px, kCutRoundFactor, every);
   else
-    hipLaunchKernelGGL(lexp::k_cut_lds<1024>, dim3(n), dim3(1024), lds, s, d_items, d_terms, nf, d_x, d_status, max_px,
+    hipLaunchKernelGGL((lexp::k_cut_lds<lexp::CompactLayout, 1024>), dim3(n), dim3(1024),
+                       (size_t)max_px * lexp::kCutBytesCompact, s, d_items, d_terms, nf, d_x, d_status, max_px,
                        kCutRoundFactor, every);
   HIP_TRY(hipGetLastError());
   return LEXP_OK;

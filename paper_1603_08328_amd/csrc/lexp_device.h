@@ -91,10 +91,15 @@ __global__ void k_graph_terms(const PairDev* pairs, const Item* items, const flo
 __global__ void k_apply(const PairDev* pairs, const Item* items, const uint8_t* x, const float* phi_alpha);
 __global__ void k_energy(DevParams P, const float4* labels, const float* cur_cost, const double* wts,
                          double* partial);
-template <int BLOCK>
+struct FullLayout;
+struct CompactLayout;
+template <class Layout, int BLOCK>
 __global__ void k_cut_lds(const Item* items, const int* terms, int nf, uint8_t* x, int* status, int max_nodes,
                           int round_factor, int relabel_every);
-constexpr int kCutBytesPerNode = 52;  // device max-flow arrays per node (LDS)
+// device max-flow arrays per node in LDS: all eight residuals and 64-bit
+// excess, or forward residuals only with 32-bit excess and 16-bit heights
+constexpr int kCutBytesFull = 52;
+constexpr int kCutBytesCompact = 28;
 __global__ void k_pair1(DevParams P, const double* wts, int pu, int pv, int qu, int qv, float4 fp, float4 fq,
                         double* out);
 

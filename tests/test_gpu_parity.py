@@ -449,18 +449,53 @@ def test_device_cut_equals_host_cut(tiny, kind):
         assert np.array_equal(x, L.lexp_solve_binary(U, w4)), (U.shape, kind)
 
 
-@pytest.mark.parametrize("shape", [(45, 45), (31, 64), (75, 75), (40, 120)])
+@pytest.mark.parametrize("shape", [(45, 45), (31, 64), (60, 60), (75, 75), (40, 120), (76, 77), (80, 80)])
 def test_device_cut_large_regions(tiny, shape):
-    """Regions whose arrays fit in LDS run on 1024 threads; larger ones are
-    not run (status 0, left to the host max-flow)."""
+    """Regions up to about 3,100 nodes keep all residuals in LDS, larger ones
+    up to about 5,850 nodes the compact layout (forward residuals, 32-bit
+    excess, 16-bit heights); still larger ones are not run (status 0, left to
+    the host max-flow)."""
     rng = np.random.default_rng(sum(shape))
-    probs = _binary_problems(rng, [shape], "generic", 2) + _binary_problems(rng, [shape], "sparse", 2)
+    probs = _binary_problems(rng, [shape], "generic", 2) + _binary_problems(rng, [shape], "sparse", 2) + \
+        _binary_problems(rng, [shape], "ties", 1)
     xs, status = L.lexp_solve_binary_device(tiny.ctx, probs)
-    fits = shape[0] * shape[1] * 52 <= 160 * 1024
+    fits = shape[0] * shape[1] * 28 <= 160 * 1024 - 64
     assert (status == (1 if fits else 0)).all()
     if fits:
         for (U, w4), x in zip(probs, xs):
             assert np.array_equal(x, L.lexp_solve_binary(U, w4))
+
+
+def test_device_cut_compact_layout_mixed_sizes_and_large_values(tiny):
+    """One launch with a 75x75 problem runs every problem in the compact
+    layout, small ones included.  Values near the 2^30 limit either solve
+    exactly or stop on excess overflow (status 0), never give a wrong cut."""
+    rng = np.random.default_rng(21)
+    probs = _binary_problems(rng, [(75, 75), (1, 1), (3, 5), (15, 15), (45, 45)], "generic", 1) + \
+        _binary_problems(rng, [(60, 70)], "huge", 3)
+    xs, status = L.lexp_solve_binary_device(tiny.ctx, probs)
+    assert status[:5].all()
+    for (U, w4), x, st in zip(probs, xs, status):
+        if st:
+            assert np.array_equal(x, L.lexp_solve_binary(U, w4))
+
+
+def test_device_cut_compact_layout_excess_overflow_is_left_to_host(tiny):
+    """Four arcs of capacity 2^30 into one node in the same round give it an
+    excess of 2^32, past the compact layout's 32-bit excess: the region must
+    stop with status 0 (it is then cut on the host)."""
+    h, w = 60, 60
+    U = np.zeros((h, w), np.int64)
+    w4 = np.zeros((h, w, 4), np.int64)
+    cu, cv = 30, 30
+    U[cv, cu] = -(2 ** 30)
+    for d, (du, dv) in enumerate([(1, 0), (0, 1), (1, 1), (-1, 1)]):
+        pu, pv = cu - du, cv - dv
+        U[pv, pu] = 2 ** 30
+        w4[pv, pu, d] = 2 ** 30
+    xs, status = L.lexp_solve_binary_device(tiny.ctx, [(U, w4)])
+    assert status[0] == 0
+    assert L.lexp_solve_binary(U, w4).sum() >= 0  # the host solves it
 
 
 def test_device_cut_of_real_expansion_problems(tiny):
