@@ -784,14 +784,138 @@ void ora_init_labels(const ora_ctx* c, uint64_t seed, float* labels) {
     }
 }
 
-/* Candidate label of one alpha_ij-expansion step (Alg. 1): a random pixel r
- * of the clipped centre cell; alpha = f_r, perturbed for refinement steps
- * (step >= k_prop) with the sizes halved once per refinement step already
+/* ---------------------------------------------------------------------------
+ * RANSAC proposer of Alg. 1 (between the propagation and refinement steps): a
+ * plane fitted to the current disparity map over the clipped centre cell
+ * C_ij by LO-RANSAC (Chum, Matas, Kittler 2003).  The paper names the method
+ * only; the readings:
+ *   - points: every pixel p of C_ij with its current disparity
+ *     d_p = a_p u + b_p v + c_p (FP64 from the FP32 label);
+ *   - RANS_HYP minimal samples; sample m takes pixels floor(U n) of draws
+ *     1 + 3m, 2 + 3m, 3 + 3m of the step's key (n pixels in the cell); a
+ *     sample with a repeated pixel, or whose three pixels are collinear in
+ *     the image, is skipped;
+ *   - plane through three points by the normal e1 x e2 of the edge vectors
+ *     from the first point: a = -n_u / n_d, b = -n_v / n_d,
+ *     c = d_0 - a u_0 - b v_0;
+ *   - inlier: |d_p - (a u + b v + c)| <= RANS_TAU;
+ *   - a sample with more inliers than the best so far is refined by local
+ *     optimisation: up to RANS_LO times, the least-squares plane of the
+ *     current inliers (centred normal equations) replaces the model if it
+ *     keeps at least as many inliers; the refined model becomes the best;
+ *   - no valid sample (fewer than three pixels, or all collinear): the label
+ *     of the pixel of draw 0, as the propagation proposer would choose it.
+ * ------------------------------------------------------------------------- */
+#define RANS_HYP 32
+#define RANS_TAU 1.0
+#define RANS_LO 4
+
+static int rans_inliers(const double* pu, const double* pv, const double* pd, int n, const double* m,
+                        unsigned char* in) {
+  int cnt = 0;
+  for (int i = 0; i < n; ++i) {
+    double pred = m[0] * pu[i] + m[1] * pv[i] + m[2];
+    in[i] = fabs(pd[i] - pred) <= RANS_TAU;
+    cnt += in[i];
+  }
+  return cnt;
+}
+
+/* least-squares plane d = a u + b v + c over the marked points; 0 if they are
+ * fewer than three or (nearly) collinear in the image */
+static int rans_lsq(const double* pu, const double* pv, const double* pd, int n, const unsigned char* in,
+                    double* m) {
+  double su = 0.0, sv = 0.0, sd = 0.0;
+  int k = 0;
+  for (int i = 0; i < n; ++i)
+    if (in[i]) { su += pu[i]; sv += pv[i]; sd += pd[i]; ++k; }
+  if (k < 3) return 0;
+  double mu = su / k, mv = sv / k, md = sd / k;
+  double suu = 0.0, suv = 0.0, svv = 0.0, sud = 0.0, svd = 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (!in[i]) continue;
+    double du = pu[i] - mu, dv = pv[i] - mv, dd = pd[i] - md;
+    suu += du * du; suv += du * dv; svv += dv * dv; sud += du * dd; svd += dv * dd;
+  }
+  double det = suu * svv - suv * suv;
+  if (!(det > 1e-9 * suu * svv)) return 0;
+  m[0] = (sud * svv - svd * suv) / det;
+  m[1] = (svd * suu - sud * suv) / det;
+  m[2] = md - m[0] * mu - m[1] * mv;
+  return 1;
+}
+
+/* Returns 1 and the fitted plane in alpha, or 0 when no sample is valid. */
+static int ora_ransac(const ora_ctx* c, const float* labels, uint64_t seed, const uint64_t* key6, int cu0, int cv0,
+                      int cw, int ch, float* alpha) {
+  int n = cw * ch;
+  if (n < 3) return 0;
+  double* pu = (double*)malloc(sizeof(double) * 3 * n);
+  double* pv = pu + n;
+  double* pd = pv + n;
+  unsigned char* in = (unsigned char*)malloc((size_t)2 * n);
+  unsigned char* tmp = in + n;
+  for (int i = 0; i < n; ++i) {
+    int u = cu0 + i % cw, v = cv0 + i / cw;
+    pu[i] = u;
+    pv[i] = v;
+    pd[i] = disp_at(labels + ((size_t)v * c->W + u) * 3, u, v);
+  }
+  uint64_t f[7];
+  memcpy(f, key6, sizeof(uint64_t) * 6);
+  int best = -1;
+  double bm[3] = {0.0, 0.0, 0.0};
+  for (int m = 0; m < RANS_HYP; ++m) {
+    int s[3];
+    for (int k = 0; k < 3; ++k) {
+      f[6] = (uint64_t)(1 + 3 * m + k);
+      int64_t idx = (int64_t)(u01(key_chain(seed, f, 7)) * (double)n);
+      if (idx >= n) idx = n - 1;
+      s[k] = (int)idx;
+    }
+    if (s[0] == s[1] || s[0] == s[2] || s[1] == s[2]) continue;
+    double e1u = pu[s[1]] - pu[s[0]], e1v = pv[s[1]] - pv[s[0]], e1d = pd[s[1]] - pd[s[0]];
+    double e2u = pu[s[2]] - pu[s[0]], e2v = pv[s[2]] - pv[s[0]], e2d = pd[s[2]] - pd[s[0]];
+    double nu = e1v * e2d - e1d * e2v;
+    double nv = e1d * e2u - e1u * e2d;
+    double nd = e1u * e2v - e1v * e2u;
+    if (nd == 0.0) continue;
+    double mdl[3];
+    mdl[0] = -nu / nd;
+    mdl[1] = -nv / nd;
+    mdl[2] = pd[s[0]] - mdl[0] * pu[s[0]] - mdl[1] * pv[s[0]];
+    int cnt = rans_inliers(pu, pv, pd, n, mdl, in);
+    if (cnt <= best) continue;
+    for (int it = 0; it < RANS_LO; ++it) {  /* local optimisation */
+      double ls[3];
+      if (!rans_lsq(pu, pv, pd, n, in, ls)) break;
+      int c2 = rans_inliers(pu, pv, pd, n, ls, tmp);
+      if (c2 < cnt) break;
+      memcpy(mdl, ls, sizeof(ls));
+      memcpy(in, tmp, (size_t)n);
+      cnt = c2;
+    }
+    best = cnt;
+    memcpy(bm, mdl, sizeof(bm));
+  }
+  free(pu);
+  free(in);
+  if (best < 0) return 0;
+  alpha[0] = (float)bm[0];
+  alpha[1] = (float)bm[1];
+  alpha[2] = (float)bm[2];
+  return 1;
+}
+
+/* Candidate label of one alpha_ij-expansion step (Alg. 1), in the order of
+ * Alg. 1: k_prop propagation steps (alpha = f_r for a random pixel r of the
+ * clipped centre cell), then k_rans RANSAC steps (above), then refinement
+ * steps: f_r perturbed with the sizes halved once per refinement step already
  * taken.  Perturbation: disparity d at r plus U[-r_d, r_d]; unit normal plus a
  * vector of length r_n uniform on the sphere, renormalised; converted back to
  * (a, b, c). */
 void ora_propose(const ora_ctx* c, const float* labels, uint64_t seed, int iteration, int level, int cell,
-                 int ci, int cj, int step, int k_prop, double r_d, double r_n, float* alpha) {
+                 int ci, int cj, int step, int k_prop, int k_rans, double r_d, double r_n, float* alpha) {
   int W = c->W, H = c->H;
   int cu0 = ci * cell, cv0 = cj * cell;
   int cu1 = imin(cu0 + cell, W), cv1 = imin(cv0 + cell, H);
@@ -803,7 +927,11 @@ void ora_propose(const ora_ctx* c, const float* labels, uint64_t seed, int itera
   int ru = cu0 + (int)(idx % cw), rv = cv0 + (int)(idx / cw);
   const float* fr = labels + ((size_t)rv * W + ru) * 3;
   if (step < k_prop) { memcpy(alpha, fr, sizeof(float) * 3); return; }
-  int halvings = step - k_prop;
+  if (step < k_prop + k_rans) {
+    if (!ora_ransac(c, labels, seed, f, cu0, cv0, cw, ch, alpha)) memcpy(alpha, fr, sizeof(float) * 3);
+    return;
+  }
+  int halvings = step - k_prop - k_rans;
   double rd = r_d, rn = r_n;
   for (int k = 0; k < halvings; ++k) { rd *= 0.5; rn *= 0.5; }
   f[6] = 1;
@@ -840,7 +968,8 @@ void ora_propose(const ora_ctx* c, const float* labels, uint64_t seed, int itera
 /* Runs Alg. 1 for every cell of group k of one grid level.  Returns the number
  * of cost evaluations (sum of |R| over the expansions). */
 int64_t ora_run_group(const ora_ctx* c, float* labels, double* costs, uint64_t seed, int iteration, int level,
-                      int cell, int k_prop, int k_rand, double r_d, double r_n, int group, int64_t* dEq) {
+                      int cell, int k_prop, int k_rans, int k_rand, double r_d, double r_n, int group,
+                      int64_t* dEq) {
   int W = c->W, H = c->H;
   int nci = (W + cell - 1) / cell, ncj = (H + cell - 1) / cell;
   int gi = group % 4, gj = group / 4;
@@ -854,9 +983,9 @@ int64_t ora_run_group(const ora_ctx* c, float* labels, double* costs, uint64_t s
     int u0 = (ci - 1) * cell, v0 = (cj - 1) * cell;
     int u1 = (ci + 2) * cell, v1 = (cj + 2) * cell;
     rect_t R = clip_dilate(c, u0, v0, u1, v1, 0);
-    for (int t = 0; t < k_prop + k_rand; ++t) {
+    for (int t = 0; t < k_prop + k_rans + k_rand; ++t) {
       float alpha[3];
-      ora_propose(c, labels, seed, iteration, level, cell, ci, cj, t, k_prop, r_d, r_n, alpha);
+      ora_propose(c, labels, seed, iteration, level, cell, ci, cj, t, k_prop, k_rans, r_d, r_n, alpha);
       de += ora_expand(c, labels, costs, R.u0, R.v0, R.u1, R.v1, alpha, 0, NULL);
       evals += (int64_t)(R.u1 - R.u0) * (R.v1 - R.v0);
     }
@@ -871,7 +1000,8 @@ int64_t ora_run_group(const ora_ctx* c, float* labels, double* costs, uint64_t s
  * iteration.  Returns the number of cost evaluations including the per-pixel
  * initial costs. */
 int64_t ora_optimize(const ora_ctx* c, uint64_t seed, int n_levels, const int* cells, const int* k_prop,
-                     const int* k_rand, int iterations, float* labels, double* costs, double* energy) {
+                     const int* k_rans, const int* k_rand, int iterations, float* labels, double* costs,
+                     double* energy) {
   ora_init_labels(c, seed, labels);
   ora_pixel_costs(c, labels, NULL, costs);
   int64_t evals = (int64_t)c->W * c->H;
@@ -880,7 +1010,8 @@ int64_t ora_optimize(const ora_ctx* c, uint64_t seed, int n_levels, const int* c
   for (int it = 0; it < iterations; ++it) {
     for (int h = 0; h < n_levels; ++h)
       for (int k = 0; k < 16; ++k)
-        evals += ora_run_group(c, labels, costs, seed, it, h, cells[h], k_prop[h], k_rand[h], r_d, r_n, k, NULL);
+        evals += ora_run_group(c, labels, costs, seed, it, h, cells[h], k_prop[h], k_rans[h], k_rand[h], r_d, r_n, k,
+                               NULL);
     r_d *= 0.5;
     r_n *= 0.5;
     if (energy) energy[it + 1] = ora_energy(c, labels, costs, NULL, NULL);

@@ -73,13 +73,13 @@ def lib():
     L.ora_rng_key.argtypes = [C.c_uint64, _P(np.uint64), C.c_int]
     L.ora_init_labels.argtypes = [vp, C.c_uint64, f32]
     L.ora_propose.argtypes = [vp, f32, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
-                              C.c_int, C.c_int, C.c_double, C.c_double, f32]
+                              C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, f32]
     L.ora_run_group.restype = C.c_int64
     L.ora_run_group.argtypes = [vp, f32, f64, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int,
-                                C.c_int, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_int64)]
+                                C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_int64)]
     L.ora_optimize.restype = C.c_int64
     L.ora_optimize.argtypes = [vp, C.c_uint64, C.c_int, _P(np.int32), _P(np.int32), _P(np.int32),
-                               C.c_int, f32, f64, vp]
+                               _P(np.int32), C.c_int, f32, f64, vp]
     L.ora_num_threads.restype = C.c_int
     _lib = L
     return L
@@ -262,27 +262,31 @@ class Oracle:
         self._L.ora_init_labels(self.ctx, C.c_uint64(seed), out)
         return out
 
-    def propose(self, labels, seed, iteration, level, cell, ci, cj, step, k_prop, r_d, r_n):
+    def propose(self, labels, seed, iteration, level, cell, ci, cj, step, k_prop, r_d, r_n, k_rans=0):
+        """Candidate of step `step` of Alg. 1: propagation for step < k_prop,
+        RANSAC for the next k_rans steps, refinement after."""
         out = np.zeros(3, dtype=np.float32)
         self._L.ora_propose(self.ctx, np.ascontiguousarray(labels, dtype=np.float32), C.c_uint64(seed),
-                            iteration, level, cell, ci, cj, step, k_prop, float(r_d), float(r_n), out)
+                            iteration, level, cell, ci, cj, step, k_prop, k_rans, float(r_d), float(r_n), out)
         return out
 
-    def run_group(self, labels, costs, seed, iteration, level, cell, k_prop, k_rand, r_d, r_n, group):
+    def run_group(self, labels, costs, seed, iteration, level, cell, k_prop, k_rand, r_d, r_n, group, k_rans=0):
         de = C.c_int64(0)
         ev = self._L.ora_run_group(self.ctx, labels, costs, C.c_uint64(seed), iteration, level, cell,
-                                   k_prop, k_rand, float(r_d), float(r_n), group, C.byref(de))
+                                   k_prop, k_rans, k_rand, float(r_d), float(r_n), group, C.byref(de))
         return ev, de.value
 
     def optimize(self, seed, grids, iterations):
+        """grids: (cell, K_prop, K_rand) or (cell, K_prop, K_rand, K_RANS) per level."""
         n = len(grids)
         cells = np.array([g[0] for g in grids], dtype=np.int32)
         kp = np.array([g[1] for g in grids], dtype=np.int32)
         kr = np.array([g[2] for g in grids], dtype=np.int32)
+        ks = np.array([g[3] if len(g) > 3 else 0 for g in grids], dtype=np.int32)
         labels = np.zeros((self.H, self.W, 3), dtype=np.float32)
         costs = np.zeros((self.H, self.W))
         energy = np.zeros(iterations + 1)
-        ev = self._L.ora_optimize(self.ctx, C.c_uint64(seed), n, cells, kp, kr, iterations, labels, costs,
+        ev = self._L.ora_optimize(self.ctx, C.c_uint64(seed), n, cells, kp, ks, kr, iterations, labels, costs,
                                   energy.ctypes.data)
         return labels, costs, energy, ev
 
