@@ -61,7 +61,7 @@ def _traffic_from_profile():
         return None
 
 
-def run_gpu(steps: int, warmup: int, seed: int = 0):
+def run_gpu(steps: int, warmup: int, seed: int = 0, k_rans: int = 0):
     import torch
 
     import paper_1603_08328_amd.lexp as L
@@ -81,7 +81,8 @@ def run_gpu(steps: int, warmup: int, seed: int = 0):
     def one_step(timing):
         ctx = L.lexp_create(prm, left, right, stream)
         L.lexp_set_timing(ctx, timing)
-        e, t = L.lexp_optimize(ctx, wl["grids"], wl["iterations"], seed, labels, cost, stream)
+        grids = [tuple(g) + (k_rans,) for g in wl["grids"]]
+        e, t = L.lexp_optimize(ctx, grids, wl["iterations"], seed, labels, cost, stream)
         st = L.lexp_get_stats(ctx)
         ctx.close()
         return e, t, st
@@ -259,6 +260,8 @@ def main():
                     help="instead: the uneven-size many-pair workload with this many pairs, pair by pair and "
                          "batched (one JSON line with both)")
     ap.add_argument("--iterations", type=int, default=10, help="iterations of the many-pair runs")
+    ap.add_argument("--k-rans", type=int, default=0,
+                    help="RANSAC proposer steps per cell and level (Alg. 1; 0 in the workload as specified)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path runs on a single "
@@ -283,7 +286,7 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-    g = run_gpu(args.steps, args.warmup)
+    g = run_gpu(args.steps, args.warmup, k_rans=args.k_rans)
     ms = g["elapsed"] / args.steps * 1e3
     value = g["evals"] / g["elapsed"] / 1e9
     achieved = g["kernel_bytes"] / (g["kernel_ms"] / 1e3) / 1e9 if g["kernel_ms"] > 0 else 0.0
@@ -308,7 +311,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "450x375 synthetic pair, 12 planar + 2 quadric segments, 2% holes, "
                                "disparity [0,60], guided-filter radius 20, cells 5/15/25, 10 iterations, "
-                               "{K_prop,K_rand}={1,7}",
+                               "{K_prop,K_rand}={1,7}" + (f", K_RANS={args.k_rans}" if args.k_rans else ""),
                    "evals_per_step": g["evals"] // args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
@@ -320,6 +323,7 @@ def main():
         "time_to_final_energy_s": g["times"][-1],
         "final_energy": g["final_energy"],
         "energy_trace": [round(x, 3) for x in g["energy"]],
+        "time_trace_s": [round(x, 4) for x in g["times"]],
         "kernel_evals_per_s": (g["evals"] / (g["kernel_ms"] / 1e3) / 1e9) if g["kernel_ms"] > 0 else None,
         "host_threads": len(os.sched_getaffinity(0)), "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
         "host_cut_ms_per_step": g["stats"]["host_cut_ms"],

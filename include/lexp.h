@@ -82,13 +82,16 @@ typedef struct {
 } lexp_params;
 
 /* Grid levels of the optimisation procedure (Alg. 2): cell size in pixels and
- * the proposer counts of Alg. 1 per level. */
+ * the proposer counts of Alg. 1 per level, run in Alg. 1's order: k_prop
+ * propagation, k_rans RANSAC (LO-RANSAC plane fit to the current disparities
+ * of the centre cell), k_rand refinement steps (k_prop + k_rans + k_rand <= 64). */
 typedef struct {
   int32_t n_levels; /* 1..4 */
   int32_t cell[4];
   int32_t k_prop[4];
   int32_t k_rand[4];
   int32_t iterations;
+  int32_t k_rans[4];
 } lexp_schedule;
 
 /* Counters of the hot kernel, accumulated while timing is enabled. */
@@ -261,14 +264,16 @@ uint64_t lexp_rng_key(uint64_t seed, const uint64_t* fields, int32_t n_fields);
 lexp_status lexp_init_labels_host(int32_t width, int32_t height, double disp_max, uint64_t seed,
                                   float* labels_hw3);
 
-/* Candidate label of one alpha_ij-expansion step (Alg. 1): random pixel r of
- * the clipped centre cell (ci, cj) of a grid with cells of `cell` pixels;
- * alpha = f_r for step < k_prop, otherwise f_r perturbed (Sec. 3.4) with
- * sizes (r_d, r_n) halved once per refinement step already taken.
- * labels_hw3: host HxWx3 float32. */
+/* Candidate label of one alpha_ij-expansion step (Alg. 1) for the clipped
+ * centre cell (ci, cj) of a grid with cells of `cell` pixels, r a random
+ * pixel of that cell: alpha = f_r for step < k_prop; for the next k_rans
+ * steps the LO-RANSAC plane of the cell's current disparities (f_r where the
+ * cell defines no plane: fewer than three pixels, or all in one row or
+ * column); after that f_r perturbed (Sec. 3.4) with sizes (r_d, r_n) halved
+ * once per refinement step already taken.  labels_hw3: host HxWx3 float32. */
 lexp_status lexp_propose(int32_t width, int32_t height, const float* labels_hw3, uint64_t seed,
                          int32_t iteration, int32_t level, int32_t cell, int32_t ci, int32_t cj, int32_t step,
-                         int32_t k_prop, double r_d, double r_n, lexp_plane* out);
+                         int32_t k_prop, int32_t k_rans, double r_d, double r_n, lexp_plane* out);
 
 #ifdef __cplusplus
 }

@@ -942,7 +942,7 @@ struct CutBalance {
 };
 
 struct StepArgs {
-  int it, level, cell, kp;
+  int it, level, cell, kp, kr;  // kr: RANSAC steps of the level (after its kp propagation steps)
   double scale;  // 0.5^it: the iteration's perturbation sizes relative to the first (Alg. 2)
   RunPair* pairs;
 };
@@ -954,7 +954,7 @@ void propose_item(Part& P, const StepArgs& a, int q, int step) {
   const lexp_ctx* c = rp.c;
   float al[3];
   lexp::propose(c->W, c->H, rp.mirror.data(), 3, rp.seed, a.it, a.level, a.cell, P.ci[q], P.cj[q], step, a.kp,
-                c->prm.disp_max / 2.0 * a.scale, a.scale, al);
+                a.kr, c->prm.disp_max / 2.0 * a.scale, a.scale, al);
   item.a = al[0];
   item.b = al[1];
   item.c = al[2];
@@ -1224,7 +1224,8 @@ void assign_parts(const RunPair* pairs, const GroupPlan& g, double share, Part* 
 lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, double* time_trace, hipStream_t s) {
   if (sch->n_levels < 1 || sch->n_levels > 4 || sch->iterations < 0) return fail(LEXP_EINVAL, "bad schedule");
   for (int h = 0; h < sch->n_levels; ++h)
-    if (sch->cell[h] < 1 || sch->k_prop[h] < 0 || sch->k_rand[h] < 0 || sch->k_prop[h] + sch->k_rand[h] > 64)
+    if (sch->cell[h] < 1 || sch->k_prop[h] < 0 || sch->k_rand[h] < 0 || sch->k_rans[h] < 0 ||
+        sch->k_prop[h] + sch->k_rans[h] + sch->k_rand[h] > 64)
       return fail(LEXP_EINVAL, "bad grid level %d", h);
   lexp_ctx* c = pairs[0].c;
   const auto t_start = std::chrono::steady_clock::now();
@@ -1316,8 +1317,8 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
   double scale = 1.0;  // Alg. 2 line 3: (r_d, r_n) = (disp_max / 2, 1) times scale
   for (int it = 0; it < sch->iterations; ++it) {
     for (int h = 0; h < sch->n_levels; ++h) {
-      const int K = sch->k_prop[h] + sch->k_rand[h];
-      const StepArgs a{it, h, sch->cell[h], sch->k_prop[h], scale, pairs};
+      const int K = sch->k_prop[h] + sch->k_rans[h] + sch->k_rand[h];
+      const StepArgs a{it, h, sch->cell[h], sch->k_prop[h], sch->k_rans[h], scale, pairs};
       for (int k = 0; k < 16; ++k) {
         const auto g0 = std::chrono::steady_clock::now();
         if ((st = split_group(h, k))) return st;
@@ -1522,11 +1523,12 @@ lexp_status lexp_init_labels_host(int32_t width, int32_t height, double disp_max
 
 lexp_status lexp_propose(int32_t width, int32_t height, const float* labels, uint64_t seed, int32_t iteration,
                          int32_t level, int32_t cell, int32_t ci, int32_t cj, int32_t step, int32_t k_prop,
-                         double r_d, double r_n, lexp_plane* out) {
+                         int32_t k_rans, double r_d, double r_n, lexp_plane* out) {
   if (width <= 0 || height <= 0 || !labels || !out || cell < 1) return fail(LEXP_EINVAL, "bad argument");
   if (ci < 0 || cj < 0 || ci * cell >= width || cj * cell >= height) return fail(LEXP_EINVAL, "cell outside the image");
   float a[3];
-  lexp::propose(width, height, labels, 3, seed, iteration, level, cell, ci, cj, step, k_prop, r_d, r_n, a);
+  if (k_prop < 0 || k_rans < 0) return fail(LEXP_EINVAL, "negative proposer count");
+  lexp::propose(width, height, labels, 3, seed, iteration, level, cell, ci, cj, step, k_prop, k_rans, r_d, r_n, a);
   out->a = a[0];
   out->b = a[1];
   out->c = a[2];

@@ -7,6 +7,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 namespace lexp {
 
@@ -58,8 +59,132 @@ static double plane_at(const float* f, int u, int v) {
   return s + (double)f[2];
 }
 
+// RANSAC proposer (Alg. 1): LO-RANSAC (Chum, Matas, Kittler 2003) plane fit
+// d = a u + b v + c to the current disparities of the clipped centre cell.
+// kRansSamples minimal samples, pixel k of sample m from draw 1 + 3m + k of
+// the step's key; a sample with a repeated pixel or collinear pixels is
+// skipped.  A sample plane comes from the normal (e1 x e2) of the edge
+// vectors from its first point; inliers are within kRansTau in disparity.  A
+// sample that beats the best inlier count is refined up to kRansLocal times
+// by the least-squares plane of its inliers (centred normal equations), kept
+// while the inlier count does not fall.  Returns false when no sample is
+// valid.
+namespace {
+
+constexpr int kRansSamples = 32;
+constexpr double kRansTau = 1.0;
+constexpr int kRansLocal = 4;
+
+struct CellPoints {
+  std::vector<double> u, v, d;
+  int n = 0;
+
+  int count(const double m[3], std::vector<unsigned char>& in) const {
+    int k = 0;
+    for (int i = 0; i < n; ++i) {
+      const double pred = m[0] * u[i] + m[1] * v[i] + m[2];
+      in[i] = std::fabs(d[i] - pred) <= kRansTau ? 1 : 0;
+      k += in[i];
+    }
+    return k;
+  }
+
+  bool least_squares(const std::vector<unsigned char>& in, double m[3]) const {
+    double su = 0.0, sv = 0.0, sd = 0.0;
+    int k = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!in[i]) continue;
+      su += u[i];
+      sv += v[i];
+      sd += d[i];
+      ++k;
+    }
+    if (k < 3) return false;
+    const double mu = su / k, mv = sv / k, md = sd / k;
+    double suu = 0.0, suv = 0.0, svv = 0.0, sud = 0.0, svd = 0.0;
+    for (int i = 0; i < n; ++i) {
+      if (!in[i]) continue;
+      const double du = u[i] - mu, dv = v[i] - mv, dd = d[i] - md;
+      suu += du * du;
+      suv += du * dv;
+      svv += dv * dv;
+      sud += du * dd;
+      svd += dv * dd;
+    }
+    const double det = suu * svv - suv * suv;
+    if (!(det > 1e-9 * suu * svv)) return false;
+    m[0] = (sud * svv - svd * suv) / det;
+    m[1] = (svd * suu - sud * suv) / det;
+    m[2] = md - m[0] * mu - m[1] * mv;
+    return true;
+  }
+};
+
+}  // namespace
+
+static bool ransac_plane(int width, const float* labels, int stride, uint64_t seed, uint64_t key[7], int cu0,
+                         int cv0, int cw, int chh, float out[3]) {
+  CellPoints P;
+  P.n = cw * chh;
+  if (P.n < 3) return false;
+  P.u.resize(P.n);
+  P.v.resize(P.n);
+  P.d.resize(P.n);
+  for (int i = 0; i < P.n; ++i) {
+    const int u = cu0 + i % cw, v = cv0 + i / cw;
+    P.u[i] = u;
+    P.v[i] = v;
+    P.d[i] = plane_at(labels + ((size_t)v * width + u) * stride, u, v);
+  }
+  std::vector<unsigned char> in(P.n), trial(P.n);
+  int best = -1;
+  double bm[3] = {0.0, 0.0, 0.0};
+  for (int m = 0; m < kRansSamples; ++m) {
+    int s[3];
+    for (int k = 0; k < 3; ++k) {
+      key[6] = (uint64_t)(1 + 3 * m + k);
+      int64_t idx = (int64_t)(u01_open1(key_chain(seed, key, 7)) * (double)P.n);
+      if (idx >= P.n) idx = P.n - 1;
+      s[k] = (int)idx;
+    }
+    if (s[0] == s[1] || s[0] == s[2] || s[1] == s[2]) continue;
+    const double e1u = P.u[s[1]] - P.u[s[0]], e1v = P.v[s[1]] - P.v[s[0]], e1d = P.d[s[1]] - P.d[s[0]];
+    const double e2u = P.u[s[2]] - P.u[s[0]], e2v = P.v[s[2]] - P.v[s[0]], e2d = P.d[s[2]] - P.d[s[0]];
+    const double nu = e1v * e2d - e1d * e2v;
+    const double nv = e1d * e2u - e1u * e2d;
+    const double nd = e1u * e2v - e1v * e2u;
+    if (nd == 0.0) continue;
+    double mdl[3];
+    mdl[0] = -nu / nd;
+    mdl[1] = -nv / nd;
+    mdl[2] = P.d[s[0]] - mdl[0] * P.u[s[0]] - mdl[1] * P.v[s[0]];
+    int cnt = P.count(mdl, in);
+    if (cnt <= best) continue;
+    for (int r = 0; r < kRansLocal; ++r) {
+      double ls[3];
+      if (!P.least_squares(in, ls)) break;
+      const int c2 = P.count(ls, trial);
+      if (c2 < cnt) break;
+      mdl[0] = ls[0];
+      mdl[1] = ls[1];
+      mdl[2] = ls[2];
+      in.swap(trial);
+      cnt = c2;
+    }
+    best = cnt;
+    bm[0] = mdl[0];
+    bm[1] = mdl[1];
+    bm[2] = mdl[2];
+  }
+  if (best < 0) return false;
+  out[0] = (float)bm[0];
+  out[1] = (float)bm[1];
+  out[2] = (float)bm[2];
+  return true;
+}
+
 void propose(int width, int height, const float* labels, int stride, uint64_t seed, int iteration, int level,
-             int cell, int ci, int cj, int step, int k_prop, double r_d, double r_n, float out[3]) {
+             int cell, int ci, int cj, int step, int k_prop, int k_rans, double r_d, double r_n, float out[3]) {
   const int cu0 = ci * cell, cv0 = cj * cell;
   const int cw = std::min(cu0 + cell, width) - cu0;
   const int chh = std::min(cv0 + cell, height) - cv0;
@@ -71,12 +196,14 @@ void propose(int width, int height, const float* labels, int stride, uint64_t se
   const int ru = cu0 + (int)(idx % cw);
   const int rv = cv0 + (int)(idx / cw);
   const float* fr = labels + ((size_t)rv * width + ru) * stride;
-  if (step < k_prop) {
+  if (step < k_prop || (step < k_prop + k_rans && !ransac_plane(width, labels, stride, seed, key, cu0, cv0, cw, chh,
+                                                                   out))) {
     out[0] = fr[0]; out[1] = fr[1]; out[2] = fr[2];
     return;
   }
+  if (step < k_prop + k_rans) return;
   double rd = r_d, rn = r_n;
-  for (int k = 0; k < step - k_prop; ++k) { rd *= 0.5; rn *= 0.5; }
+  for (int k = 0; k < step - k_prop - k_rans; ++k) { rd *= 0.5; rn *= 0.5; }
   key[6] = 1;
   const double dd = (2.0 * u01_open1(key_chain(seed, key, 7)) - 1.0) * rd;
   key[6] = 2;

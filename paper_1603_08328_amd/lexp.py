@@ -45,7 +45,7 @@ class lexp_rect(C.Structure):
 
 class lexp_schedule(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("cell", C.c_int32 * 4), ("k_prop", C.c_int32 * 4),
-                ("k_rand", C.c_int32 * 4), ("iterations", C.c_int32)]
+                ("k_rand", C.c_int32 * 4), ("iterations", C.c_int32), ("k_rans", C.c_int32 * 4)]
 
 
 class lexp_stats(C.Structure):
@@ -87,7 +87,7 @@ _SIGS = {
     "lexp_solve_binary_device": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "lexp_rng_key": (_u64, [_u64, _vp, _i32]),
     "lexp_init_labels_host": (_i32, [_i32, _i32, _f64, _u64, _vp]),
-    "lexp_propose": (_i32, [_i32, _i32, _vp, _u64, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _f64, _f64,
+    "lexp_propose": (_i32, [_i32, _i32, _vp, _u64, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _f64, _f64,
                             C.POINTER(lexp_plane)]),
 }
 
@@ -307,8 +307,9 @@ def make_schedule(grids, iterations) -> lexp_schedule:
     if not 1 <= len(grids) <= 4:
         raise ValueError("1 to 4 grid levels")
     s.n_levels = len(grids)
-    for i, (cell, kp, kr) in enumerate(grids):
-        s.cell[i], s.k_prop[i], s.k_rand[i] = int(cell), int(kp), int(kr)
+    for i, g in enumerate(grids):  # (cell, K_prop, K_rand) or (cell, K_prop, K_rand, K_RANS)
+        s.cell[i], s.k_prop[i], s.k_rand[i] = int(g[0]), int(g[1]), int(g[2])
+        s.k_rans[i] = int(g[3]) if len(g) > 3 else 0
     s.iterations = int(iterations)
     return s
 
@@ -424,11 +425,12 @@ def lexp_init_labels_host(width, height, disp_max, seed) -> np.ndarray:
     return out
 
 
-def lexp_propose(labels_hw3, seed, iteration, level, cell, ci, cj, step, k_prop, r_d, r_n) -> np.ndarray:
+def lexp_propose(labels_hw3, seed, iteration, level, cell, ci, cj, step, k_prop, r_d, r_n,
+                 k_rans=0) -> np.ndarray:
     lab = np.ascontiguousarray(np.asarray(labels_hw3, dtype=np.float32))
     h, w = lab.shape[:2]
     out = lexp_plane()
     _check(load_library().lexp_propose(w, h, lab.ctypes.data, C.c_uint64(seed), int(iteration), int(level),
-                                       int(cell), int(ci), int(cj), int(step), int(k_prop), float(r_d),
-                                       float(r_n), C.byref(out)))
+                                       int(cell), int(ci), int(cj), int(step), int(k_prop), int(k_rans),
+                                       float(r_d), float(r_n), C.byref(out)))
     return np.array([out.a, out.b, out.c], np.float32)

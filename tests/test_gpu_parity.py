@@ -410,6 +410,23 @@ def test_optimize_tiny_bit_identical_to_oracle(tiny):
     assert torch.equal(lab, lab2) and torch.equal(cost, cost2)
 
 
+def test_optimize_tiny_with_ransac_bit_identical_to_oracle(tiny):
+    """Alg. 1 with the RANSAC proposer enabled (one propagation, one RANSAC
+    and two refinement steps per cell): labels bit-identical to the oracle's
+    run, energies to 1e-5."""
+    P = tiny
+    grids = [(5, 1, 2, 1)]
+    lab = torch.zeros((P.H, P.W, 4), device="cuda")
+    cost = torch.zeros((P.H, P.W), device="cuda")
+    e, _ = L.lexp_optimize(P.ctx, grids, 2, 3, lab, cost)
+    olab, ocost, oe, _ = P.ora.optimize(3, grids, 2)
+    g3 = lab.cpu().numpy()[..., :3]
+    assert np.array_equal(g3.view(np.uint32), olab.view(np.uint32)), \
+        f"{np.any(g3 != olab, axis=-1).sum()} pixels differ"
+    assert np.allclose(e, oe, rtol=1e-5)
+    assert_cost_close(cost.cpu().numpy(), ocost, P.rho_max, "final costs")
+
+
 # ---------------------------------------------------------------------------
 # Device max-flow (push-relabel kernel) against the host max-flow and the
 # oracle: the cut of the fewest ones is unique, so the comparison is bitwise.

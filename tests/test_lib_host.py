@@ -157,3 +157,39 @@ def test_fused_kernel_row_pipeline_fits_its_rings(CH):
                         kv_e = e_first + e_rows
                         e_first, e_rows = first, nC
                         produced += nA
+
+
+@pytest.mark.parametrize("w,h", [(64, 48), (61, 41)])
+def test_ransac_proposals_bitwise_equal_to_oracle(tiny_pair, w, h):
+    """The library's RANSAC proposer and the oracle's, written apart, agree
+    bit for bit: on a ground-truth plane field with 30% of its labels
+    replaced by random ones, on purely random labels and on the clipped
+    edge cells of a ragged grid (degenerate one-pixel-wide cells included);
+    the refinement steps after the RANSAC steps keep their perturbation
+    schedule."""
+    rng = np.random.default_rng(w + h)
+    pair, _ = tiny_pair
+    o = Oracle(base_params(w, h), texture(rng, h, w), texture(rng, h, w))
+    rand = o.init_labels(3)
+    gt = np.zeros((h, w, 3), np.float32)
+    gh, gw = min(h, 48), min(w, 64)
+    gt[:gh, :gw] = pair.gt_labels[:gh, :gw]
+    gt[gh:, :] = gt[gh - 1:gh, :]
+    gt[:, gw:] = gt[:, gw - 1:gw]
+    mixed = np.where(rng.random((h, w, 1)) < 0.3, rand, gt).astype(np.float32)
+    n = 0
+    for lab in (mixed, rand):
+        for it in range(2):
+            for level, cell in enumerate((5, 15, 25)):
+                nci, ncj = -(-w // cell), -(-h // cell)
+                cells = [(ci, cj) for cj in range(ncj) for ci in range(nci)]
+                if len(cells) > 40:
+                    cells = [cells[k] for k in rng.choice(len(cells), 40, replace=False)] + [(nci - 1, ncj - 1)]
+                for ci, cj in cells:
+                    for step in range(1, 5):  # k_prop = 1, k_rans = 2: steps 1-2 RANSAC, 3-4 refinement
+                        args = (lab, 11, it, level, cell, ci, cj, step, 1, 6.0, 0.5)
+                        a = L.lexp_propose(*args, k_rans=2)
+                        b = o.propose(*args, k_rans=2)
+                        assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (args[2:], a, b)
+                        n += 1
+    assert n > 500
