@@ -1019,6 +1019,114 @@ int64_t ora_optimize(const ora_ctx* c, uint64_t seed, int n_levels, const int* c
   return evals;
 }
 
+/* ---------------------------------------------------------------------------
+ * Post-processing of the left view (the paper applies that of Bleyer, Rhemann
+ * and Rother 2011 without restating it).  Readings:
+ *   - left-right check: pixel p = (u, v) of the left map with disparity d_L
+ *     matches right pixel x = floor(u - d_L + 1/2) of its row; p is consistent
+ *     when 0 <= x < W and |d_L - d_R(x)| <= PP_TOL, where d_R(x) is the right
+ *     view's disparity at x (its labels are in the mirrored frame of the right
+ *     image: right pixel x is mirrored pixel W-1-x);
+ *   - filling: an inconsistent pixel takes, of the planes of the nearest
+ *     consistent pixels to its left and right in its row, the one with the
+ *     lower disparity at the pixel (either one if the other is missing; its
+ *     own disparity if the row has none);
+ *   - weighted median: each inconsistent pixel then takes the weighted median
+ *     of the filled disparities in the (2 PP_R + 1)^2 window around it
+ *     (clipped), with weights exp(-||I_L(p) - I_L(q)||_1 / gamma) quantised
+ *     down to multiples of 2^-24; values ordered by (disparity, row-major
+ *     index), the median being the first whose cumulative weight reaches half
+ *     the total (integer sums, so the choice does not depend on summation
+ *     order).  Consistent pixels keep their disparity.
+ * Disparities are d = a u + b v + c in FP64 from the FP32 labels.
+ * ------------------------------------------------------------------------- */
+#define PP_R 17
+#define PP_TOL 1.0
+#define PP_WQ 16777216.0
+
+typedef struct { double d; int idx; int64_t w; } pp_item;
+
+static int pp_cmp(const void* x, const void* y) {
+  const pp_item* a = (const pp_item*)x;
+  const pp_item* b = (const pp_item*)y;
+  if (a->d < b->d) return -1;
+  if (a->d > b->d) return 1;
+  return (a->idx > b->idx) - (a->idx < b->idx);
+}
+
+void ora_postprocess(const ora_ctx* c, const float* labL, const float* labR, double* out, uint8_t* invalid) {
+  int W = c->W, H = c->H;
+  size_t n = (size_t)W * H;
+  double* dL = (double*)malloc(sizeof(double) * n);
+  double* fill = (double*)malloc(sizeof(double) * n);
+  uint8_t* ok = (uint8_t*)malloc(n);
+  for (int v = 0; v < H; ++v)
+    for (int u = 0; u < W; ++u) {
+      size_t p = (size_t)v * W + u;
+      dL[p] = disp_at(labL + p * 3, u, v);
+      double xd = floor((double)u - dL[p] + 0.5);
+      ok[p] = 0;
+      if (xd >= 0.0 && xd <= (double)(W - 1)) {
+        int x = (int)xd, um = W - 1 - x;
+        double dR = disp_at(labR + ((size_t)v * W + um) * 3, um, v);
+        ok[p] = fabs(dL[p] - dR) <= PP_TOL;
+      }
+    }
+  for (int v = 0; v < H; ++v)
+    for (int u = 0; u < W; ++u) {
+      size_t p = (size_t)v * W + u;
+      fill[p] = dL[p];
+      if (ok[p]) continue;
+      int ul = u - 1, ur = u + 1;
+      while (ul >= 0 && !ok[(size_t)v * W + ul]) --ul;
+      while (ur < W && !ok[(size_t)v * W + ur]) ++ur;
+      int have_l = ul >= 0, have_r = ur < W;
+      if (have_l && have_r) {
+        double a = disp_at(labL + ((size_t)v * W + ul) * 3, u, v);
+        double b = disp_at(labL + ((size_t)v * W + ur) * 3, u, v);
+        fill[p] = a <= b ? a : b;
+      } else if (have_l) {
+        fill[p] = disp_at(labL + ((size_t)v * W + ul) * 3, u, v);
+      } else if (have_r) {
+        fill[p] = disp_at(labL + ((size_t)v * W + ur) * 3, u, v);
+      }
+    }
+  int side = 2 * PP_R + 1;
+  pp_item* items = (pp_item*)malloc(sizeof(pp_item) * side * side);
+  for (int v = 0; v < H; ++v)
+    for (int u = 0; u < W; ++u) {
+      size_t p = (size_t)v * W + u;
+      if (invalid) invalid[p] = !ok[p];
+      if (ok[p]) { out[p] = dL[p]; continue; }
+      const double* cp = c->L + p * 3;
+      int m = 0;
+      int64_t total = 0;
+      for (int y = imax(v - PP_R, 0); y <= imin(v + PP_R, H - 1); ++y)
+        for (int x = imax(u - PP_R, 0); x <= imin(u + PP_R, W - 1); ++x) {
+          size_t q = (size_t)y * W + x;
+          const double* cq = c->L + q * 3;
+          double sdist = fabs(cp[0] - cq[0]) + fabs(cp[1] - cq[1]) + fabs(cp[2] - cq[2]);
+          items[m].d = fill[q];
+          items[m].idx = (int)q;
+          items[m].w = (int64_t)floor(exp(-sdist / c->p.gamma) * PP_WQ);
+          total += items[m].w;
+          ++m;
+        }
+      qsort(items, (size_t)m, sizeof(pp_item), pp_cmp);
+      int64_t cum = 0;
+      double med = items[m - 1].d;
+      for (int k = 0; k < m; ++k) {
+        cum += items[k].w;
+        if (2 * cum >= total) { med = items[k].d; break; }
+      }
+      out[p] = med;
+    }
+  free(items);
+  free(dL);
+  free(fill);
+  free(ok);
+}
+
 int ora_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -80,6 +80,8 @@ def lib():
     L.ora_optimize.restype = C.c_int64
     L.ora_optimize.argtypes = [vp, C.c_uint64, C.c_int, _P(np.int32), _P(np.int32), _P(np.int32),
                                _P(np.int32), C.c_int, f32, f64, vp]
+    L.ora_postprocess.restype = None
+    L.ora_postprocess.argtypes = [vp, f32, f32, f64, _P(np.uint8)]
     L.ora_num_threads.restype = C.c_int
     _lib = L
     return L
@@ -289,6 +291,26 @@ class Oracle:
         ev = self._L.ora_optimize(self.ctx, C.c_uint64(seed), n, cells, kp, ks, kr, iterations, labels, costs,
                                   energy.ctypes.data)
         return labels, costs, energy, ev
+
+    @classmethod
+    def right_view(cls, params: dict, left: np.ndarray, right: np.ndarray) -> "Oracle":
+        """The right image's data term: I_L and I_R swapped in Eqs. (7) and (9)
+        with the disparity added in the warp (Eq. (8)), computed as the
+        left-view term of the horizontally mirrored pair.  Its pixels, label
+        fields and rects are in the mirrored frame of the right image: pixel
+        (u, v) is right pixel (W-1-u, v), and label (a, b, c) there is the plane
+        (-a, b, c + a (W-1)) of the right image."""
+        return cls(params, np.ascontiguousarray(right[:, ::-1]), np.ascontiguousarray(left[:, ::-1]))
+
+    def postprocess(self, labels_left, labels_right_mirrored):
+        """Left-right check, row filling and weighted median of the left view
+        (this oracle must be the left view's).  Returns (disparity FP64 HxW,
+        inconsistent-pixel mask HxW uint8)."""
+        out = np.zeros((self.H, self.W))
+        inv = np.zeros((self.H, self.W), np.uint8)
+        self._L.ora_postprocess(self.ctx, np.ascontiguousarray(labels_left, dtype=np.float32),
+                                np.ascontiguousarray(labels_right_mirrored, dtype=np.float32), out, inv)
+        return out, inv
 
     @staticmethod
     def num_threads() -> int:
