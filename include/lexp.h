@@ -68,6 +68,17 @@ typedef struct {
  *                              it leaves unfinished is cut on the host; 0 = every
  *                              cut on the host (Boykov-Kolmogorov).  Both return the
  *                              same cut (the minimiser with the fewest ones).
+ *   view                     : 0 = the left view (data term on I_L, samples of I_R
+ *                              at u - d); 1 = the right view: I_L and I_R swapped
+ *                              in Eqs. (7) and (9), samples at u + d, contrast
+ *                              weights of Eq. (11) from I_R.  A right-view context
+ *                              evaluates it as the left-view term of the mirrored
+ *                              pair, and all its pixels, rects and label fields are
+ *                              in the mirrored frame of the right image: pixel
+ *                              (u, v) is right pixel (W-1-u, v), and label (a, b, c)
+ *                              is the right image's plane (-a, b, c + a (W-1))
+ *                              (lexp_view_labels converts).  The images passed to
+ *                              lexp_create are (left, right) for both views.
  */
 typedef struct {
   int32_t width, height;
@@ -79,6 +90,7 @@ typedef struct {
   int32_t neighbours;
   int32_t host_threads;
   int32_t device_cut;
+  int32_t view;
 } lexp_params;
 
 /* Grid levels of the optimisation procedure (Alg. 2): cell size in pixels and
@@ -218,6 +230,29 @@ lexp_status lexp_optimize(lexp_ctx* ctx, const lexp_schedule* schedule, uint64_t
 lexp_status lexp_optimize_batch(int32_t n_pairs, lexp_ctx* const* ctxs, const lexp_schedule* schedule,
                                 const uint64_t* seeds, float* const* labels, float* const* cur_cost,
                                 double* const* energy_traces, double* time_trace, void* hip_stream);
+
+/* Label field of a context (device HxWx4) in its view image's own frame:
+ * a copy for the left view; for the right view, out(u, v) = the plane of
+ * in(W-1-u, v) in right-image coordinates, (a, b, c) -> (-a, b, c + a (W-1)),
+ * with c rounded once to FP32.  in and out must not overlap.  Stream-ordered. */
+lexp_status lexp_view_labels(lexp_ctx* ctx, const float* labels_in, float* labels_out, void* hip_stream);
+
+/* Post-processing of the left view (the final step of the paper's method,
+ * after Bleyer et al. 2011): left-right consistency check, filling of the
+ * inconsistent pixels from the nearest consistent ones of their row (the
+ * plane with the lower disparity there) and a weighted median over a 35x35
+ * window on the filled pixels (colour weights exp(-||I_L(p)-I_L(q)||_1/gamma)
+ * quantised down to multiples of 2^-24).
+ *   left, labels_left  : a left-view context and its labels (device HxWx4);
+ *   right, labels_right: a right-view context of the same pair and its labels
+ *                        (device HxWx4, in its mirrored frame, as lexp_optimize
+ *                        leaves them);
+ *   out_disp           : device HxW float32, the left disparity map;
+ *   out_invalid        : device HxW uint8 (1 = failed the check), may be NULL.
+ * Scratch belongs to the left context (calls on one left context must share a
+ * stream).  Stream-ordered. */
+lexp_status lexp_postprocess(lexp_ctx* left, const float* labels_left, lexp_ctx* right, const float* labels_right,
+                             float* out_disp, uint8_t* out_invalid, void* hip_stream);
 
 /* Timing of the fused cost kernel (HIP events around each launch on its
  * stream) and host phases.  enable != 0 turns it on; reset clears counters. */

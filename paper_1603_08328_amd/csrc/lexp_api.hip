@@ -122,6 +122,7 @@ struct lexp_ctx {
   DevBuf<float4> d_labels_tmp;
   DevBuf<int> d_status;
   PinBuf<int> h_status;
+  DevBuf<unsigned char> d_post;  // post-processing scratch (disparity, fill, flags, row links)
   PinBuf<Item> h_items;
   PinBuf<Tile> h_tiles;
   PinBuf<int> h_terms;
@@ -653,6 +654,7 @@ lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const 
     return fail(LEXP_EINVAL, "lambda*tau_dis or truncations too large for 32-bit binary terms");
   if (p.host_threads < 0 || p.host_threads > 64) return fail(LEXP_EINVAL, "host_threads outside [0, 64]");
   if (p.device_cut != 0 && p.device_cut != 1) return fail(LEXP_EINVAL, "device_cut must be 0 or 1");
+  if (p.view != 0 && p.view != 1) return fail(LEXP_EINVAL, "view must be 0 (left) or 1 (right)");
   hipStream_t s = (hipStream_t)hip_stream;
   std::unique_ptr<lexp_ctx> c(new lexp_ctx());
   c->prm = p;
@@ -685,11 +687,16 @@ lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const 
   double* tmp = nullptr;
   HIP_TRY(hipMalloc((void**)&tmp, n * 9 * sizeof(double)));
   const int nb = (int)((n + 255) / 256);
-  hipLaunchKernelGGL(lexp::k_pack, dim3(nb), dim3(256), 0, s, left_hwc, c->left4, c->left4T, c->W, c->H);
-  hipLaunchKernelGGL(lexp::k_pack, dim3(nb), dim3(256), 0, s, right_hwc, c->right4, (float4*)nullptr, c->W, c->H);
+  // the right view is the left-view problem of the mirrored pair (roles swapped)
+  const int mirror = p.view;
+  const float* own = mirror ? right_hwc : left_hwc;
+  const float* other = mirror ? left_hwc : right_hwc;
+  hipLaunchKernelGGL(lexp::k_pack, dim3(nb), dim3(256), 0, s, own, c->left4, c->left4T, c->W, c->H, mirror);
+  hipLaunchKernelGGL(lexp::k_pack, dim3(nb), dim3(256), 0, s, other, c->right4, (float4*)nullptr, c->W, c->H,
+                     mirror);
   hipLaunchKernelGGL(lexp::k_guide_h, dim3(nb), dim3(256), 0, s, c->left4, tmp, c->W, c->H, c->r);
   hipLaunchKernelGGL(lexp::k_guide_v, dim3(nb), dim3(256), 0, s, tmp, c->guide, c->W, c->H, c->r, p.gf_eps);
-  hipLaunchKernelGGL(lexp::k_weights, dim3(nb), dim3(256), 0, s, left_hwc, c->wts, c->W, c->H, p.gamma);
+  hipLaunchKernelGGL(lexp::k_weights, dim3(nb), dim3(256), 0, s, own, c->wts, c->W, c->H, p.gamma, mirror);
   hipError_t e = hipGetLastError();
   hipError_t e2 = hipStreamSynchronize(s);
   (void)hipFree(tmp);
@@ -723,6 +730,7 @@ lexp_status lexp_destroy(lexp_ctx* c) {
   c->d_flag.release(); c->d_partial.release(); c->d_labels_tmp.release();
   c->d_status.release(); c->h_status.release();
   c->d_pair.release(); c->h_pair.release(); c->d_run_pairs.release(); c->h_run_pairs.release();
+  c->d_post.release();
   c->h_items.release(); c->h_tiles.release(); c->h_terms.release(); c->h_x.release(); c->h_flag.release();
   c->h_partial.release(); c->h_labels4.release();
   for (auto& b : c->part) {
@@ -872,6 +880,44 @@ lexp_status lexp_energy(lexp_ctx* c, const float* labels, const float* cur_cost,
                         double* pairwise, void* hip_stream) {
   if (!c || !labels || !cur_cost) return fail(LEXP_EINVAL, "null argument");
   return energy_impl(c, labels, cur_cost, total, unary, pairwise, (hipStream_t)hip_stream);
+}
+
+lexp_status lexp_view_labels(lexp_ctx* c, const float* labels_in, float* labels_out, void* hip_stream) {
+  if (!c || !labels_in || !labels_out) return fail(LEXP_EINVAL, "null argument");
+  const size_t n = (size_t)c->W * c->H;
+  const float* a = labels_in;
+  const float* b = labels_out;
+  if (a < b + 4 * n && b < a + 4 * n) return fail(LEXP_EINVAL, "labels_in and labels_out overlap");
+  hipLaunchKernelGGL(lexp::k_view_labels, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)hip_stream,
+                     (const float4*)labels_in, (float4*)labels_out, c->W, c->H, c->prm.view);
+  HIP_TRY(hipGetLastError());
+  return LEXP_OK;
+}
+
+lexp_status lexp_postprocess(lexp_ctx* left, const float* labels_left, lexp_ctx* right, const float* labels_right,
+                             float* out_disp, uint8_t* out_invalid, void* hip_stream) {
+  if (!left || !right || !labels_left || !labels_right || !out_disp) return fail(LEXP_EINVAL, "null argument");
+  if (left->prm.view != 0 || right->prm.view != 1)
+    return fail(LEXP_EINVAL, "left must be a left-view context and right a right-view context");
+  if (left->W != right->W || left->H != right->H) return fail(LEXP_EINVAL, "the two views differ in size");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int W = left->W, H = left->H;
+  const size_t n = (size_t)W * H;
+  // scratch: disparity and fill (FP64), next-consistent links (int), flags (byte)
+  HIP_TRY(left->d_post.ensure(n * (8 + 8 + 4 + 1)));
+  double* disp = reinterpret_cast<double*>(left->d_post.p);
+  double* fill = disp + n;
+  int* next_ok = reinterpret_cast<int*>(fill + n);
+  uint8_t* ok = reinterpret_cast<uint8_t*>(next_ok + n);
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(lexp::k_pp_check, dim3(nb), dim3(256), 0, s, (const float4*)labels_left,
+                     (const float4*)labels_right, W, H, disp, ok);
+  hipLaunchKernelGGL(lexp::k_pp_fill, dim3((unsigned)((H + 63) / 64)), dim3(64), 0, s, (const float4*)labels_left,
+                     disp, ok, W, H, next_ok, fill);
+  hipLaunchKernelGGL(lexp::k_pp_median, dim3((unsigned)n), dim3(256), 0, s, left->left4, disp, fill, ok, W, H,
+                     left->prm.gamma, out_disp, out_invalid);
+  HIP_TRY(hipGetLastError());
+  return LEXP_OK;
 }
 
 lexp_status lexp_init_labels(lexp_ctx* c, uint64_t seed, float* labels, void* hip_stream) {

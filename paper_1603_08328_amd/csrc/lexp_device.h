@@ -81,11 +81,18 @@ constexpr int kMaxTW = 128;
 template <int MODE, int NSEG, int NC>
 __global__ void k_unary(const PairDev* pairs, const Item* items, const Tile* tiles, int n_tiles,
                         const float4* label_field, float* out, int ring, int wp_cap, int tw_cap, int ws_cap);
-__global__ void k_pack(const float* img, float4* out, float4* outT, int W, int H);
+__global__ void k_pack(const float* img, float4* out, float4* outT, int W, int H, int mirror);
 __global__ void k_guide_h(const float4* left4, double* tmp, int W, int H, int r);
 __global__ void k_guide_v(const double* tmp, float* guide, int W, int H, int r, double eps);
 __global__ void k_guide_planes(const float* guide, float* planes, int W, int H);
-__global__ void k_weights(const float* left, double* wts, int W, int H, double gamma);
+__global__ void k_weights(const float* img, double* wts, int W, int H, double gamma, int mirror);
+__global__ void k_view_labels(const float4* in, float4* out, int W, int H, int mirror);
+__global__ void k_pp_check(const float4* labels_left, const float4* labels_right, int W, int H, double* disp,
+                           uint8_t* ok);
+__global__ void k_pp_fill(const float4* labels_left, const double* disp, const uint8_t* ok, int W, int H,
+                          int* next_ok, double* fill);
+__global__ void k_pp_median(const float4* left4, const double* disp, const double* fill, const uint8_t* ok, int W,
+                            int H, double gamma, float* out, uint8_t* invalid);
 __global__ void k_graph_terms(const PairDev* pairs, const Item* items, const float* phi_alpha, int* terms,
                               int* flag);
 __global__ void k_apply(const PairDev* pairs, const Item* items, const uint8_t* x, const float* phi_alpha);

@@ -27,16 +27,20 @@ __device__ inline float gray_of(const float* px) {
 }
 
 // (R, G, B, x-gradient of the gray value by [-0.5 0 0.5], replicated borders),
-// row-major; a column-major copy too where outT is given.
+// row-major; a column-major copy too where outT is given.  mirror != 0 packs
+// the horizontally mirrored image (column u from column W-1-u), its gradient
+// taken on the mirrored image.
 __global__ void k_pack(const float* __restrict__ img, float4* __restrict__ out, float4* __restrict__ outT, int W,
-                       int H) {
+                       int H, int mirror) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= W * H) return;
   const int u = i % W, v = i / W;
   const int ul = u > 0 ? u - 1 : 0, ur = u < W - 1 ? u + 1 : W - 1;
+  auto src = [&](int x) { return mirror ? W - 1 - x : x; };
   const float* row = img + (size_t)v * W * 3;
-  const float gx = 0.5f * (gray_of(row + ur * 3) - gray_of(row + ul * 3));
-  const float4 val = make_float4(row[u * 3 + 0], row[u * 3 + 1], row[u * 3 + 2], gx);
+  const float gx = 0.5f * (gray_of(row + src(ur) * 3) - gray_of(row + src(ul) * 3));
+  const int us = src(u);
+  const float4 val = make_float4(row[us * 3 + 0], row[us * 3 + 1], row[us * 3 + 2], gx);
   out[i] = val;
   if (outT) outT[(size_t)u * H + v] = val;
 }
@@ -103,18 +107,21 @@ __global__ void k_guide_planes(const float* __restrict__ guide, float* __restric
   for (int q = 0; q < 9; ++q) planes[q * hw + i] = vals[q];
 }
 
-// Contrast weights w_pq = exp(-||I_L(p) - I_L(q)||_1 / gamma), Eq. (11), for
-// the forward neighbours q = p + (1,0), (0,1), (1,1), (-1,1); 0 outside.
-__global__ void k_weights(const float* __restrict__ left, double* __restrict__ wts, int W, int H, double gamma) {
+// Contrast weights w_pq = exp(-||I(p) - I(q)||_1 / gamma), Eq. (11), of the
+// view's own image I, for the forward neighbours q = p + (1,0), (0,1), (1,1),
+// (-1,1); 0 outside.  mirror != 0: I is the mirrored image.
+__global__ void k_weights(const float* __restrict__ img, double* __restrict__ wts, int W, int H, double gamma,
+                          int mirror) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= W * H) return;
   const int u = i % W, v = i / W;
-  const float* a = left + (size_t)i * 3;
+  auto px = [&](int x, int y) { return img + ((size_t)y * W + (mirror ? W - 1 - x : x)) * 3; };
+  const float* a = px(u, v);
   for (int d = 0; d < 4; ++d) {
     const int qu = u + kFwdDU[d], qv = v + kFwdDV[d];
     double w = 0.0;
     if (qu >= 0 && qu < W && qv < H) {
-      const float* b = left + ((size_t)qv * W + qu) * 3;
+      const float* b = px(qu, qv);
       double s = fabs((double)a[0] - (double)b[0]) + fabs((double)a[1] - (double)b[1]);
       s = s + fabs((double)a[2] - (double)b[2]);
       w = exp(-s / gamma);

@@ -32,7 +32,7 @@ class lexp_params(C.Structure):
                 ("gf_radius", C.c_int32), ("gf_eps", C.c_double),
                 ("lam", C.c_double), ("tau_dis", C.c_double), ("w_floor", C.c_double),
                 ("gamma", C.c_double), ("neighbours", C.c_int32), ("host_threads", C.c_int32),
-                ("device_cut", C.c_int32)]
+                ("device_cut", C.c_int32), ("view", C.c_int32)]
 
 
 class lexp_plane(C.Structure):
@@ -78,6 +78,8 @@ _SIGS = {
     "lexp_energy": (_i32, [_vp, _vp, _vp, C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64), _vp]),
     "lexp_init_labels": (_i32, [_vp, _u64, _vp, _vp]),
     "lexp_optimize": (_i32, [_vp, C.POINTER(lexp_schedule), _u64, _vp, _vp, _vp, _vp, _vp]),
+    "lexp_view_labels": (_i32, [_vp, _vp, _vp, _vp]),
+    "lexp_postprocess": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "lexp_optimize_batch": (_i32, [_i32, _vp, C.POINTER(lexp_schedule), _vp, _vp, _vp, _vp, _vp, _vp]),
     "lexp_set_timing": (_i32, [_vp, _i32]),
     "lexp_get_stats": (_i32, [_vp, C.POINTER(lexp_stats)]),
@@ -201,7 +203,7 @@ def lexp_create(params: dict, left, right, stream=None) -> LexpContext:
                     float(params["tau_grad"]), int(params["gf_radius"]), float(params["gf_eps"]),
                     float(params["lam"]), float(params["tau_dis"]), float(params["w_floor"]),
                     float(params["gamma"]), int(params["neighbours"]), int(params.get("host_threads", 0)),
-                    int(params.get("device_cut", 1)))
+                    int(params.get("device_cut", 1)), int(params.get("view", 0)))
     lp = _dev(left, torch.float32, (h, w, 3), name="left")
     rp = _dev(right, torch.float32, (h, w, 3), name="right")
     out = C.c_void_p()
@@ -347,6 +349,30 @@ def lexp_optimize_batch(ctxs, grids, iterations, seeds, labels, cur_costs, strea
     _check(load_library().lexp_optimize_batch(n, hs, C.byref(sch), sd, lp, cp, ep, t.ctypes.data,
                                               _stream_ptr(stream)))
     return e, t
+
+
+def lexp_view_labels(ctx, labels, stream=None):
+    """The context's label field in its view image's own frame (a new device
+    tensor HxWx4): a copy for the left view, un-mirrored for the right view."""
+    torch = _torch()
+    lp = _dev(labels, torch.float32, (ctx.height, ctx.width, 4), name="labels")
+    out = torch.empty_like(labels)
+    _check(load_library().lexp_view_labels(ctx.handle, lp, C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def lexp_postprocess(left_ctx, labels_left, right_ctx, labels_right, stream=None):
+    """Left-right check, row filling and weighted median of the left view;
+    returns (disparity HxW float32, inconsistent mask HxW uint8), device tensors."""
+    torch = _torch()
+    h, w = left_ctx.height, left_ctx.width
+    lp = _dev(labels_left, torch.float32, (h, w, 4), name="labels_left")
+    rp = _dev(labels_right, torch.float32, (h, w, 4), name="labels_right")
+    disp = torch.empty((h, w), dtype=torch.float32, device=labels_left.device)
+    inv = torch.empty((h, w), dtype=torch.uint8, device=labels_left.device)
+    _check(load_library().lexp_postprocess(left_ctx.handle, lp, right_ctx.handle, rp, C.c_void_p(disp.data_ptr()),
+                                           C.c_void_p(inv.data_ptr()), _stream_ptr(stream)))
+    return disp, inv
 
 
 def lexp_set_timing(ctx, enable: bool):

@@ -679,3 +679,117 @@ def test_optimize_batch_rejects_mixed_radius_and_shared_buffers(tiny):
     with pytest.raises(L.LexpError):
         L.lexp_optimize_batch([tiny.ctx, tiny.ctx], [(5, 1, 3)], 1, [0, 0], [lab[0], lab[0]], [cost[0], cost[0]])
     ctx2.close()
+
+
+# ---------------------------------------------------------------------------
+# Right view and post-processing.
+def _right_view(P):
+    """Right-view context of a Pair and its oracle (both in the mirrored frame)."""
+    ctx = L.lexp_create(dict(P.p, view=1), _cuda(P.left), _cuda(P.right))
+    ora = Oracle.right_view(P.p, P.left, P.right)
+    return ctx, ora
+
+
+def test_right_view_unary_matches_oracle(lowres):
+    P = lowres
+    ctx, ora = _right_view(P)
+    rng = np.random.default_rng(31)
+    for size in [(15, 15), (45, 45), (75, 75), (1, 1)]:
+        rects, labs = [], []
+        for k in range(6):
+            u0, v0 = int(rng.integers(-10, P.W - 5)), int(rng.integers(-10, P.H - 5))
+            rects.append((u0, v0, u0 + size[0], v0 + size[1]))
+            labs.append(random_labels(rng, 1, 1, float(P.p["disp_max"]))[0, 0] if k % 2 else
+                        [0.0, 0.0, rng.uniform(0, P.p["disp_max"])])
+        rects = np.array(rects, np.int32)
+        labs = np.array(labs, np.float32)
+        sizes = [max(min(u1, P.W) - max(u0, 0), 0) * max(min(v1, P.H) - max(v0, 0), 0) for u0, v0, u1, v1 in rects]
+        offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+        out = torch.full((int(sum(sizes)),), float("nan"), device="cuda")
+        L.lexp_unary_cost(ctx, rects, labs, offs, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        for r, f, o, n in zip(rects, labs, offs, sizes):
+            if n:
+                assert_cost_close(got[o:o + n], ora.unary_region(tuple(r), f).ravel(), P.rho_max, "right view")
+    ctx.close()
+
+
+def test_right_view_optimize_bit_identical_to_oracle_and_batched_with_left(tiny):
+    """The tiny pair's right view alone equals the oracle's right-view run; run
+    together with the left view in one batch, both views equal their runs
+    alone."""
+    P = tiny
+    ctx, ora = _right_view(P)
+    lab = torch.zeros((P.H, P.W, 4), device="cuda")
+    cost = torch.zeros((P.H, P.W), device="cuda")
+    e, _ = L.lexp_optimize(ctx, [(5, 1, 3)], 2, 0, lab, cost)
+    olab, _, oe, _ = ora.optimize(0, [(5, 1, 3)], 2)
+    g3 = lab.cpu().numpy()[..., :3]
+    assert np.array_equal(g3.view(np.uint32), olab.view(np.uint32)), f"{np.any(g3 != olab, axis=-1).sum()} differ"
+    assert np.allclose(e, oe, rtol=1e-5)
+    labl = torch.zeros_like(lab)
+    costl = torch.zeros_like(cost)
+    el, _ = L.lexp_optimize(P.ctx, [(5, 1, 3)], 2, 0, labl, costl)
+    labs = [torch.zeros_like(lab), torch.zeros_like(lab)]
+    costs = [torch.zeros_like(cost), torch.zeros_like(cost)]
+    es, _ = L.lexp_optimize_batch([P.ctx, ctx], [(5, 1, 3)], 2, [0, 0], labs, costs)
+    assert torch.equal(labs[0], labl) and torch.equal(labs[1], lab)
+    assert np.array_equal(es[0], el) and np.array_equal(es[1], e)
+    ctx.close()
+
+
+def test_view_labels_conversion(tiny):
+    P = tiny
+    ctx, _ = _right_view(P)
+    rng = np.random.default_rng(2)
+    lab = np.zeros((P.H, P.W, 4), np.float32)
+    lab[..., :3] = random_labels(rng, P.H, P.W, 16.0)
+    got = L.lexp_view_labels(ctx, _cuda(lab)).cpu().numpy()
+    m = lab[:, ::-1]
+    expect = np.zeros_like(lab)
+    expect[..., 0] = -m[..., 0]
+    expect[..., 1] = m[..., 1]
+    expect[..., 2] = (m[..., 2].astype(np.float64) + m[..., 0].astype(np.float64) * (P.W - 1)).astype(np.float32)
+    assert np.array_equal(got.view(np.uint32), expect.view(np.uint32))
+    same = L.lexp_view_labels(P.ctx, _cuda(lab)).cpu().numpy()
+    assert np.array_equal(same, lab)
+    # the converted labels give the same disparity at mirrored pixels
+    u = np.arange(P.W)[None, :]
+    v = np.arange(P.H)[:, None]
+    d_ctx = lab[..., 0] * u + lab[..., 1] * v + lab[..., 2]  # disparity at context-frame pixel u
+    d_img = got[..., 0] * u + got[..., 1] * v + got[..., 2]
+    assert np.allclose(d_img, d_ctx[:, ::-1], atol=1e-3)
+    ctx.close()
+
+
+@pytest.mark.parametrize("which", ["tiny", "lowres"])
+def test_postprocess_matches_oracle(tiny, lowres, which):
+    """Both views optimised on the device, then post-processed on the device
+    and by the oracle from the same labels: the disparity maps agree bit for
+    bit (FP64 arithmetic rounded once to FP32) and so do the masks of the
+    inconsistent pixels."""
+    P = tiny if which == "tiny" else lowres
+    grids = [(5, 1, 3)] if which == "tiny" else [(5, 1, 7), (15, 1, 7), (25, 1, 7)]
+    ctx_r, _ = _right_view(P)
+    labs = [torch.zeros((P.H, P.W, 4), device="cuda") for _ in range(2)]
+    costs = [torch.zeros((P.H, P.W), device="cuda") for _ in range(2)]
+    L.lexp_optimize_batch([P.ctx, ctx_r], grids, 2, [1, 2], labs, costs)
+    disp, inv = L.lexp_postprocess(P.ctx, labs[0], ctx_r, labs[1])
+    torch.cuda.synchronize()
+    ll = labs[0].cpu().numpy()[..., :3]
+    lr = labs[1].cpu().numpy()[..., :3]
+    odisp, oinv = P.ora.postprocess(ll, lr)
+    inv = inv.cpu().numpy()
+    assert np.array_equal(inv, oinv), f"{(inv != oinv).sum()} flags differ"
+    assert 0 < inv.sum() < inv.size
+    got = disp.cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), odisp.astype(np.float32).view(np.uint32)), \
+        f"{(got != odisp.astype(np.float32)).sum()} of {got.size} differ"
+    ctx_r.close()
+
+
+def test_postprocess_rejects_wrong_views(tiny):
+    lab = torch.zeros((tiny.H, tiny.W, 4), device="cuda")
+    with pytest.raises(L.LexpError):
+        L.lexp_postprocess(tiny.ctx, lab, tiny.ctx, lab)
