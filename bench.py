@@ -175,6 +175,53 @@ def run_many_pairs(n_pairs: int, iterations: int, seed: int = 0):
                 batch_alg_gbps=bst["unary_alg_bytes"] / max(bst["unary_kernel_ms"], 1e-9) / 1e6)
 
 
+def run_both_views(seed: int = 0):
+    """Both views of the 450x375 pair in one batched run, then the
+    post-processing of the left view; times and the share of pixels whose
+    disparity is off the synthetic ground truth by more than 1 and 2, before
+    and after the post-processing."""
+    import torch
+
+    import paper_1603_08328_amd.lexp as L
+    from synth import make_workload_pair, params_for, workload
+
+    wl = workload(WORKLOAD)
+    prm = params_for(WORKLOAD)
+    pair = make_workload_pair(WORKLOAD)
+    dev = torch.device("cuda:0")
+    left = torch.from_numpy(pair.left).to(dev)
+    right = torch.from_numpy(pair.right).to(dev)
+    h, w = pair.left.shape[:2]
+    ctxs = [L.lexp_create(dict(prm, view=v), left, right) for v in (0, 1)]
+    labs = [torch.zeros((h, w, 4), device=dev) for _ in range(2)]
+    costs = [torch.zeros((h, w), device=dev) for _ in range(2)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e, _ = L.lexp_optimize_batch(ctxs, wl["grids"], wl["iterations"], [seed, seed], labs, costs)
+    torch.cuda.synchronize()
+    t_opt = time.perf_counter() - t0
+    L.lexp_postprocess(ctxs[0], labs[0], ctxs[1], labs[1])  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    disp, inv = L.lexp_postprocess(ctxs[0], labs[0], ctxs[1], labs[1])
+    torch.cuda.synchronize()
+    t_pp = time.perf_counter() - t0
+    lab = labs[0].cpu().numpy().astype(np.float64)
+    u = np.arange(w)[None, :]
+    v = np.arange(h)[:, None]
+    d0 = lab[..., 0] * u + lab[..., 1] * v + lab[..., 2]
+    d1 = disp.cpu().numpy().astype(np.float64)
+    gt = pair.gt_disp.astype(np.float64)
+    bad = lambda d, t: float(np.mean(np.abs(d - gt) > t) * 100.0)  # noqa: E731
+    for c in ctxs:
+        c.close()
+    return dict(optimize_both_views_s=t_opt, postprocess_ms=t_pp * 1e3,
+                final_energy_left=float(e[0][-1]), final_energy_right=float(e[1][-1]),
+                inconsistent_pct=float(inv.float().mean().item() * 100.0),
+                bad1_pct_before=bad(d0, 1.0), bad1_pct_after=bad(d1, 1.0),
+                bad2_pct_before=bad(d0, 2.0), bad2_pct_after=bad(d1, 2.0))
+
+
 def run_cpu_baseline():
     """The oracle on a bounded sample of the same workload: initial per-pixel
     costs of the regions of a sample of group-0 cells at grid levels 5/15/25 px
@@ -260,6 +307,8 @@ def main():
                     help="instead: the uneven-size many-pair workload with this many pairs, pair by pair and "
                          "batched (one JSON line with both)")
     ap.add_argument("--iterations", type=int, default=10, help="iterations of the many-pair runs")
+    ap.add_argument("--both-views", action="store_true",
+                    help="instead: both views batched, then the post-processing (times and ground-truth errors)")
     ap.add_argument("--k-rans", type=int, default=0,
                     help="RANSAC proposer steps per cell and level (Alg. 1; 0 in the workload as specified)")
     args = ap.parse_args()
@@ -267,6 +316,10 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path runs on a single "
               "MI355X; see the design notes for how it would shard)", file=sys.stderr)
         sys.exit(2)
+    if args.both_views:
+        print(json.dumps({"workload": "450x375 synthetic pair, both views and post-processing",
+                          "both_views": run_both_views()}), flush=True)
+        return
     if args.many_pairs:
         m = run_many_pairs(args.many_pairs, args.iterations)
         out = {"metric": METRIC, "value": m["batch_value"], "unit": "Gpix*labels/s", "n_gpus": 1, "steps": 1,
