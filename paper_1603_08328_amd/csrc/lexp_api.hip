@@ -100,6 +100,7 @@ struct lexp_ctx {
   DevParams dp{};
   int W = 0, H = 0, r = 0;
   int tw_lim = 1;           // widest R tile column strip
+  int n_cu = 256;           // compute units (the fused kernel runs one tile per CU)
   size_t lds_limit = 65536; // dynamic LDS per workgroup
   float4* left4 = nullptr;
   float4* left4T = nullptr;  // column-major copy (index u*H + v)
@@ -674,6 +675,9 @@ lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const 
   int lds = 0;
   HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   c->lds_limit = (size_t)std::max(lds, 16384);
+  int cus = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  c->n_cu = std::max(cus, 1);
   // one 16-wave workgroup per CU: a tile may use all of the CU's LDS
   c->tw_lim = max_tile_width(c->r, c->lds_limit);
   if (c->tw_lim < 1)
@@ -1218,11 +1222,15 @@ void sort_group(GroupPlan& g) {
 // part 1) to the group's range of the tile table.  share < 0: every cut on
 // the host, the parts being the pairs' own splits.  Otherwise part 0 takes
 // that share of the regions the device max-flow can hold (every region of
-// part 0 is cut on the device) and part 1 the rest.
+// part 0 is cut on the device) and part 1 the rest; when the group's tiles
+// fit two rounds of one tile per CU, part 0 takes at most one round (a launch
+// of a few more tiles than CUs would take two rounds).
 void assign_parts(const RunPair* pairs, const GroupPlan& g, double share, Part* P, Tile* table) {
   const lexp_ctx* c = pairs[0].c;
   for (int hp = 0; hp < 2; ++hp) P[hp] = Part{};
   std::vector<int> which(g.items.size());
+  const size_t budget = g.n_tiles <= (size_t)2 * c->n_cu ? (size_t)c->n_cu : g.n_tiles;
+  size_t tiles0 = 0;
   double acc = 0.5;
   for (size_t q = 0; q < g.items.size(); ++q) {
     const Item& it = g.items[q];
@@ -1230,8 +1238,9 @@ void assign_parts(const RunPair* pairs, const GroupPlan& g, double share, Part* 
       which[q] = g.pair_part[q];
     } else if (cut_fits(c, (int64_t)it.rw * it.rh)) {
       acc += share;
-      which[q] = acc >= 1.0 ? 0 : 1;
+      which[q] = acc >= 1.0 && tiles0 + g.tiles[q].size() <= budget ? 0 : 1;
       if (acc >= 1.0) acc -= 1.0;
+      if (which[q] == 0) tiles0 += g.tiles[q].size();
     } else {
       which[q] = 1;
     }
