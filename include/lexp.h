@@ -104,6 +104,9 @@ typedef struct {
   int32_t k_rand[4];
   int32_t iterations;
   int32_t k_rans[4];
+  int32_t learned; /* 1: refinement steps with an odd index take the plane of the
+                      learned network (lexp_set_net) at the chosen pixel, computed
+                      from the labels at the start of each level pass; 0: none */
 } lexp_schedule;
 
 /* Counters of the hot kernel, accumulated while timing is enabled. */
@@ -253,6 +256,39 @@ lexp_status lexp_view_labels(lexp_ctx* ctx, const float* labels_in, float* label
  * stream).  Stream-ordered. */
 lexp_status lexp_postprocess(lexp_ctx* left, const float* labels_left, lexp_ctx* right, const float* labels_right,
                              float* out_disp, uint8_t* out_invalid, void* hip_stream);
+
+/* ---- learned proposal network ---------------------------------------------
+ * Five 3x3 convolutions (zero padding), ReLU after the first four, channels
+ * 16 -> 32 -> 32 -> 32 -> 32 -> 16, on the BF16 matrix cores with FP32 sums.
+ * Input per pixel: left and right RGB / 255 of the context's packed images,
+ * then a, b, d / disp_max of the label (d = a u + b v + c), then zeros.
+ * Output channels 0..2: (a, b, d / disp_max) of a proposed plane.  Training
+ * loss: mean over pixels of the mean over the 5x5 neighbourhood q of
+ * |d_p + a_p (u_q - u_p) + b_p (v_q - v_p) - d*_q| (d* from the target
+ * labels); Adam (0.9, 0.999, 1e-8) on FP32 master weights.  Weights are laid
+ * out per layer [tap][out][in] (tap = 3 ky + kx), layers one after the other;
+ * biases likewise.  Not in the paper: the method admits any proposer. */
+typedef struct lexp_net lexp_net;
+lexp_status lexp_net_sizes(int32_t* n_weights, int32_t* n_biases);
+/* He-uniform weights from the counter-based generator keyed by seed, zero
+ * biases; buffers for images up to max_width x max_height. */
+lexp_status lexp_net_create(int32_t max_width, int32_t max_height, uint64_t seed, lexp_net** out);
+lexp_status lexp_net_destroy(lexp_net* net);
+/* Host arrays of lexp_net_sizes' lengths; setting resets the Adam state.  Synchronous. */
+lexp_status lexp_net_set_weights(lexp_net* net, const float* weights, const float* biases);
+lexp_status lexp_net_get_weights(lexp_net* net, float* weights, float* biases);
+/* Gradients of the last training step (same layout; inspection).  Synchronous. */
+lexp_status lexp_net_get_grads(lexp_net* net, float* weights, float* biases);
+/* Output of the network on ctx's images and labels (device HxWx4): out is
+ * device HxWx16 FP32.  Stream-ordered. */
+lexp_status lexp_net_forward(lexp_net* net, lexp_ctx* ctx, const float* labels, float* out, void* hip_stream);
+/* One Adam step on the loss of the network's output for labels against
+ * target labels (both device HxWx4); loss (host, may be NULL) receives the
+ * loss before the step.  Synchronises hip_stream. */
+lexp_status lexp_net_train_step(lexp_net* net, lexp_ctx* ctx, const float* labels, const float* target_labels,
+                                float learning_rate, double* loss, void* hip_stream);
+/* The network lexp_optimize uses when schedule->learned is 1 (NULL: none). */
+lexp_status lexp_set_net(lexp_ctx* ctx, lexp_net* net);
 
 /* Timing of the fused cost kernel (HIP events around each launch on its
  * stream) and host phases.  enable != 0 turns it on; reset clears counters. */

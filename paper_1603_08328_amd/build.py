@@ -43,7 +43,7 @@ def build(verbose: bool = False) -> str:
         _run(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
               "-I", INCLUDE, "-c", os.path.join(CSRC, "lexp_host.cpp"), "-o", host_obj], verbose)
         objs = [host_obj]
-        for src in ("lexp_kernels.hip", "lexp_cut.hip", "lexp_post.hip", "lexp_api.hip"):
+        for src in ("lexp_kernels.hip", "lexp_cut.hip", "lexp_post.hip", "lexp_net.hip", "lexp_api.hip"):
             obj = os.path.join(tmp, src.replace(".hip", ".o"))
             _run([hipcc, "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
                   "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

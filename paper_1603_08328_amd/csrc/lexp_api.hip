@@ -161,6 +161,34 @@ struct lexp_ctx {
     hipEvent_t ready = nullptr;
   } part[2];
   size_t res_items = 0;  // status slots in the result buffers
+  lexp_net* net = nullptr;  // learned proposals for lexp_optimize (not owned)
+};
+
+// The learned proposal network (five 3x3 convolutions, channels 16 -> 32 ->
+// 32 -> 32 -> 32 -> 16): FP32 master parameters with Adam moments, BF16
+// weight copies, and activation buffers for images up to max_w x max_h.
+struct lexp_net {
+  static constexpr int kLayers = 5;
+  static constexpr int kCh[kLayers + 1] = {16, 32, 32, 32, 32, 16};
+  static constexpr int kChunk = 4096;  // pixels per weight-gradient partial sum
+  int max_w = 0, max_h = 0;
+  size_t w_off[kLayers] = {}, b_off[kLayers] = {}, n_prm = 0;  // parameter layout: per layer [w][b]
+  size_t w16_off[kLayers] = {}, n_w16 = 0;
+  float* prm = nullptr;     // FP32 master parameters
+  float* grad = nullptr;
+  float* mom1 = nullptr;
+  float* mom2 = nullptr;
+  uint16_t* w16 = nullptr;  // BF16 weights [tap][out][in]
+  uint16_t* wt16 = nullptr; // BF16 weights [tap][in][out]
+  uint16_t* act[kLayers] = {};  // layer inputs x0..x4
+  uint16_t* gbuf[2] = {};       // gradients of the layer outputs (ping-pong)
+  float* y = nullptr;           // last layer output, 16 FP32 per pixel
+  float4* planes = nullptr;     // candidate planes per pixel
+  float* part_w = nullptr;
+  float* part_b = nullptr;
+  double* part_loss = nullptr;
+  PinBuf<double> h_loss;
+  int steps = 0;  // Adam steps taken
 };
 
 namespace {
@@ -937,6 +965,54 @@ lexp_status lexp_init_labels(lexp_ctx* c, uint64_t seed, float* labels, void* hi
 
 namespace {
 
+constexpr int lexp_net_ch(int l) { return lexp_net::kCh[l]; }
+
+// Forward pass of the network on a context's images and a label field
+// (device HxWx4); the output stays in net->y, the planes in net->planes.
+lexp_status net_forward(lexp_net* net, lexp_ctx* c, const float* labels, hipStream_t s) {
+  const int W = c->W, H = c->H;
+  if (W > net->max_w || H > net->max_h)
+    return fail(LEXP_EINVAL, "image %dx%d larger than the network's %dx%d", W, H, net->max_w, net->max_h);
+  const int n = W * H;
+  hipLaunchKernelGGL(lexp::k_net_input, dim3((n + 255) / 256), dim3(256), 0, s, c->left4, c->right4,
+                     (const float4*)labels, W, H, (double)c->prm.disp_max, net->act[0]);
+  const int segs = ((W + 15) / 16) * H;
+  const dim3 grid((segs + 3) / 4);
+  for (int l = 0; l < lexp_net::kLayers; ++l) {
+    const uint16_t* w16 = net->w16 + net->w16_off[l];
+    const float* b = net->prm + net->b_off[l];
+    if (l == 0)
+      hipLaunchKernelGGL((lexp::k_conv_fwd<16, 32, false>), grid, dim3(256), 0, s, net->act[0], w16, b, W, H,
+                         net->act[1], (float*)nullptr);
+    else if (l < lexp_net::kLayers - 1)
+      hipLaunchKernelGGL((lexp::k_conv_fwd<32, 32, false>), grid, dim3(256), 0, s, net->act[l], w16, b, W, H,
+                         net->act[l + 1], (float*)nullptr);
+    else
+      hipLaunchKernelGGL((lexp::k_conv_fwd<32, 16, true>), grid, dim3(256), 0, s, net->act[l], w16, b, W, H,
+                         (uint16_t*)nullptr, net->y);
+  }
+  hipLaunchKernelGGL(lexp::k_net_planes, dim3((n + 255) / 256), dim3(256), 0, s, net->y, W, H,
+                     (double)c->prm.disp_max, net->planes);
+  HIP_TRY(hipGetLastError());
+  return LEXP_OK;
+}
+
+// Weight and bias gradients of layer l from the gradient g of its output.
+template <int CI, int CO>
+void net_weight_grad(lexp_net* net, int l, const uint16_t* g, int W, int H, hipStream_t s) {
+  const int n = W * H, chunks = (n + lexp_net::kChunk - 1) / lexp_net::kChunk;
+  hipLaunchKernelGGL((lexp::k_conv_bwd_w<CI, CO>), dim3(chunks, 9), dim3(256), 0, s, g, net->act[l], W, H,
+                     lexp_net::kChunk, net->part_w, net->part_b);
+  hipLaunchKernelGGL(lexp::k_sum_chunks, dim3((9 * CO * CI + 255) / 256), dim3(256), 0, s, net->part_w, chunks,
+                     9 * CO * CI, net->grad + net->w_off[l]);
+  hipLaunchKernelGGL(lexp::k_sum_chunks, dim3(1), dim3(256), 0, s, net->part_b, chunks, CO,
+                     net->grad + net->b_off[l]);
+}
+
+}  // namespace
+
+namespace {
+
 // One stereo pair of an optimisation run.
 struct RunPair {
   lexp_ctx* c = nullptr;
@@ -945,6 +1021,7 @@ struct RunPair {
   float* cur_cost = nullptr;
   double* energy_trace = nullptr;
   std::vector<float> mirror;  // host copy of the labels (HxWx3) for the proposers
+  std::vector<float> net_planes;  // learned proposals of the current level pass (HxWx4), if any
 };
 
 // One part of a group step: regions of one or more pairs (Item::pair), their
@@ -1004,7 +1081,8 @@ void propose_item(Part& P, const StepArgs& a, int q, int step) {
   const lexp_ctx* c = rp.c;
   float al[3];
   lexp::propose(c->W, c->H, rp.mirror.data(), 3, rp.seed, a.it, a.level, a.cell, P.ci[q], P.cj[q], step, a.kp,
-                a.kr, c->prm.disp_max / 2.0 * a.scale, a.scale, al);
+                a.kr, c->prm.disp_max / 2.0 * a.scale, a.scale, al,
+                rp.net_planes.empty() ? nullptr : rp.net_planes.data());
   item.a = al[0];
   item.b = al[1];
   item.c = al[2];
@@ -1283,6 +1361,10 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
         sch->k_prop[h] + sch->k_rans[h] + sch->k_rand[h] > 64)
       return fail(LEXP_EINVAL, "bad grid level %d", h);
   lexp_ctx* c = pairs[0].c;
+  if (sch->learned != 0 && sch->learned != 1) return fail(LEXP_EINVAL, "learned must be 0 or 1");
+  if (sch->learned)
+    for (int p = 0; p < np; ++p)
+      if (!pairs[p].c->net) return fail(LEXP_ESTATE, "pair %d: learned proposals need lexp_set_net", p);
   const auto t_start = std::chrono::steady_clock::now();
   auto now_s = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(); };
   lexp_status st;
@@ -1374,6 +1456,17 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     for (int h = 0; h < sch->n_levels; ++h) {
       const int K = sch->k_prop[h] + sch->k_rans[h] + sch->k_rand[h];
       const StepArgs a{it, h, sch->cell[h], sch->k_prop[h], sch->k_rans[h], scale, pairs};
+      if (sch->learned) {
+        // the network's planes from the labels at the start of the level pass
+        for (int p = 0; p < np; ++p) {
+          RunPair& rp = pairs[p];
+          if ((st = net_forward(rp.c->net, rp.c, rp.labels, s))) return st;
+          rp.net_planes.resize((size_t)rp.c->W * rp.c->H * 4);
+          HIP_TRY(hipMemcpyAsync(rp.net_planes.data(), rp.c->net->planes, sizeof(float) * rp.net_planes.size(),
+                                 hipMemcpyDeviceToHost, s));
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+      }
       for (int k = 0; k < 16; ++k) {
         const auto g0 = std::chrono::steady_clock::now();
         if ((st = split_group(h, k))) return st;
@@ -1454,6 +1547,202 @@ extern "C" lexp_status lexp_optimize_batch(int32_t n_pairs, lexp_ctx* const* ctx
 }
 
 extern "C" {
+
+lexp_status lexp_net_sizes(int32_t* n_weights, int32_t* n_biases) {
+  int32_t nw = 0, nb = 0;
+  for (int l = 0; l < lexp_net::kLayers; ++l) {
+    nw += 9 * lexp_net_ch(l) * lexp_net_ch(l + 1);
+    nb += lexp_net_ch(l + 1);
+  }
+  if (n_weights) *n_weights = nw;
+  if (n_biases) *n_biases = nb;
+  return LEXP_OK;
+}
+
+lexp_status lexp_net_destroy(lexp_net* net) {
+  if (!net) return LEXP_OK;
+  (void)hipDeviceSynchronize();
+  for (void* p : {(void*)net->prm, (void*)net->grad, (void*)net->mom1, (void*)net->mom2, (void*)net->w16,
+                  (void*)net->wt16, (void*)net->act[0], (void*)net->gbuf[0], (void*)net->y, (void*)net->planes,
+                  (void*)net->part_w, (void*)net->part_b, (void*)net->part_loss})
+    if (p) (void)hipFree(p);
+  net->h_loss.release();
+  delete net;
+  return LEXP_OK;
+}
+
+lexp_status lexp_net_set_weights(lexp_net* net, const float* weights, const float* biases) {
+  if (!net || !weights || !biases) return fail(LEXP_EINVAL, "null argument");
+  std::vector<float> h(net->n_prm);
+  size_t wi = 0, bi = 0;
+  for (int l = 0; l < lexp_net::kLayers; ++l) {
+    const size_t nw = (size_t)9 * lexp_net_ch(l) * lexp_net_ch(l + 1), nb = (size_t)lexp_net_ch(l + 1);
+    for (size_t e = 0; e < nw; ++e) h[net->w_off[l] + e] = weights[wi + e];
+    for (size_t e = 0; e < nb; ++e) h[net->b_off[l] + e] = biases[bi + e];
+    wi += nw;
+    bi += nb;
+  }
+  HIP_TRY(hipMemcpy(net->prm, h.data(), sizeof(float) * net->n_prm, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(net->mom1, 0, sizeof(float) * net->n_prm));
+  HIP_TRY(hipMemset(net->mom2, 0, sizeof(float) * net->n_prm));
+  net->steps = 0;
+  for (int l = 0; l < lexp_net::kLayers; ++l) {
+    const int co = lexp_net_ch(l + 1), ci = lexp_net_ch(l), nw = 9 * co * ci;
+    hipLaunchKernelGGL(lexp::k_net_w16, dim3((nw + 255) / 256), dim3(256), 0, 0, net->prm + net->w_off[l], nw, co,
+                       ci, net->w16 + net->w16_off[l], net->wt16 + net->w16_off[l]);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipDeviceSynchronize());
+  return LEXP_OK;
+}
+
+lexp_status lexp_net_get_weights(lexp_net* net, float* weights, float* biases) {
+  if (!net || !weights || !biases) return fail(LEXP_EINVAL, "null argument");
+  std::vector<float> h(net->n_prm);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(h.data(), net->prm, sizeof(float) * net->n_prm, hipMemcpyDeviceToHost));
+  size_t wi = 0, bi = 0;
+  for (int l = 0; l < lexp_net::kLayers; ++l) {
+    const size_t nw = (size_t)9 * lexp_net_ch(l) * lexp_net_ch(l + 1), nb = (size_t)lexp_net_ch(l + 1);
+    for (size_t e = 0; e < nw; ++e) weights[wi + e] = h[net->w_off[l] + e];
+    for (size_t e = 0; e < nb; ++e) biases[bi + e] = h[net->b_off[l] + e];
+    wi += nw;
+    bi += nb;
+  }
+  return LEXP_OK;
+}
+
+lexp_status lexp_net_create(int32_t max_width, int32_t max_height, uint64_t seed, lexp_net** out) {
+  if (!out || max_width <= 0 || max_height <= 0 || (int64_t)max_width * max_height > (1ll << 26))
+    return fail(LEXP_EINVAL, "bad argument");
+  std::unique_ptr<lexp_net> net(new lexp_net());
+  net->max_w = max_width;
+  net->max_h = max_height;
+  size_t off = 0, off16 = 0;
+  for (int l = 0; l < lexp_net::kLayers; ++l) {
+    const size_t nw = (size_t)9 * lexp_net_ch(l) * lexp_net_ch(l + 1);
+    net->w_off[l] = off;
+    net->b_off[l] = off + nw;
+    off += nw + lexp_net_ch(l + 1);
+    net->w16_off[l] = off16;
+    off16 += nw;
+  }
+  net->n_prm = off;
+  net->n_w16 = off16;
+  const size_t n = (size_t)max_width * max_height;
+  const size_t chunks = (n + lexp_net::kChunk - 1) / lexp_net::kChunk;
+  HIP_TRY(hipMalloc((void**)&net->prm, sizeof(float) * off));
+  HIP_TRY(hipMalloc((void**)&net->grad, sizeof(float) * off));
+  HIP_TRY(hipMalloc((void**)&net->mom1, sizeof(float) * off));
+  HIP_TRY(hipMalloc((void**)&net->mom2, sizeof(float) * off));
+  HIP_TRY(hipMalloc((void**)&net->w16, sizeof(uint16_t) * off16));
+  HIP_TRY(hipMalloc((void**)&net->wt16, sizeof(uint16_t) * off16));
+  size_t act = 0;
+  for (int l = 0; l < lexp_net::kLayers; ++l) act += n * lexp_net_ch(l);
+  HIP_TRY(hipMalloc((void**)&net->act[0], sizeof(uint16_t) * act));
+  for (int l = 1; l < lexp_net::kLayers; ++l) net->act[l] = net->act[l - 1] + n * lexp_net_ch(l - 1);
+  HIP_TRY(hipMalloc((void**)&net->gbuf[0], sizeof(uint16_t) * n * 32 * 2));
+  net->gbuf[1] = net->gbuf[0] + n * 32;
+  HIP_TRY(hipMalloc((void**)&net->y, sizeof(float) * n * 16));
+  HIP_TRY(hipMalloc((void**)&net->planes, sizeof(float4) * n));
+  HIP_TRY(hipMalloc((void**)&net->part_w, sizeof(float) * chunks * 9 * 32 * 32));
+  HIP_TRY(hipMalloc((void**)&net->part_b, sizeof(float) * chunks * 32));
+  HIP_TRY(hipMalloc((void**)&net->part_loss, sizeof(double) * ((n + 255) / 256)));
+  HIP_TRY(net->h_loss.ensure((n + 255) / 256));
+  // He-uniform weights from the counter-based generator, zero biases
+  std::vector<float> w, b;
+  for (int l = 0; l < lexp_net::kLayers; ++l) {
+    const int ci = lexp_net_ch(l), co = lexp_net_ch(l + 1);
+    const double lim = std::sqrt(6.0 / (9.0 * ci));
+    for (int e = 0; e < 9 * co * ci; ++e) {
+      const uint64_t key[3] = {5, (uint64_t)l, (uint64_t)e};
+      w.push_back((float)((2.0 * lexp::u01_open1(lexp::key_chain(seed, key, 3)) - 1.0) * lim));
+    }
+    for (int e = 0; e < co; ++e) b.push_back(0.f);
+  }
+  lexp_status st = lexp_net_set_weights(net.get(), w.data(), b.data());
+  if (st) return st;
+  *out = net.release();
+  return LEXP_OK;
+}
+
+lexp_status lexp_net_forward(lexp_net* net, lexp_ctx* c, const float* labels, float* out, void* hip_stream) {
+  if (!net || !c || !labels || !out) return fail(LEXP_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  lexp_status st = net_forward(net, c, labels, s);
+  if (st) return st;
+  HIP_TRY(hipMemcpyAsync(out, net->y, sizeof(float) * 16 * c->W * c->H, hipMemcpyDeviceToDevice, s));
+  return LEXP_OK;
+}
+
+lexp_status lexp_net_train_step(lexp_net* net, lexp_ctx* c, const float* labels, const float* target, float lr,
+                                double* loss, void* hip_stream) {
+  if (!net || !c || !labels || !target) return fail(LEXP_EINVAL, "null argument");
+  if (!(lr > 0.f)) return fail(LEXP_EINVAL, "learning rate must be positive");
+  hipStream_t s = (hipStream_t)hip_stream;
+  lexp_status st = net_forward(net, c, labels, s);
+  if (st) return st;
+  const int W = c->W, H = c->H, n = W * H;
+  const int nb = (n + 255) / 256;
+  uint16_t* g = net->gbuf[0];
+  hipLaunchKernelGGL(lexp::k_net_loss, dim3(nb), dim3(256), 0, s, net->y, (const float4*)target, W, H,
+                     (double)c->prm.disp_max, g, net->part_loss);
+  const int segs = ((W + 15) / 16) * H;
+  const dim3 grid((segs + 3) / 4);
+  // backward through the layers: weight gradients, then the gradient of the
+  // layer's input (through the ReLU that produced it)
+  for (int l = lexp_net::kLayers - 1; l >= 0; --l) {
+    uint16_t* gp = net->gbuf[(lexp_net::kLayers - l) & 1];
+    const uint16_t* wt = net->wt16 + net->w16_off[l];
+    if (l == lexp_net::kLayers - 1) {
+      net_weight_grad<32, 16>(net, l, g, W, H, s);
+      hipLaunchKernelGGL((lexp::k_conv_bwd_x<32, 16>), grid, dim3(256), 0, s, g, wt, net->act[l], W, H, gp);
+    } else if (l > 0) {
+      net_weight_grad<32, 32>(net, l, g, W, H, s);
+      hipLaunchKernelGGL((lexp::k_conv_bwd_x<32, 32>), grid, dim3(256), 0, s, g, wt, net->act[l], W, H, gp);
+    } else {
+      net_weight_grad<16, 32>(net, l, g, W, H, s);
+    }
+    g = gp;
+  }
+  net->steps += 1;
+  const float c1 = (float)(1.0 - std::pow(0.9, net->steps)), c2 = (float)(1.0 - std::pow(0.999, net->steps));
+  for (int l = 0; l < lexp_net::kLayers; ++l) {
+    const int co = lexp_net_ch(l + 1), ci = lexp_net_ch(l), nw = 9 * co * ci;
+    hipLaunchKernelGGL(lexp::k_net_adam, dim3((nw + co + 255) / 256), dim3(256), 0, s, net->prm + net->w_off[l],
+                       net->grad + net->w_off[l], net->mom1 + net->w_off[l], net->mom2 + net->w_off[l], nw + co, nw,
+                       co, ci, lr, c1, c2, net->w16 + net->w16_off[l], net->wt16 + net->w16_off[l]);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(net->h_loss.p, net->part_loss, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double sum = 0.0;
+  for (int b = 0; b < nb; ++b) sum += net->h_loss.p[b];
+  if (loss) *loss = sum / (double)n;
+  return LEXP_OK;
+}
+
+lexp_status lexp_net_get_grads(lexp_net* net, float* weights, float* biases) {
+  if (!net || !weights || !biases) return fail(LEXP_EINVAL, "null argument");
+  std::vector<float> h(net->n_prm);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(h.data(), net->grad, sizeof(float) * net->n_prm, hipMemcpyDeviceToHost));
+  size_t wi = 0, bi = 0;
+  for (int l = 0; l < lexp_net::kLayers; ++l) {
+    const size_t nw = (size_t)9 * lexp_net_ch(l) * lexp_net_ch(l + 1), nb = (size_t)lexp_net_ch(l + 1);
+    for (size_t e = 0; e < nw; ++e) weights[wi + e] = h[net->w_off[l] + e];
+    for (size_t e = 0; e < nb; ++e) biases[bi + e] = h[net->b_off[l] + e];
+    wi += nw;
+    bi += nb;
+  }
+  return LEXP_OK;
+}
+
+lexp_status lexp_set_net(lexp_ctx* c, lexp_net* net) {
+  if (!c) return fail(LEXP_EINVAL, "null context");
+  c->net = net;
+  return LEXP_OK;
+}
 
 lexp_status lexp_set_timing(lexp_ctx* c, int32_t enable) {
   if (!c) return fail(LEXP_EINVAL, "null context");

@@ -107,6 +107,25 @@ __global__ void k_cut_lds(const Item* items, const int* terms, int nf, uint8_t* 
 // excess, or forward residuals only with 32-bit excess and 16-bit heights
 constexpr int kCutBytesFull = 52;
 constexpr int kCutBytesCompact = 28;
+// learned proposal network (lexp_net.hip)
+__global__ void k_net_input(const float4* left4, const float4* right4, const float4* labels, int W, int H,
+                            double disp_max, uint16_t* x0);
+template <int CI, int CO, bool LAST>
+__global__ void k_conv_fwd(const uint16_t* x, const uint16_t* w16, const float* bias, int W, int H, uint16_t* xo,
+                           float* yo);
+template <int CI, int CO>
+__global__ void k_conv_bwd_x(const uint16_t* g, const uint16_t* wt16, const uint16_t* x, int W, int H,
+                             uint16_t* gp);
+template <int CI, int CO>
+__global__ void k_conv_bwd_w(const uint16_t* g, const uint16_t* x, int W, int H, int chunk_px, float* part_w,
+                             float* part_b);
+__global__ void k_sum_chunks(const float* part, int n_chunks, int n, float* out);
+__global__ void k_net_loss(const float* y, const float4* target, int W, int H, double disp_max, uint16_t* g,
+                           double* part);
+__global__ void k_net_adam(float* prm, const float* grad, float* m1, float* m2, int n, int n_w, int co, int ci,
+                           float lr, float c1, float c2, uint16_t* w16, uint16_t* wt16);
+__global__ void k_net_w16(const float* prm, int n_w, int co, int ci, uint16_t* w16, uint16_t* wt16);
+__global__ void k_net_planes(const float* y, int W, int H, double disp_max, float4* planes);
 __global__ void k_pair1(DevParams P, const double* wts, int pu, int pv, int qu, int qv, float4 fp, float4 fq,
                         double* out);
 

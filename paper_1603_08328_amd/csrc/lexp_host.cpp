@@ -184,7 +184,8 @@ static bool ransac_plane(int width, const float* labels, int stride, uint64_t se
 }
 
 void propose(int width, int height, const float* labels, int stride, uint64_t seed, int iteration, int level,
-             int cell, int ci, int cj, int step, int k_prop, int k_rans, double r_d, double r_n, float out[3]) {
+             int cell, int ci, int cj, int step, int k_prop, int k_rans, double r_d, double r_n, float out[3],
+             const float* net_planes) {
   const int cu0 = ci * cell, cv0 = cj * cell;
   const int cw = std::min(cu0 + cell, width) - cu0;
   const int chh = std::min(cv0 + cell, height) - cv0;
@@ -202,6 +203,11 @@ void propose(int width, int height, const float* labels, int stride, uint64_t se
     return;
   }
   if (step < k_prop + k_rans) return;
+  if (net_planes && ((step - k_prop - k_rans) & 1)) {  // learned refinement step
+    const float* g = net_planes + ((size_t)rv * width + ru) * 4;
+    out[0] = g[0]; out[1] = g[1]; out[2] = g[2];
+    return;
+  }
   double rd = r_d, rn = r_n;
   for (int k = 0; k < step - k_prop - k_rans; ++k) { rd *= 0.5; rn *= 0.5; }
   key[6] = 1;

@@ -25,8 +25,12 @@ void init_label(int width, int u, int v, double disp_max, uint64_t seed, float o
 // Candidate label of one alpha_ij-expansion step (Alg. 1), in its order:
 // k_prop propagation steps, k_rans RANSAC steps, then refinement steps.
 // labels: HxWx3 host mirror (stride `stride` floats per pixel).
+// net_planes (optional, HxWx4): planes proposed by the learned network; the
+// refinement steps with an odd refinement index then take the plane of the
+// chosen pixel r instead of a perturbation.
 void propose(int width, int height, const float* labels, int stride, uint64_t seed, int iteration, int level,
-             int cell, int ci, int cj, int step, int k_prop, int k_rans, double r_d, double r_n, float out[3]);
+             int cell, int ci, int cj, int step, int k_prop, int k_rans, double r_d, double r_n, float out[3],
+             const float* net_planes = nullptr);
 
 // ---- exact binary minimisation ------------------------------------------
 // E(x) = sum_i U_i x_i + sum_{i, d < nf} w_{i,d} (1 - x_i) x_{i + fwd_d} on a

@@ -45,7 +45,8 @@ class lexp_rect(C.Structure):
 
 class lexp_schedule(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("cell", C.c_int32 * 4), ("k_prop", C.c_int32 * 4),
-                ("k_rand", C.c_int32 * 4), ("iterations", C.c_int32), ("k_rans", C.c_int32 * 4)]
+                ("k_rand", C.c_int32 * 4), ("iterations", C.c_int32), ("k_rans", C.c_int32 * 4),
+                ("learned", C.c_int32)]
 
 
 class lexp_stats(C.Structure):
@@ -79,6 +80,15 @@ _SIGS = {
     "lexp_init_labels": (_i32, [_vp, _u64, _vp, _vp]),
     "lexp_optimize": (_i32, [_vp, C.POINTER(lexp_schedule), _u64, _vp, _vp, _vp, _vp, _vp]),
     "lexp_view_labels": (_i32, [_vp, _vp, _vp, _vp]),
+    "lexp_net_sizes": (_i32, [_vp, _vp]),
+    "lexp_net_create": (_i32, [_i32, _i32, _u64, C.POINTER(_vp)]),
+    "lexp_net_destroy": (_i32, [_vp]),
+    "lexp_net_set_weights": (_i32, [_vp, _vp, _vp]),
+    "lexp_net_get_weights": (_i32, [_vp, _vp, _vp]),
+    "lexp_net_get_grads": (_i32, [_vp, _vp, _vp]),
+    "lexp_net_forward": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "lexp_net_train_step": (_i32, [_vp, _vp, _vp, _vp, C.c_float, C.POINTER(_f64), _vp]),
+    "lexp_set_net": (_i32, [_vp, _vp]),
     "lexp_postprocess": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "lexp_optimize_batch": (_i32, [_i32, _vp, C.POINTER(lexp_schedule), _vp, _vp, _vp, _vp, _vp, _vp]),
     "lexp_set_timing": (_i32, [_vp, _i32]),
@@ -304,7 +314,7 @@ def lexp_init_labels(ctx, seed, labels, stream=None):
     _check(load_library().lexp_init_labels(ctx.handle, C.c_uint64(seed), lp, _stream_ptr(stream)))
 
 
-def make_schedule(grids, iterations) -> lexp_schedule:
+def make_schedule(grids, iterations, learned=False) -> lexp_schedule:
     s = lexp_schedule()
     if not 1 <= len(grids) <= 4:
         raise ValueError("1 to 4 grid levels")
@@ -313,15 +323,16 @@ def make_schedule(grids, iterations) -> lexp_schedule:
         s.cell[i], s.k_prop[i], s.k_rand[i] = int(g[0]), int(g[1]), int(g[2])
         s.k_rans[i] = int(g[3]) if len(g) > 3 else 0
     s.iterations = int(iterations)
+    s.learned = 1 if learned else 0
     return s
 
 
-def lexp_optimize(ctx, grids, iterations, seed, labels, cur_cost, stream=None):
+def lexp_optimize(ctx, grids, iterations, seed, labels, cur_cost, stream=None, learned=False):
     """Alg. 2 on the device + host; returns (energy_trace, time_trace)."""
     torch = _torch()
     lp = _dev(labels, torch.float32, (ctx.height, ctx.width, 4), name="labels")
     cp = _dev(cur_cost, torch.float32, (ctx.height, ctx.width), name="cur_cost")
-    sch = make_schedule(grids, iterations)
+    sch = make_schedule(grids, iterations, learned)
     e = np.zeros(iterations + 1)
     t = np.zeros(iterations + 1)
     _check(load_library().lexp_optimize(ctx.handle, C.byref(sch), C.c_uint64(seed), lp, cp, e.ctypes.data,
@@ -329,7 +340,7 @@ def lexp_optimize(ctx, grids, iterations, seed, labels, cur_cost, stream=None):
     return e, t
 
 
-def lexp_optimize_batch(ctxs, grids, iterations, seeds, labels, cur_costs, stream=None):
+def lexp_optimize_batch(ctxs, grids, iterations, seeds, labels, cur_costs, stream=None, learned=False):
     """Alg. 2 for several pairs at once (one launch per group step for all of
     them); returns (energy traces [n_pairs, iterations+1], time_trace)."""
     torch = _torch()
@@ -342,7 +353,7 @@ def lexp_optimize_batch(ctxs, grids, iterations, seeds, labels, cur_costs, strea
     cp = (C.c_void_p * n)(*[_dev(q, torch.float32, (c.height, c.width), name="cur_cost")
                             for c, q in zip(ctxs, cur_costs)])
     sd = (C.c_uint64 * n)(*[int(x) for x in seeds])
-    sch = make_schedule(grids, iterations)
+    sch = make_schedule(grids, iterations, learned)
     e = np.zeros((n, iterations + 1))
     ep = (C.c_void_p * n)(*[e[i].ctypes.data for i in range(n)])
     t = np.zeros(iterations + 1)
@@ -373,6 +384,86 @@ def lexp_postprocess(left_ctx, labels_left, right_ctx, labels_right, stream=None
     _check(load_library().lexp_postprocess(left_ctx.handle, lp, right_ctx.handle, rp, C.c_void_p(disp.data_ptr()),
                                            C.c_void_p(inv.data_ptr()), _stream_ptr(stream)))
     return disp, inv
+
+
+class LexpNet:
+    """Owns one lexp_net (the learned proposal network)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            load_library().lexp_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lexp_net_sizes():
+    nw, nb = C.c_int32(), C.c_int32()
+    _check(load_library().lexp_net_sizes(C.byref(nw), C.byref(nb)))
+    return nw.value, nb.value
+
+
+def lexp_net_create(max_width, max_height, seed=0) -> LexpNet:
+    out = C.c_void_p()
+    _check(load_library().lexp_net_create(int(max_width), int(max_height), C.c_uint64(seed), C.byref(out)))
+    return LexpNet(out)
+
+
+def lexp_net_set_weights(net, weights, biases):
+    nw, nb = lexp_net_sizes()
+    w = np.ascontiguousarray(np.asarray(weights, np.float32).ravel())
+    b = np.ascontiguousarray(np.asarray(biases, np.float32).ravel())
+    if w.size != nw or b.size != nb:
+        raise ValueError(f"need {nw} weights and {nb} biases")
+    _check(load_library().lexp_net_set_weights(net.handle, w.ctypes.data, b.ctypes.data))
+
+
+def _net_params(fn, net):
+    nw, nb = lexp_net_sizes()
+    w = np.zeros(nw, np.float32)
+    b = np.zeros(nb, np.float32)
+    _check(fn(net.handle, w.ctypes.data, b.ctypes.data))
+    return w, b
+
+
+def lexp_net_get_weights(net):
+    return _net_params(load_library().lexp_net_get_weights, net)
+
+
+def lexp_net_get_grads(net):
+    return _net_params(load_library().lexp_net_get_grads, net)
+
+
+def lexp_net_forward(net, ctx, labels, stream=None):
+    """Network output (device tensor HxWx16, FP32) for a context's labels."""
+    torch = _torch()
+    lp = _dev(labels, torch.float32, (ctx.height, ctx.width, 4), name="labels")
+    out = torch.empty((ctx.height, ctx.width, 16), dtype=torch.float32, device=labels.device)
+    _check(load_library().lexp_net_forward(net.handle, ctx.handle, lp, C.c_void_p(out.data_ptr()),
+                                           _stream_ptr(stream)))
+    return out
+
+
+def lexp_net_train_step(net, ctx, labels, target, lr=1e-3, stream=None) -> float:
+    torch = _torch()
+    lp = _dev(labels, torch.float32, (ctx.height, ctx.width, 4), name="labels")
+    tp = _dev(target, torch.float32, (ctx.height, ctx.width, 4), name="target")
+    loss = C.c_double()
+    _check(load_library().lexp_net_train_step(net.handle, ctx.handle, lp, tp, C.c_float(lr), C.byref(loss),
+                                              _stream_ptr(stream)))
+    return loss.value
+
+
+def lexp_set_net(ctx, net):
+    _check(load_library().lexp_set_net(ctx.handle, net.handle if net is not None else None))
+    ctx._net = net  # keep the network alive as long as the context uses it
 
 
 def lexp_set_timing(ctx, enable: bool):
