@@ -222,6 +222,32 @@ def run_both_views(seed: int = 0):
                 bad2_pct_before=bad(d0, 2.0), bad2_pct_after=bad(d1, 2.0))
 
 
+def run_learned(n_train: int, epochs: int, n_eval: int):
+    """Learned proposals: training set, training, held-out evaluation and the
+    matrix-core throughput of the network's convolutions."""
+    import torch
+
+    import paper_1603_08328_amd.lexp as L
+    from paper_1603_08328_amd import learned as LP
+
+    t0 = time.perf_counter()
+    samples = LP.make_training_set(range(1000, 1000 + n_train))
+    t_data = time.perf_counter() - t0
+    net = L.lexp_net_create(450, 375, seed=0)
+    t0 = time.perf_counter()
+    hist = LP.train(net, samples, epochs=epochs, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    res = LP.evaluate(net, range(1200, 1200 + n_eval))
+    ctx, lab, _ = samples[0]
+    f_ms, t_ms, f_tf, t_tf = LP.conv_throughput(net, ctx, lab)
+    steps = len(samples) * epochs
+    return dict(train_pairs=n_train, samples=len(samples), epochs=epochs, data_s=t_data, train_s=t_train,
+                train_step_ms=t_train / steps * 1e3, loss_per_epoch=[round(x, 4) for x in hist],
+                forward_ms=f_ms, train_step_bench_ms=t_ms, forward_tflops=f_tf, train_tflops=t_tf,
+                bf16_peak_tflops=2500.0, eval=res)
+
+
 def run_cpu_baseline():
     """The oracle on a bounded sample of the same workload: initial per-pixel
     costs of the regions of a sample of group-0 cells at grid levels 5/15/25 px
@@ -309,6 +335,11 @@ def main():
     ap.add_argument("--iterations", type=int, default=10, help="iterations of the many-pair runs")
     ap.add_argument("--both-views", action="store_true",
                     help="instead: both views batched, then the post-processing (times and ground-truth errors)")
+    ap.add_argument("--learned", action="store_true",
+                    help="instead: train the proposal network and compare the plain method with learned proposals")
+    ap.add_argument("--train-pairs", type=int, default=32)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--eval-pairs", type=int, default=4)
     ap.add_argument("--k-rans", type=int, default=0,
                     help="RANSAC proposer steps per cell and level (Alg. 1; 0 in the workload as specified)")
     args = ap.parse_args()
@@ -316,6 +347,10 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path runs on a single "
               "MI355X; see the design notes for how it would shard)", file=sys.stderr)
         sys.exit(2)
+    if args.learned:
+        print(json.dumps({"workload": "learned proposals, 450x375 synthetic pairs",
+                          "learned": run_learned(args.train_pairs, args.epochs, args.eval_pairs)}), flush=True)
+        return
     if args.both_views:
         print(json.dumps({"workload": "450x375 synthetic pair, both views and post-processing",
                           "both_views": run_both_views()}), flush=True)
