@@ -248,6 +248,43 @@ def run_learned(n_train: int, epochs: int, n_eval: int):
                 bf16_peak_tflops=2500.0, eval=res)
 
 
+def run_graph_compare(steps: int, seed: int = 0):
+    """Whole plain-method runs on the 450x375 pair with the device work of
+    each part step launched eagerly and replayed from captured HIP graphs
+    (timing off in both, since timing events are not captured)."""
+    import torch
+
+    import paper_1603_08328_amd.lexp as L
+    from synth import make_workload_pair, params_for, workload
+
+    wl = workload(WORKLOAD)
+    prm = params_for(WORKLOAD)
+    pair = make_workload_pair(WORKLOAD)
+    dev = torch.device("cuda:0")
+    left = torch.from_numpy(pair.left).to(dev)
+    right = torch.from_numpy(pair.right).to(dev)
+    h, w = pair.left.shape[:2]
+    out = {}
+    for graph in (0, 1, 0, 1):
+        ctx = L.lexp_create(dict(prm, graph=graph), left, right)
+        lab = torch.zeros((h, w, 4), device=dev)
+        cost = torch.zeros((h, w), device=dev)
+        L.lexp_optimize(ctx, wl["grids"], 1, seed, lab, cost)  # warm-up
+        torch.cuda.synchronize()
+        L.lexp_reset_stats(ctx)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            e, _ = L.lexp_optimize(ctx, wl["grids"], wl["iterations"], seed, lab, cost)
+        torch.cuda.synchronize()
+        st = L.lexp_get_stats(ctx)
+        key = "graph" if graph else "eager"
+        out[key] = dict(ms_per_run=(time.perf_counter() - t0) / steps * 1e3, final_energy=float(e[-1]),
+                        host_enqueue_ms_per_run=st["host_enqueue_ms"] / steps,
+                        graphs_captured_per_run=st["graphs_captured"] / steps)
+        ctx.close()
+    return out
+
+
 def run_cpu_baseline():
     """The oracle on a bounded sample of the same workload: initial per-pixel
     costs of the regions of a sample of group-0 cells at grid levels 5/15/25 px
@@ -340,6 +377,8 @@ def main():
     ap.add_argument("--train-pairs", type=int, default=32)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--eval-pairs", type=int, default=4)
+    ap.add_argument("--graph-compare", action="store_true",
+                    help="instead: whole runs with eager launches and with HIP-graph replay of each part step")
     ap.add_argument("--k-rans", type=int, default=0,
                     help="RANSAC proposer steps per cell and level (Alg. 1; 0 in the workload as specified)")
     args = ap.parse_args()
@@ -347,6 +386,10 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this path runs on a single "
               "MI355X; see the design notes for how it would shard)", file=sys.stderr)
         sys.exit(2)
+    if args.graph_compare:
+        print(json.dumps({"workload": "450x375 synthetic pair, eager vs HIP-graph launches",
+                          "graph_compare": run_graph_compare(args.steps)}), flush=True)
+        return
     if args.learned:
         print(json.dumps({"workload": "learned proposals, 450x375 synthetic pairs",
                           "learned": run_learned(args.train_pairs, args.epochs, args.eval_pairs)}), flush=True)

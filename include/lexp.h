@@ -79,6 +79,15 @@ typedef struct {
  *                              is the right image's plane (-a, b, c + a (W-1))
  *                              (lexp_view_labels converts).  The images passed to
  *                              lexp_create are (left, right) for both views.
+ *   graph                    : lexp_optimize: 1 = the device work of each step of a
+ *                              part (items copy, cost kernel, graph terms, device
+ *                              max-flow, copy back) is captured once per split of
+ *                              its group into a HIP graph and replayed for every
+ *                              candidate step (the device/host split of each level
+ *                              is tuned in the first iteration only, then kept, so
+ *                              later iterations replay); runs with timing enabled launch
+ *                              eagerly (timing events are not captured).  Same
+ *                              results either way.
  */
 typedef struct {
   int32_t width, height;
@@ -91,6 +100,7 @@ typedef struct {
   int32_t host_threads;
   int32_t device_cut;
   int32_t view;
+  int32_t graph;
 } lexp_params;
 
 /* Grid levels of the optimisation procedure (Alg. 2): cell size in pixels and
@@ -126,6 +136,7 @@ typedef struct {
   int64_t device_cut_fallbacks; /* lexp_optimize: regions the device max-flow left to the host */
   double device_cut_share[4];   /* lexp_optimize: share of each level's device-sized regions cut on
                                    the device in the last iteration (0 with device_cut off) */
+  int64_t graphs_captured;      /* lexp_optimize: HIP graphs captured (graph mode) */
 } lexp_stats;
 
 /* Creates a context for one stereo pair and runs the label-independent set-up

@@ -162,6 +162,7 @@ struct lexp_ctx {
   } part[2];
   size_t res_items = 0;  // status slots in the result buffers
   lexp_net* net = nullptr;  // learned proposals for lexp_optimize (not owned)
+  hipStream_t capture_stream = nullptr;  // graph mode: work is captured here, replayed on the caller's stream
 };
 
 // The learned proposal network (five 3x3 convolutions, channels 16 -> 32 ->
@@ -684,6 +685,7 @@ lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const 
   if (p.host_threads < 0 || p.host_threads > 64) return fail(LEXP_EINVAL, "host_threads outside [0, 64]");
   if (p.device_cut != 0 && p.device_cut != 1) return fail(LEXP_EINVAL, "device_cut must be 0 or 1");
   if (p.view != 0 && p.view != 1) return fail(LEXP_EINVAL, "view must be 0 (left) or 1 (right)");
+  if (p.graph != 0 && p.graph != 1) return fail(LEXP_EINVAL, "graph must be 0 or 1");
   hipStream_t s = (hipStream_t)hip_stream;
   std::unique_ptr<lexp_ctx> c(new lexp_ctx());
   c->prm = p;
@@ -753,6 +755,7 @@ lexp_status lexp_destroy(lexp_ctx* c) {
   collect_timing(c);
   for (hipEvent_t e : c->ev_free) (void)hipEventDestroy(e);
   if (c->staging_done) (void)hipEventDestroy(c->staging_done);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   (void)hipFree(c->left4);
   (void)hipFree(c->left4T);
   (void)hipFree(c->right4);
@@ -1035,7 +1038,13 @@ struct Part {
   TileCaps caps;
   double bytes = 0.0;
   bool device_cut = false;  // minimum cuts by the device max-flow
+  hipGraphExec_t graph = nullptr;  // captured device sequence of one step of this part (graph mode)
 };
+
+void drop_graph(Part& P) {
+  if (P.graph) (void)hipGraphExecDestroy(P.graph);
+  P.graph = nullptr;
+}
 
 // Split of each grid level's cuts between the device max-flow and the host
 // pool.  Per group step the device evaluates and cuts part 0 while the host
@@ -1091,11 +1100,9 @@ void propose_item(Part& P, const StepArgs& a, int q, int step) {
 // A part's items (with their candidates already proposed), cost kernel, graph
 // terms and the copy of the terms (or of the device cut) to the host, all
 // queued on the stream.
-lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairDev* d_pairs, const Tile* d_tiles,
-                         hipStream_t s) {
-  const auto t0 = std::chrono::steady_clock::now();
+lexp_status part_device_work(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairDev* d_pairs, const Tile* d_tiles,
+                             hipStream_t s) {
   const int n = (int)P.items.size();
-  std::copy(P.items.begin(), P.items.end(), B.h_items.p);
   HIP_TRY(hipMemcpyAsync(B.d_items.p, B.h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
   lexp_status st = launch_unary<0>(c, d_pairs, B.d_items.p, d_tiles + P.tile_off, (int)P.n_tiles, P.caps, nullptr,
                                    B.d_phi.p, s, P.bytes, P.n_px, n);
@@ -1113,6 +1120,47 @@ lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairD
                        B.d_phi.p, B.d_terms.p + 1, B.d_terms.p);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(B.h_terms.p, B.d_terms.p, sizeof(int) * (1 + 5 * P.n_px), hipMemcpyDeviceToHost, s));
+  }
+  return LEXP_OK;
+}
+
+// Queues one step of a part: its items (candidates already proposed) go to
+// the pinned staging buffer, then the device work.  In graph mode the device
+// work of the part's current split is captured once into a HIP graph (the
+// items copy from the same pinned buffer, the kernels, the copy back) and
+// replayed for every candidate step.
+lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairDev* d_pairs, const Tile* d_tiles,
+                         bool use_graph, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  std::copy(P.items.begin(), P.items.end(), B.h_items.p);
+  if (use_graph) {
+    if (!P.graph) {
+      // captured on a stream of the context's own (the caller's stream may be
+      // the legacy default stream, which cannot be captured); nothing runs
+      // during capture, and the graph is launched on the caller's stream
+      if (!c->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+      const hipStream_t cs = c->capture_stream;
+      HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      lexp_status st = part_device_work(c, P, B, d_pairs, d_tiles, cs);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(cs, &g);
+      if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return fail(LEXP_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+      const hipError_t e2 = hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e2 != hipSuccess) {
+        P.graph = nullptr;
+        return fail(LEXP_EDEVICE, "graph instantiation: %s", hipGetErrorString(e2));
+      }
+      c->stats.graphs_captured += 1;
+    }
+    HIP_TRY(hipGraphLaunch(P.graph, s));
+  } else {
+    lexp_status st = part_device_work(c, P, B, d_pairs, d_tiles, s);
+    if (st) return st;
   }
   HIP_TRY(hipEventRecord(B.ready, s));
   c->stats.host_enqueue_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1382,8 +1430,16 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
   // device and part 1 on the host, in a proportion balanced per level after
   // every iteration; otherwise both are cut on the host.
   const bool dev_cut = c->prm.device_cut != 0;
+  // kernel timing events are not captured, so a timed run launches eagerly
+  const bool use_graph = c->prm.graph != 0 && !c->timing;
   std::vector<GroupPlan> groups((size_t)sch->n_levels * 16);
   std::vector<Part> parts((size_t)sch->n_levels * 16 * 2);
+  struct GraphGuard {  // frees the captured graphs on every way out
+    std::vector<Part>& p;
+    ~GraphGuard() {
+      for (Part& x : p) drop_graph(x);
+    }
+  } graph_guard{parts};
   std::vector<CutBalance> balance((size_t)sch->n_levels);
   size_t n_tiles = 0;
   int64_t max_px = 1;
@@ -1415,6 +1471,8 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     const double share = dev_cut ? balance[h].share : -1.0;
     if (g.share == share) return LEXP_OK;
     g.share = share;
+    drop_graph(parts[((size_t)h * 16 + k) * 2]);
+    drop_graph(parts[((size_t)h * 16 + k) * 2 + 1]);
     assign_parts(pairs, g, share, &parts[((size_t)h * 16 + k) * 2], c->h_tiles.p);
     if (g.n_tiles > 0)
       HIP_TRY(hipMemcpyAsync(c->d_tiles.p + g.tile_off, c->h_tiles.p + g.tile_off, sizeof(Tile) * g.n_tiles,
@@ -1478,7 +1536,7 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
           if (!P[hp]->items.empty() && K > 0) {
             Part& Q = *P[hp];
             pool_of(c).parallel_for((int)Q.items.size(), [&](int q, int) { propose_item(Q, a, q, 0); });
-            if ((st = enqueue_part(c, Q, c->part[hp], d_pairs, c->d_tiles.p, s))) return st;
+            if ((st = enqueue_part(c, Q, c->part[hp], d_pairs, c->d_tiles.p, use_graph, s))) return st;
           }
         for (int step = 0; step < K; ++step)
           for (int hp = 0; hp < 2; ++hp) {
@@ -1486,12 +1544,16 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
             const int next = step + 1 < K ? step + 1 : -1;
             if ((st = finish_part(c, *P[hp], c->part[hp], a, next, d_pairs, s))) return st;
             if (next >= 0)
-              if ((st = enqueue_part(c, *P[hp], c->part[hp], d_pairs, c->d_tiles.p, s))) return st;
+              if ((st = enqueue_part(c, *P[hp], c->part[hp], d_pairs, c->d_tiles.p, use_graph, s))) return st;
           }
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - g0).count();
         balance[h].update(ms / (double)std::max<int64_t>(1, groups[(size_t)h * 16 + k].n_px));
       }
     }
+    // graph mode keeps the splits tuned in the first iteration, so each
+    // group's captured graphs are replayed by the later iterations
+    if (use_graph)
+      for (CutBalance& b : balance) b.tune = false;
     scale *= 0.5;  // Alg. 2 line 12
     for (int p = 0; p < np; ++p) {
       RunPair& rp = pairs[p];
@@ -1502,6 +1564,7 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     if (time_trace) time_trace[it + 1] = now_s();
   }
   HIP_TRY(hipStreamSynchronize(s));
+  for (Part& P : parts) drop_graph(P);
   for (int h = 0; h < 4; ++h) c->stats.device_cut_share[h] = dev_cut && h < sch->n_levels ? balance[h].share : 0.0;
   for (int p = 0; p < np; ++p) HIP_TRY(hipEventRecord(pairs[p].c->staging_done, s));
   if (c->timing) collect_timing(c);

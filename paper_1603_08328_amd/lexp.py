@@ -32,7 +32,7 @@ class lexp_params(C.Structure):
                 ("gf_radius", C.c_int32), ("gf_eps", C.c_double),
                 ("lam", C.c_double), ("tau_dis", C.c_double), ("w_floor", C.c_double),
                 ("gamma", C.c_double), ("neighbours", C.c_int32), ("host_threads", C.c_int32),
-                ("device_cut", C.c_int32), ("view", C.c_int32)]
+                ("device_cut", C.c_int32), ("view", C.c_int32), ("graph", C.c_int32)]
 
 
 class lexp_plane(C.Structure):
@@ -55,7 +55,7 @@ class lexp_stats(C.Structure):
                 ("expand_calls", C.c_int64), ("host_cut_ms", C.c_double), ("host_wait_ms", C.c_double),
                 ("host_enqueue_ms", C.c_double), ("host_update_ms", C.c_double),
                 ("host_cut_level_ms", C.c_double * 4), ("device_cut_fallbacks", C.c_int64),
-                ("device_cut_share", C.c_double * 4)]
+                ("device_cut_share", C.c_double * 4), ("graphs_captured", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -213,7 +213,7 @@ def lexp_create(params: dict, left, right, stream=None) -> LexpContext:
                     float(params["tau_grad"]), int(params["gf_radius"]), float(params["gf_eps"]),
                     float(params["lam"]), float(params["tau_dis"]), float(params["w_floor"]),
                     float(params["gamma"]), int(params["neighbours"]), int(params.get("host_threads", 0)),
-                    int(params.get("device_cut", 1)), int(params.get("view", 0)))
+                    int(params.get("device_cut", 1)), int(params.get("view", 0)), int(params.get("graph", 0)))
     lp = _dev(left, torch.float32, (h, w, 3), name="left")
     rp = _dev(right, torch.float32, (h, w, 3), name="right")
     out = C.c_void_p()

@@ -793,3 +793,33 @@ def test_postprocess_rejects_wrong_views(tiny):
     lab = torch.zeros((tiny.H, tiny.W, 4), device="cuda")
     with pytest.raises(L.LexpError):
         L.lexp_postprocess(tiny.ctx, lab, tiny.ctx, lab)
+
+
+@pytest.mark.parametrize("which", ["tiny", "lowres"])
+def test_graph_mode_gives_identical_runs(tiny, lowres, which):
+    """Each part step's device work captured in a HIP graph and replayed:
+    labels, costs and energies equal the eager run's bit for bit (single
+    pair, and a batch of two pairs)."""
+    P = tiny if which == "tiny" else lowres
+    grids = [(5, 1, 3)] if which == "tiny" else [(5, 1, 7), (15, 1, 7), (25, 1, 7)]
+    runs = []
+    for graph in (0, 1):
+        ctx = L.lexp_create(dict(P.p, graph=graph), _cuda(P.left), _cuda(P.right))
+        ctx2 = L.lexp_create(dict(P.p, graph=graph, view=1), _cuda(P.left), _cuda(P.right))
+        lab = torch.zeros((P.H, P.W, 4), device="cuda")
+        cost = torch.zeros((P.H, P.W), device="cuda")
+        e, _ = L.lexp_optimize(ctx, grids, 1, 4, lab, cost)
+        labs = [torch.zeros_like(lab), torch.zeros_like(lab)]
+        costs = [torch.zeros_like(cost), torch.zeros_like(cost)]
+        es, _ = L.lexp_optimize_batch([ctx, ctx2], grids, 1, [4, 9], labs, costs)
+        st = L.lexp_get_stats(ctx)
+        runs.append((lab.cpu().numpy(), cost.cpu().numpy(), e, [x.cpu().numpy() for x in labs], es))
+        assert (st["graphs_captured"] > 0) == bool(graph)
+        ctx.close()
+        ctx2.close()
+    a, b = runs
+    assert np.array_equal(a[0].view(np.uint32), b[0].view(np.uint32))
+    assert np.array_equal(a[1].view(np.uint32), b[1].view(np.uint32))
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[4], b[4])
+    for x, y in zip(a[3], b[3]):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
