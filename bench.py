@@ -172,6 +172,7 @@ def run_many_pairs(n_pairs: int, iterations: int, seed: int = 0):
                 batch_host_cut_level_ms=[round(x, 2) for x in bst["host_cut_level_ms"]],
                 batch_device_cut_fallbacks=bst["device_cut_fallbacks"],
                 batch_device_cut_share=[round(x, 3) for x in bst["device_cut_share"]],
+                batch_device_cut_shape=[[b, e] for b, e in zip(bst["device_cut_block"], bst["device_cut_relabel"])],
                 batch_alg_gbps=bst["unary_alg_bytes"] / max(bst["unary_kernel_ms"], 1e-9) / 1e6)
 
 
@@ -463,6 +464,7 @@ def main():
         "host_update_ms_per_step": g["stats"]["host_update_ms"],
         "host_cut_level_ms_per_step": [round(x, 2) for x in g["stats"]["host_cut_level_ms"]],
         "device_cut_share": [round(x, 3) for x in g["stats"]["device_cut_share"]],
+        "device_cut_shape": [[b, e] for b, e in zip(g["stats"]["device_cut_block"], g["stats"]["device_cut_relabel"])],
     }
     print(json.dumps(out), flush=True)
 

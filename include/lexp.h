@@ -137,6 +137,9 @@ typedef struct {
   double device_cut_share[4];   /* lexp_optimize: share of each level's device-sized regions cut on
                                    the device in the last iteration (0 with device_cut off) */
   int64_t graphs_captured;      /* lexp_optimize: HIP graphs captured (graph mode) */
+  int32_t device_cut_block[4];  /* lexp_optimize: threads per region the device max-flow's launch-shape
+                                   tuner chose per level (0: not tuned; every shape gives the same cut) */
+  int32_t device_cut_relabel[4];/* its rounds between global relabels */
 } lexp_stats;
 
 /* Creates a context for one stereo pair and runs the label-independent set-up

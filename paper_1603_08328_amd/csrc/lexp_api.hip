@@ -159,6 +159,9 @@ struct lexp_ctx {
     PinBuf<uint8_t> h_x;
     PinBuf<unsigned char> h_res;
     hipEvent_t ready = nullptr;
+    hipEvent_t cut0 = nullptr, cut1 = nullptr;  // around a timed device max-flow launch
+    bool cut_timed = false;
+    int cut_block = 0, cut_every = 0;  // shape of that launch
   } part[2];
   size_t res_items = 0;  // status slots in the result buffers
   lexp_net* net = nullptr;  // learned proposals for lexp_optimize (not owned)
@@ -409,25 +412,61 @@ bool cut_fits(const lexp_ctx* c, int64_t px) {
   return px * lexp::kCutBytesCompact <= (int64_t)c->lds_limit - 64;
 }
 
+// Launch shape of the device max-flow: threads per region and push-relabel
+// rounds between global relabels.  Every shape returns the same exact cut.
+struct CutShape {
+  int block = 0;  // 0: the default rule
+  int every = 0;
+};
+
+bool cut_full_fits(const lexp_ctx* c, int64_t px) {
+  return px * lexp::kCutBytesFull + 64 <= (int64_t)c->lds_limit;
+}
+
+// Shapes worth trying for a launch whose largest region has max_px nodes.
+std::vector<CutShape> cut_shapes(const lexp_ctx* c, int max_px) {
+  std::vector<CutShape> v;
+  if (max_px <= 512) {
+    for (int b : {128, 256, 512})
+      for (int e : {4, 8, 16}) v.push_back({b, e});
+  } else if (cut_full_fits(c, max_px)) {
+    for (int b : {512, 1024})
+      for (int e : {8, 16, 32}) v.push_back({b, e});
+  } else {
+    for (int e : {8, 16, 32}) v.push_back({1024, e});
+  }
+  return v;
+}
+
 // Device minimum cuts of n regions whose terms start at the items' aux_off;
 // x at the same offsets, one status per item.  Every region must fit.
 lexp_status launch_cut(lexp_ctx* c, const Item* d_items, int n, const int* d_terms, uint8_t* d_x, int* d_status,
-                       int max_px, hipStream_t s) {
+                       int max_px, hipStream_t s, CutShape shape = CutShape{}) {
   if (n <= 0) return LEXP_OK;
   if (!cut_fits(c, max_px)) return fail(LEXP_ESTATE, "region of %d pixels too large for the device max-flow", max_px);
   const int nf = c->dp.nf;
-  const int every = cut_relabel_every(max_px);
-  const size_t full = (size_t)max_px * lexp::kCutBytesFull;
-  if (max_px <= 512)
-    hipLaunchKernelGGL((lexp::k_cut_lds<lexp::FullLayout, 256>), dim3(n), dim3(256), full, s, d_items, d_terms, nf,
-                       d_x, d_status, max_px, kCutRoundFactor, every);
-  else if (full + 64 <= c->lds_limit)
-    hipLaunchKernelGGL((lexp::k_cut_lds<lexp::FullLayout, 1024>), dim3(n), dim3(1024), full, s, d_items, d_terms,
-                       nf, d_x, d_status, max_px, kCutRoundFactor, every);
-  else
-    hipLaunchKernelGGL((lexp::k_cut_lds<lexp::CompactLayout, 1024>), dim3(n), dim3(1024),
-                       (size_t)max_px * lexp::kCutBytesCompact, s, d_items, d_terms, nf, d_x, d_status, max_px,
-                       kCutRoundFactor, every);
+  const bool full = cut_full_fits(c, max_px);
+  if (shape.block == 0) shape = CutShape{max_px <= 512 ? 256 : 1024, cut_relabel_every(max_px)};
+  const int every = shape.every;
+  const size_t lds = (size_t)max_px * (full ? lexp::kCutBytesFull : lexp::kCutBytesCompact);
+#define LEXP_CUT(L, B)                                                                                        \
+  hipLaunchKernelGGL((lexp::k_cut_lds<lexp::L, B>), dim3(n), dim3(B), lds, s, d_items, d_terms, nf, d_x, d_status, \
+                     max_px, kCutRoundFactor, every)
+  if (!full) {
+    if (shape.block != 1024) return fail(LEXP_ESTATE, "compact device max-flow runs 1024 threads per region");
+    LEXP_CUT(CompactLayout, 1024);
+  } else if (shape.block == 128) {
+    LEXP_CUT(FullLayout, 128);
+  } else if (shape.block == 256) {
+    LEXP_CUT(FullLayout, 256);
+  } else if (shape.block == 512) {
+    LEXP_CUT(FullLayout, 512);
+  } else if (shape.block == 1024) {
+    LEXP_CUT(FullLayout, 1024);
+  } else {
+    return fail(LEXP_ESTATE, "device max-flow block %d not built", shape.block);
+  }
+#undef LEXP_CUT
   HIP_TRY(hipGetLastError());
   return LEXP_OK;
 }
@@ -772,6 +811,8 @@ lexp_status lexp_destroy(lexp_ctx* c) {
     b.d_items.release(); b.d_phi.release(); b.d_terms.release(); b.d_x.release(); b.d_res.release();
     b.h_items.release(); b.h_terms.release(); b.h_x.release(); b.h_res.release();
     if (b.ready) (void)hipEventDestroy(b.ready);
+    if (b.cut0) (void)hipEventDestroy(b.cut0);
+    if (b.cut1) (void)hipEventDestroy(b.cut1);
   }
   delete c;
   return LEXP_OK;
@@ -1041,6 +1082,46 @@ struct Part {
   hipGraphExec_t graph = nullptr;  // captured device sequence of one step of this part (graph mode)
 };
 
+// Per grid level: picks the device max-flow's launch shape by timing each
+// candidate shape twice, interleaved, on the level's first device-cut steps,
+// then keeps the fastest on average.  A launch whose largest region is of
+// another size class than the first gets the default shape.
+struct CutTuner {
+  static constexpr int kRounds = 2;
+  std::vector<CutShape> cand;
+  std::vector<double> ms;
+  int cls = -1, trials = 0;
+  bool done = false;
+  CutShape best{};
+
+  static int size_class(const lexp_ctx* c, int max_px) { return max_px <= 512 ? 0 : (cut_full_fits(c, max_px) ? 1 : 2); }
+
+  CutShape pick(const lexp_ctx* c, int max_px, bool* timed) {
+    *timed = false;
+    if (cls < 0) {
+      cls = size_class(c, max_px);
+      cand = cut_shapes(c, max_px);
+      ms.assign(cand.size(), 0.0);
+    }
+    if (size_class(c, max_px) != cls) return CutShape{};
+    if (done) return best;
+    *timed = true;
+    return cand[trials % cand.size()];
+  }
+
+  void report(int block, int every, double t) {
+    for (size_t i = 0; i < cand.size(); ++i)
+      if (cand[i].block == block && cand[i].every == every) ms[i] += t;
+    if (++trials >= kRounds * (int)cand.size()) {
+      size_t b = 0;
+      for (size_t i = 1; i < cand.size(); ++i)
+        if (ms[i] < ms[b]) b = i;
+      best = cand[b];
+      done = true;
+    }
+  }
+};
+
 void drop_graph(Part& P) {
   if (P.graph) (void)hipGraphExecDestroy(P.graph);
   P.graph = nullptr;
@@ -1101,7 +1182,7 @@ void propose_item(Part& P, const StepArgs& a, int q, int step) {
 // terms and the copy of the terms (or of the device cut) to the host, all
 // queued on the stream.
 lexp_status part_device_work(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairDev* d_pairs, const Tile* d_tiles,
-                             hipStream_t s) {
+                             CutTuner* tuner, hipStream_t s) {
   const int n = (int)P.items.size();
   HIP_TRY(hipMemcpyAsync(B.d_items.p, B.h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
   lexp_status st = launch_unary<0>(c, d_pairs, B.d_items.p, d_tiles + P.tile_off, (int)P.n_tiles, P.caps, nullptr,
@@ -1112,8 +1193,16 @@ lexp_status part_device_work(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const P
     hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, d_pairs, B.d_items.p,
                        B.d_phi.p, B.d_terms.p + 1, flag);
     HIP_TRY(hipGetLastError());
-    if ((st = launch_cut(c, B.d_items.p, n, B.d_terms.p + 1, B.d_res.p + 4 + 4 * c->res_items, flag + 1, P.max_px, s)))
+    bool timed = false;
+    const CutShape shape = tuner ? tuner->pick(c, P.max_px, &timed) : CutShape{};
+    if (timed) HIP_TRY(hipEventRecord(B.cut0, s));
+    if ((st = launch_cut(c, B.d_items.p, n, B.d_terms.p + 1, B.d_res.p + 4 + 4 * c->res_items, flag + 1, P.max_px, s,
+                         shape)))
       return st;
+    if (timed) HIP_TRY(hipEventRecord(B.cut1, s));
+    B.cut_timed = timed;
+    B.cut_block = shape.block;
+    B.cut_every = shape.every;
     HIP_TRY(hipMemcpyAsync(B.h_res.p, B.d_res.p, 4 + 4 * c->res_items + (size_t)P.n_px, hipMemcpyDeviceToHost, s));
   } else {
     hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, d_pairs, B.d_items.p,
@@ -1130,7 +1219,7 @@ lexp_status part_device_work(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const P
 // items copy from the same pinned buffer, the kernels, the copy back) and
 // replayed for every candidate step.
 lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairDev* d_pairs, const Tile* d_tiles,
-                         bool use_graph, hipStream_t s) {
+                         bool use_graph, CutTuner* tuner, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
   std::copy(P.items.begin(), P.items.end(), B.h_items.p);
   if (use_graph) {
@@ -1141,7 +1230,7 @@ lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairD
       if (!c->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
       const hipStream_t cs = c->capture_stream;
       HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      lexp_status st = part_device_work(c, P, B, d_pairs, d_tiles, cs);
+      lexp_status st = part_device_work(c, P, B, d_pairs, d_tiles, nullptr, cs);
       hipGraph_t g = nullptr;
       const hipError_t e = hipStreamEndCapture(cs, &g);
       if (st) {
@@ -1159,7 +1248,7 @@ lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairD
     }
     HIP_TRY(hipGraphLaunch(P.graph, s));
   } else {
-    lexp_status st = part_device_work(c, P, B, d_pairs, d_tiles, s);
+    lexp_status st = part_device_work(c, P, B, d_pairs, d_tiles, tuner, s);
     if (st) return st;
   }
   HIP_TRY(hipEventRecord(B.ready, s));
@@ -1175,13 +1264,19 @@ lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairD
 // that step: a candidate reads labels of the region's own centre cell only,
 // which no other region of the group changes (Lemma 3).
 lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepArgs& a, int next_step,
-                        const PairDev* d_pairs, hipStream_t s) {
+                        const PairDev* d_pairs, CutTuner* tuner, hipStream_t s) {
   const int n = (int)P.items.size();
   const bool dev = P.device_cut;
   lexp::ThreadPool& pool = pool_of(c);
   const auto t0 = std::chrono::steady_clock::now();
   HIP_TRY(hipEventSynchronize(B.ready));
   const auto t1 = std::chrono::steady_clock::now();
+  if (B.cut_timed && tuner) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, B.cut0, B.cut1));
+    tuner->report(B.cut_block, B.cut_every, ms);
+    B.cut_timed = false;
+  }
   const int flag = dev ? reinterpret_cast<const int*>(B.h_res.p)[0] : B.h_terms.p[0];
   if (flag) return fail(LEXP_EINVAL, "binary-problem term exceeds 2^30 quanta (parameters too large)");
   const int nf = c->dp.nf;
@@ -1441,6 +1536,7 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     }
   } graph_guard{parts};
   std::vector<CutBalance> balance((size_t)sch->n_levels);
+  std::vector<CutTuner> tuners((size_t)sch->n_levels);
   size_t n_tiles = 0;
   int64_t max_px = 1;
   size_t max_items = 1;
@@ -1492,6 +1588,9 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     HIP_TRY(B.h_x.ensure((size_t)max_px));
     HIP_TRY(B.h_res.ensure(4 + 4 * max_items + (size_t)max_px));
     if (!B.ready) HIP_TRY(hipEventCreateWithFlags(&B.ready, hipEventDisableTiming));
+    if (!B.cut0) HIP_TRY(hipEventCreate(&B.cut0));
+    if (!B.cut1) HIP_TRY(hipEventCreate(&B.cut1));
+    B.cut_timed = false;
     HIP_TRY(hipMemsetAsync(B.d_terms.p, 0, sizeof(int), s));  // overflow flags
     HIP_TRY(hipMemsetAsync(B.d_res.p, 0, sizeof(int), s));
   }
@@ -1536,15 +1635,15 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
           if (!P[hp]->items.empty() && K > 0) {
             Part& Q = *P[hp];
             pool_of(c).parallel_for((int)Q.items.size(), [&](int q, int) { propose_item(Q, a, q, 0); });
-            if ((st = enqueue_part(c, Q, c->part[hp], d_pairs, c->d_tiles.p, use_graph, s))) return st;
+            if ((st = enqueue_part(c, Q, c->part[hp], d_pairs, c->d_tiles.p, use_graph, &tuners[h], s))) return st;
           }
         for (int step = 0; step < K; ++step)
           for (int hp = 0; hp < 2; ++hp) {
             if (P[hp]->items.empty()) continue;
             const int next = step + 1 < K ? step + 1 : -1;
-            if ((st = finish_part(c, *P[hp], c->part[hp], a, next, d_pairs, s))) return st;
+            if ((st = finish_part(c, *P[hp], c->part[hp], a, next, d_pairs, &tuners[h], s))) return st;
             if (next >= 0)
-              if ((st = enqueue_part(c, *P[hp], c->part[hp], d_pairs, c->d_tiles.p, use_graph, s))) return st;
+              if ((st = enqueue_part(c, *P[hp], c->part[hp], d_pairs, c->d_tiles.p, use_graph, &tuners[h], s))) return st;
           }
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - g0).count();
         balance[h].update(ms / (double)std::max<int64_t>(1, groups[(size_t)h * 16 + k].n_px));
@@ -1565,7 +1664,12 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
   }
   HIP_TRY(hipStreamSynchronize(s));
   for (Part& P : parts) drop_graph(P);
-  for (int h = 0; h < 4; ++h) c->stats.device_cut_share[h] = dev_cut && h < sch->n_levels ? balance[h].share : 0.0;
+  for (int h = 0; h < 4; ++h) {
+    c->stats.device_cut_share[h] = dev_cut && h < sch->n_levels ? balance[h].share : 0.0;
+    const bool tuned = h < sch->n_levels && tuners[h].done;
+    c->stats.device_cut_block[h] = tuned ? tuners[h].best.block : 0;
+    c->stats.device_cut_relabel[h] = tuned ? tuners[h].best.every : 0;
+  }
   for (int p = 0; p < np; ++p) HIP_TRY(hipEventRecord(pairs[p].c->staging_done, s));
   if (c->timing) collect_timing(c);
   return LEXP_OK;

@@ -309,7 +309,9 @@ __global__ __launch_bounds__(BLOCK) void k_cut_lds(const Item* __restrict__ item
                             relabel_every, any_flags, &overflow);
 }
 
+template __global__ void k_cut_lds<FullLayout, 128>(const Item*, const int*, int, uint8_t*, int*, int, int, int);
 template __global__ void k_cut_lds<FullLayout, 256>(const Item*, const int*, int, uint8_t*, int*, int, int, int);
+template __global__ void k_cut_lds<FullLayout, 512>(const Item*, const int*, int, uint8_t*, int*, int, int, int);
 template __global__ void k_cut_lds<FullLayout, 1024>(const Item*, const int*, int, uint8_t*, int*, int, int, int);
 template __global__ void k_cut_lds<CompactLayout, 1024>(const Item*, const int*, int, uint8_t*, int*, int, int,
                                                         int);

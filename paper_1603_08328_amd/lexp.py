@@ -55,12 +55,15 @@ class lexp_stats(C.Structure):
                 ("expand_calls", C.c_int64), ("host_cut_ms", C.c_double), ("host_wait_ms", C.c_double),
                 ("host_enqueue_ms", C.c_double), ("host_update_ms", C.c_double),
                 ("host_cut_level_ms", C.c_double * 4), ("device_cut_fallbacks", C.c_int64),
-                ("device_cut_share", C.c_double * 4), ("graphs_captured", C.c_int64)]
+                ("device_cut_share", C.c_double * 4), ("graphs_captured", C.c_int64),
+                ("device_cut_block", C.c_int32 * 4), ("device_cut_relabel", C.c_int32 * 4)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["host_cut_level_ms"] = list(d["host_cut_level_ms"])
         d["device_cut_share"] = list(d["device_cut_share"])
+        d["device_cut_block"] = list(d["device_cut_block"])
+        d["device_cut_relabel"] = list(d["device_cut_relabel"])
         return d
 
 
