@@ -61,15 +61,15 @@ def _traffic_from_profile():
         return None
 
 
-def run_gpu(steps: int, warmup: int, seed: int = 0, k_rans: int = 0):
+def run_gpu(steps: int, warmup: int, seed: int = 0, k_rans: int = 0, name: str = WORKLOAD):
     import torch
 
     import paper_1603_08328_amd.lexp as L
     from synth import make_workload_pair, params_for, workload
 
-    wl = workload(WORKLOAD)
-    prm = params_for(WORKLOAD)
-    pair = make_workload_pair(WORKLOAD)
+    wl = workload(name)
+    prm = params_for(name)
+    pair = make_workload_pair(name)
     dev = torch.device("cuda:0")
     left = torch.from_numpy(pair.left).to(dev)
     right = torch.from_numpy(pair.right).to(dev)
@@ -104,7 +104,7 @@ def run_gpu(steps: int, warmup: int, seed: int = 0, k_rans: int = 0):
                 final_energy=e_final, stats=results[-1][2], final_labels=labels.cpu().numpy())
 
 
-def run_many_pairs(n_pairs: int, iterations: int, seed: int = 0):
+def run_many_pairs(n_pairs: int, iterations: int, seed: int = 0, loop: bool = True):
     """The uneven-size many-pair workload (width ~ U[320,1500], height 0.67 w
     rounded to 8, disparity range 0.13 w, scenes as the 450x375 one, r = 20,
     cells 5/15/25): the plain method run pair by pair (lexp_optimize in a loop)
@@ -141,13 +141,13 @@ def run_many_pairs(n_pairs: int, iterations: int, seed: int = 0):
         L.lexp_reset_stats(c)
     t0 = time.perf_counter()
     loop_e = []
-    for c, sd, lab, cost in zip(ctxs, seeds, lab_a, cost_a):
-        e, _ = L.lexp_optimize(c, grids, iterations, sd, lab, cost, stream)
-        loop_e.append(e)
+    if loop:
+        for c, sd, lab, cost in zip(ctxs, seeds, lab_a, cost_a):
+            e, _ = L.lexp_optimize(c, grids, iterations, sd, lab, cost, stream)
+            loop_e.append(e)
     torch.cuda.synchronize()
     t_loop = time.perf_counter() - t0
     loop_stats = [L.lexp_get_stats(c) for c in ctxs]
-    evals = sum(s["unary_evals"] for s in loop_stats) + px
     loop_kernel_ms = sum(s["unary_kernel_ms"] for s in loop_stats)
 
     lab_b, cost_b = buffers()
@@ -158,13 +158,15 @@ def run_many_pairs(n_pairs: int, iterations: int, seed: int = 0):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     bst = L.lexp_get_stats(ctxs[0])
-    same = all(torch.equal(a, b) for a, b in zip(lab_a, lab_b)) and \
-        all(np.array_equal(a, b) for a, b in zip(loop_e, batch_e))
+    evals = bst["unary_evals"] + px
+    same = (all(torch.equal(a, b) for a, b in zip(lab_a, lab_b)) and
+            all(np.array_equal(a, b) for a, b in zip(loop_e, batch_e))) if loop else None
     for c in ctxs:
         c.close()
     return dict(n_pairs=n_pairs, megapixels=px / 1e6, iterations=iterations, evals=evals,
-                loop_s=t_loop, batch_s=t_batch, loop_value=evals / t_loop / 1e9, batch_value=evals / t_batch / 1e9,
-                identical=bool(same), energy_total_trace=[round(float(x), 3) for x in np.sum(batch_e, axis=0)],
+                loop_s=t_loop if loop else None, batch_s=t_batch,
+                loop_value=evals / t_loop / 1e9 if loop else None, batch_value=evals / t_batch / 1e9,
+                identical=same, energy_total_trace=[round(float(x), 3) for x in np.sum(batch_e, axis=0)],
                 batch_time_trace=[round(float(x), 3) for x in batch_t],
                 loop_kernel_ms=loop_kernel_ms, batch_kernel_ms=bst["unary_kernel_ms"],
                 batch_launches=bst["unary_launches"], batch_host_cut_ms=bst["host_cut_ms"],
@@ -371,6 +373,9 @@ def main():
                     help="instead: the uneven-size many-pair workload with this many pairs, pair by pair and "
                          "batched (one JSON line with both)")
     ap.add_argument("--iterations", type=int, default=10, help="iterations of the many-pair runs")
+    ap.add_argument("--no-loop", action="store_true", help="many-pair runs: batched only (no pair-by-pair loop)")
+    ap.add_argument("--workload", default=WORKLOAD, choices=["lowres-450x375", "highres-1500x1000"],
+                    help="single-pair workload of the default line (the metric is quoted on 450x375)")
     ap.add_argument("--both-views", action="store_true",
                     help="instead: both views batched, then the post-processing (times and ground-truth errors)")
     ap.add_argument("--learned", action="store_true",
@@ -400,7 +405,7 @@ def main():
                           "both_views": run_both_views()}), flush=True)
         return
     if args.many_pairs:
-        m = run_many_pairs(args.many_pairs, args.iterations)
+        m = run_many_pairs(args.many_pairs, args.iterations, loop=not args.no_loop)
         out = {"metric": METRIC, "value": m["batch_value"], "unit": "Gpix*labels/s", "n_gpus": 1, "steps": 1,
                "warmup": 0, "ms_per_step": m["batch_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
                "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -418,13 +423,13 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-    g = run_gpu(args.steps, args.warmup, k_rans=args.k_rans)
+    g = run_gpu(args.steps, args.warmup, k_rans=args.k_rans, name=args.workload)
     ms = g["elapsed"] / args.steps * 1e3
     value = g["evals"] / g["elapsed"] / 1e9
     achieved = g["kernel_bytes"] / (g["kernel_ms"] / 1e3) / 1e9 if g["kernel_ms"] > 0 else 0.0
-    traffic = _traffic_from_profile()
+    traffic = _traffic_from_profile() if args.workload == WORKLOAD else None
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == WORKLOAD:
         c = run_cpu_baseline()
         cpu = {"value": c["value"], "unit": "Gpix*labels/s", "cores": c["cores"], "kind": "oracle",
                "sample": c["sample"], "sample_seconds": round(c["sample_s"], 2)}
@@ -441,9 +446,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "450x375 synthetic pair, 12 planar + 2 quadric segments, 2% holes, "
-                               "disparity [0,60], guided-filter radius 20, cells 5/15/25, 10 iterations, "
-                               "{K_prop,K_rand}={1,7}" + (f", K_RANS={args.k_rans}" if args.k_rans else ""),
+        "config": {"workload": ("450x375 synthetic pair, 12 planar + 2 quadric segments, 2% holes, disparity [0,60]"
+                                if args.workload == WORKLOAD else
+                                "1500x1000 synthetic pair, 40 planar + 6 quadric segments, 2% holes, disparity [0,200]")
+                               + ", guided-filter radius 20, cells 5/15/25, 10 iterations, {K_prop,K_rand}={1,7}"
+                               + (f", K_RANS={args.k_rans}" if args.k_rans else ""),
                    "evals_per_step": g["evals"] // args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
