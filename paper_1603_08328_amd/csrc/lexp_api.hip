@@ -1779,10 +1779,10 @@ lexp_status lexp_net_get_weights(lexp_net* net, float* weights, float* biases) {
   return LEXP_OK;
 }
 
-lexp_status lexp_net_create(int32_t max_width, int32_t max_height, uint64_t seed, lexp_net** out) {
-  if (!out || max_width <= 0 || max_height <= 0 || (int64_t)max_width * max_height > (1ll << 26))
-    return fail(LEXP_EINVAL, "bad argument");
-  std::unique_ptr<lexp_net> net(new lexp_net());
+namespace {
+
+// Allocates a network's buffers and sets its initial weights.
+lexp_status net_init(lexp_net* net, int32_t max_width, int32_t max_height, uint64_t seed) {
   net->max_w = max_width;
   net->max_h = max_height;
   size_t off = 0, off16 = 0;
@@ -1827,9 +1827,21 @@ lexp_status lexp_net_create(int32_t max_width, int32_t max_height, uint64_t seed
     }
     for (int e = 0; e < co; ++e) b.push_back(0.f);
   }
-  lexp_status st = lexp_net_set_weights(net.get(), w.data(), b.data());
-  if (st) return st;
-  *out = net.release();
+  return lexp_net_set_weights(net, w.data(), b.data());
+}
+
+}  // namespace
+
+lexp_status lexp_net_create(int32_t max_width, int32_t max_height, uint64_t seed, lexp_net** out) {
+  if (!out || max_width <= 0 || max_height <= 0 || (int64_t)max_width * max_height > (1ll << 26))
+    return fail(LEXP_EINVAL, "bad argument");
+  lexp_net* net = new lexp_net();
+  const lexp_status st = net_init(net, max_width, max_height, seed);
+  if (st) {
+    (void)lexp_net_destroy(net);  // frees whatever was allocated (keeps the error message)
+    return st;
+  }
+  *out = net;
   return LEXP_OK;
 }
 
