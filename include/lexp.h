@@ -114,9 +114,11 @@ typedef struct {
   int32_t k_rand[4];
   int32_t iterations;
   int32_t k_rans[4];
-  int32_t learned; /* 1: refinement steps with an odd index take the plane of the
-                      learned network (lexp_set_net) at the chosen pixel, computed
-                      from the labels at the start of each level pass; 0: none */
+  int32_t learned; /* 1: from the second iteration on, refinement steps with an odd
+                      index take the plane of the learned network (lexp_set_net) at
+                      the chosen pixel, computed from the labels at the start of each
+                      level pass (the first iteration starts from random labels,
+                      unlike anything the network is trained on); 0: none */
 } lexp_schedule;
 
 /* Counters of the hot kernel, accumulated while timing is enabled. */

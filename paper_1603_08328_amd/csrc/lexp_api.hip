@@ -1613,7 +1613,9 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     for (int h = 0; h < sch->n_levels; ++h) {
       const int K = sch->k_prop[h] + sch->k_rans[h] + sch->k_rand[h];
       const StepArgs a{it, h, sch->cell[h], sch->k_prop[h], sch->k_rans[h], scale, pairs};
-      if (sch->learned) {
+      if (sch->learned && it == 0) {
+        for (int p = 0; p < np; ++p) pairs[p].net_planes.clear();  // random labels: nothing to learn from yet
+      } else if (sch->learned) {
         // the network's planes from the labels at the start of the level pass
         for (int p = 0; p < np; ++p) {
           RunPair& rp = pairs[p];
