@@ -7,14 +7,14 @@
 // offset (kx-1, ky-1)) with a BF16 copy in that order and one in
 // [tap][in][out] for the backward-data products.
 //
-// One wave computes one 16 x 16 block of a product per matrix instruction.
+// One matrix instruction computes one 16 x 16 block of a product.
 // Operand fragments (checked on the device): lane l holds A[l % 16][4 (l/16)
 // + i] and B[4 (l/16) + i][l % 16] for i < 4, and receives
 // D[4 (l/16) + i][l % 16].
 //   forward     : M = 16 pixels of a row, N = output channels, K = 9 taps x
-//                 input channels;
+//                 input channels (a wave takes four such blocks of a row);
 //   backward x  : M = 16 pixels, N = input channels, K = 9 taps x output
-//                 channels (gradient at p - offset);
+//                 channels (gradient at p - offset; four blocks per wave);
 //   backward w  : per tap, M = output channels, N = input channels, K = the
 //                 pixels of a chunk; chunk partial sums are added in chunk
 //                 order by a second kernel (the result does not depend on
@@ -83,34 +83,47 @@ __global__ void k_net_input(const float4* __restrict__ left4, const float4* __re
   for (int c = 0; c < 16; ++c) x0[(size_t)p * 16 + c] = to_bf16(ch[c]);
 }
 
-// Forward convolution of one layer: each wave computes 16 pixels of a row
-// (all output channels); bias, then ReLU and BF16 (hidden layers) or FP32
+// Pixels per wave in the forward and input-gradient convolutions: kSegs
+// segments of 16 consecutive pixels of one row, each weight fragment loaded
+// once and used for all of them.
+constexpr int kSegs = 4;
+
+// Forward convolution of one layer: each wave computes kSegs x 16 pixels of a
+// row (all output channels); bias, then ReLU and BF16 (hidden layers) or FP32
 // output (last layer).
 template <int CI, int CO, bool LAST>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w16,
                                                   const float* __restrict__ bias, int W, int H,
                                                   uint16_t* __restrict__ xo, float* __restrict__ yo) {
   const int lane = threadIdx.x & 63;
-  const int segs = (W + 15) / 16;
-  const int seg = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (seg >= segs * H) return;
-  const int v = seg / segs, u0 = (seg % segs) * 16;
+  const int runs = (W + 16 * kSegs - 1) / (16 * kSegs);
+  const int run = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (run >= runs * H) return;
+  const int v = run / runs, u0 = (run % runs) * 16 * kSegs;
   const int m = lane & 15, kq = (lane >> 4) * 4;
-  f32x4 acc[CO / 16];
+  f32x4 acc[kSegs][CO / 16];
 #pragma unroll
-  for (int nb = 0; nb < CO / 16; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int sg = 0; sg < kSegs; ++sg)
+#pragma unroll
+    for (int nb = 0; nb < CO / 16; ++nb) acc[sg][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
-    const int yy = v + tap / 3 - 1, xx = u0 + m + tap % 3 - 1;
-    const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
-    const uint16_t* xp = x + ((size_t)(in ? yy : 0) * W + (in ? xx : 0)) * CI;
+    const int yy = v + tap / 3 - 1;
+    const bool row_in = yy >= 0 && yy < H;
 #pragma unroll
     for (int cb = 0; cb < CI / 16; ++cb) {
-      const bf16x4 a = in ? load4(xp + cb * 16 + kq) : zero4();
+      bf16x4 b[CO / 16];
 #pragma unroll
-      for (int nb = 0; nb < CO / 16; ++nb) {
-        const bf16x4 b = load4(w16 + ((size_t)tap * CO + nb * 16 + m) * CI + cb * 16 + kq);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nb], 0, 0, 0);
+      for (int nb = 0; nb < CO / 16; ++nb) b[nb] = load4(w16 + ((size_t)tap * CO + nb * 16 + m) * CI + cb * 16 + kq);
+#pragma unroll
+      for (int sg = 0; sg < kSegs; ++sg) {
+        const int xx = u0 + sg * 16 + m + tap % 3 - 1;
+        const bool in = row_in && xx >= 0 && xx < W;
+        const size_t q = in ? (size_t)yy * W + xx : 0;  // an address inside the image either way
+        const bf16x4 a = in ? load4(x + q * CI + cb * 16 + kq) : zero4();
+#pragma unroll
+        for (int nb = 0; nb < CO / 16; ++nb)
+          acc[sg][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[nb], acc[sg][nb], 0, 0, 0);
       }
     }
   }
@@ -119,47 +132,57 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
     const int co = nb * 16 + m;
     const float bb = bias[co];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int u = u0 + kq + i;
-      if (u >= W) continue;
-      const size_t p = (size_t)v * W + u;
-      const float z = acc[nb][i] + bb;
-      if (LAST)
-        yo[p * CO + co] = z;
-      else
-        xo[p * CO + co] = to_bf16(z > 0.f ? z : 0.f);
-    }
+    for (int sg = 0; sg < kSegs; ++sg)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int u = u0 + sg * 16 + kq + i;
+        if (u >= W) continue;
+        const size_t p = (size_t)v * W + u;
+        const float z = acc[sg][nb][i] + bb;
+        if (LAST)
+          yo[p * CO + co] = z;
+        else
+          xo[p * CO + co] = to_bf16(z > 0.f ? z : 0.f);
+      }
   }
 }
 
 // Gradient of a layer's input: dx(p) = sum over taps and output channels of
 // W[tap][o][i] g(p - offset)[o], then gp = BF16(dx * [x(p) > 0]) (the input
-// came from a ReLU).
+// came from a ReLU).  kSegs x 16 pixels of a row per wave.
 template <int CI, int CO>
 __global__ __launch_bounds__(256) void k_conv_bwd_x(const uint16_t* __restrict__ g, const uint16_t* __restrict__ wt16,
                                                     const uint16_t* __restrict__ x, int W, int H,
                                                     uint16_t* __restrict__ gp) {
   const int lane = threadIdx.x & 63;
-  const int segs = (W + 15) / 16;
-  const int seg = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (seg >= segs * H) return;
-  const int v = seg / segs, u0 = (seg % segs) * 16;
+  const int runs = (W + 16 * kSegs - 1) / (16 * kSegs);
+  const int run = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (run >= runs * H) return;
+  const int v = run / runs, u0 = (run % runs) * 16 * kSegs;
   const int m = lane & 15, kq = (lane >> 4) * 4;
-  f32x4 acc[CI / 16];
+  f32x4 acc[kSegs][CI / 16];
 #pragma unroll
-  for (int nb = 0; nb < CI / 16; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int sg = 0; sg < kSegs; ++sg)
+#pragma unroll
+    for (int nb = 0; nb < CI / 16; ++nb) acc[sg][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
-    const int yy = v - (tap / 3 - 1), xx = u0 + m - (tap % 3 - 1);
-    const bool in = yy >= 0 && yy < H && xx >= 0 && xx < W;
-    const uint16_t* gq = g + ((size_t)(in ? yy : 0) * W + (in ? xx : 0)) * CO;
+    const int yy = v - (tap / 3 - 1);
+    const bool row_in = yy >= 0 && yy < H;
 #pragma unroll
     for (int cb = 0; cb < CO / 16; ++cb) {
-      const bf16x4 a = in ? load4(gq + cb * 16 + kq) : zero4();
+      bf16x4 b[CI / 16];
 #pragma unroll
-      for (int nb = 0; nb < CI / 16; ++nb) {
-        const bf16x4 b = load4(wt16 + ((size_t)tap * CI + nb * 16 + m) * CO + cb * 16 + kq);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nb], 0, 0, 0);
+      for (int nb = 0; nb < CI / 16; ++nb) b[nb] = load4(wt16 + ((size_t)tap * CI + nb * 16 + m) * CO + cb * 16 + kq);
+#pragma unroll
+      for (int sg = 0; sg < kSegs; ++sg) {
+        const int xx = u0 + sg * 16 + m - (tap % 3 - 1);
+        const bool in = row_in && xx >= 0 && xx < W;
+        const size_t q = in ? (size_t)yy * W + xx : 0;  // an address inside the image either way
+        const bf16x4 a = in ? load4(g + q * CO + cb * 16 + kq) : zero4();
+#pragma unroll
+        for (int nb = 0; nb < CI / 16; ++nb)
+          acc[sg][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[nb], acc[sg][nb], 0, 0, 0);
       }
     }
   }
@@ -167,14 +190,16 @@ __global__ __launch_bounds__(256) void k_conv_bwd_x(const uint16_t* __restrict__
   for (int nb = 0; nb < CI / 16; ++nb) {
     const int ci = nb * 16 + m;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int u = u0 + kq + i;
-      if (u >= W) continue;
-      const size_t p = (size_t)v * W + u;
-      const uint16_t xv = x[p * CI + ci];
-      const bool pos = (xv & 0x8000u) == 0 && xv != 0;
-      gp[p * CI + ci] = to_bf16(pos ? acc[nb][i] : 0.f);
-    }
+    for (int sg = 0; sg < kSegs; ++sg)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int u = u0 + sg * 16 + kq + i;
+        if (u >= W) continue;
+        const size_t p = (size_t)v * W + u;
+        const uint16_t xv = x[p * CI + ci];
+        const bool pos = (xv & 0x8000u) == 0 && xv != 0;
+        gp[p * CI + ci] = to_bf16(pos ? acc[sg][nb][i] : 0.f);
+      }
   }
 }
 
