@@ -276,8 +276,10 @@ lexp_status lexp_postprocess(lexp_ctx* left, const float* labels_left, lexp_ctx*
 /* ---- learned proposal network ---------------------------------------------
  * Five 3x3 convolutions (zero padding), ReLU after the first four, channels
  * 16 -> 32 -> 32 -> 32 -> 32 -> 16, on the BF16 matrix cores with FP32 sums.
- * Input per pixel: left and right RGB / 255 of the context's packed images,
- * then a, b, d / disp_max of the label (d = a u + b v + c), then zeros.
+ * Input per pixel: left RGB / 255 of the context's packed images, right
+ * RGB / 255 at the pixel's match u - d (linear interpolation, zero outside),
+ * a, b, d / disp_max of the label (d = a u + b v + c), 1 where the match is
+ * inside the right image, then zeros.
  * Output channels 0..2: (a, b, d / disp_max) of a proposed plane.  Training
  * loss: mean over pixels of the mean over the 5x5 neighbourhood q of
  * |d_p + a_p (u_q - u_p) + b_p (v_q - v_p) - d*_q| (d* from the target

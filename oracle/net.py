@@ -7,9 +7,10 @@ The network proposes a plane label per pixel from the two images and the
 current label field: five 3x3 convolutions (zero padding), ReLU after the
 first four, 32 channels inside.  Readings (the paper's method admits any
 proposer of alpha_ij; this one is not in the paper):
-  * input, 16 channels per pixel: left RGB / 255, right RGB / 255 (the
-    context's own frame), a, b, d / disp_max with d = a u + b v + c, then
-    seven zeros;
+  * input, 16 channels per pixel: left RGB / 255; right RGB / 255 at the
+    pixel's match x = u - d (linear interpolation, zero outside the right
+    image); a, b, d / disp_max with d = a u + b v + c; 1 where the match is
+    inside the right image; then six zeros (the context's own frame);
   * output, 16 channels of which the first three are used: (a, b, d / disp_max)
     of a plane; the candidate of a pixel is that plane, c = d - a u - b v;
   * layer channels 16 -> 32 -> 32 -> 32 -> 32 -> 16; weights indexed
@@ -53,12 +54,22 @@ def net_input(left: np.ndarray, right: np.ndarray, labels: np.ndarray, disp_max:
     u = np.arange(w)[None, :]
     v = np.arange(h)[:, None]
     d = lab[..., 0] * u + lab[..., 1] * v + lab[..., 2]
+    xm = u - d
+    inside = (xm >= 0) & (xm <= w - 1)
+    i0 = np.where(inside, np.floor(np.where(inside, xm, 0)), 0).astype(np.int64)
+    i1 = np.minimum(i0 + 1, w - 1)
+    t = np.where(inside, xm - i0, 0.0)
+    rows = np.broadcast_to(v, (h, w))
+    r = right.astype(np.float64)
+    warped = (1 - t)[..., None] * r[rows, i0] + t[..., None] * r[rows, i1]
+    warped[~inside] = 0.0
     x = np.zeros((16, h, w))
     x[0:3] = np.moveaxis(left.astype(np.float64) / 255.0, -1, 0)
-    x[3:6] = np.moveaxis(right.astype(np.float64) / 255.0, -1, 0)
+    x[3:6] = np.moveaxis(warped / 255.0, -1, 0)
     x[6] = lab[..., 0]
     x[7] = lab[..., 1]
     x[8] = d / disp_max
+    x[9] = inside
     return torch.from_numpy(x)[None]
 
 

@@ -58,28 +58,43 @@ __device__ inline bf16x4 zero4() {
 
 }  // namespace
 
-// Network input, 16 BF16 channels per pixel: RGB/255 of the context's two
-// packed images, then a, b, d/disp_max of the label (d = a u + b v + c in
-// FP64), then zeros.
+// Network input, 16 BF16 channels per pixel: RGB/255 of the context's left
+// image, RGB/255 of its right image at the pixel's match x = u - d (linear
+// interpolation in FP64; zero outside the image), a, b, d/disp_max of the
+// label (d = a u + b v + c in FP64), 1 where the match lies inside the right
+// image, then zeros.
 __global__ void k_net_input(const float4* __restrict__ left4, const float4* __restrict__ right4,
                             const float4* __restrict__ labels, int W, int H, double disp_max,
                             uint16_t* __restrict__ x0) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= W * H) return;
   const int u = p % W, v = p / W;
-  const float4 L = left4[p], R = right4[p], f = labels[p];
+  const float4 L = left4[p], f = labels[p];
   const double d = ((double)f.x * (double)u + (double)f.y * (double)v) + (double)f.z;
+  const double x = (double)u - d;
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0, inside = 0.0;
+  if (x >= 0.0 && x <= (double)(W - 1)) {
+    const int i0 = (int)floor(x);
+    const int i1 = i0 + 1 < W ? i0 + 1 : W - 1;
+    const double t = x - (double)i0;
+    const float4 a = right4[(size_t)v * W + i0], b = right4[(size_t)v * W + i1];
+    r0 = (1.0 - t) * (double)a.x + t * (double)b.x;
+    r1 = (1.0 - t) * (double)a.y + t * (double)b.y;
+    r2 = (1.0 - t) * (double)a.z + t * (double)b.z;
+    inside = 1.0;
+  }
   float ch[16];
   ch[0] = (float)((double)L.x / 255.0);
   ch[1] = (float)((double)L.y / 255.0);
   ch[2] = (float)((double)L.z / 255.0);
-  ch[3] = (float)((double)R.x / 255.0);
-  ch[4] = (float)((double)R.y / 255.0);
-  ch[5] = (float)((double)R.z / 255.0);
+  ch[3] = (float)(r0 / 255.0);
+  ch[4] = (float)(r1 / 255.0);
+  ch[5] = (float)(r2 / 255.0);
   ch[6] = f.x;
   ch[7] = f.y;
   ch[8] = (float)(d / disp_max);
-  for (int c = 9; c < 16; ++c) ch[c] = 0.f;
+  ch[9] = (float)inside;
+  for (int c = 10; c < 16; ++c) ch[c] = 0.f;
   for (int c = 0; c < 16; ++c) x0[(size_t)p * 16 + c] = to_bf16(ch[c]);
 }
 
