@@ -150,7 +150,8 @@ typedef struct {
  * I = I_L/255 and (Sigma_k + eU)^-1 over W'_k, computed in FP64, stored FP32)
  * and the contrast weights w_pq of Eq. (11) for the forward neighbours (FP64).
  * left_hwc / right_hwc: device, HxWx3 float32; they may be freed after return
- * (the call synchronises hip_stream).  The context owns its device scratch. */
+ * (the call synchronises hip_stream).  The context owns its device scratch.
+ * Images of at most 2^27 - 1 pixels (LEXP_EINVAL otherwise). */
 lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const float* right_hwc,
                         void* hip_stream, lexp_ctx** out);
 

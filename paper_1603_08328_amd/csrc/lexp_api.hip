@@ -323,13 +323,22 @@ void collect_timing(lexp_ctx* c) {
   c->ev_pending.clear();
 }
 
+// 1 when tile i is the only tile of item i for every item (the fused kernel
+// then loads a tile's item without waiting for the tile).
+int tiles_direct(const Tile* tiles, size_t n_tiles, size_t n_items) {
+  if (n_tiles != n_items) return 0;
+  for (size_t i = 0; i < n_tiles; ++i)
+    if (tiles[i].item != (int)i) return 0;
+  return 1;
+}
+
 // Fused cost kernel over n_tiles tiles of the items (pairs: the table the
 // items' pair indices refer to; MODE 2 covers every pixel of pairs[0]).
 template <int MODE>
 lexp_status launch_unary(lexp_ctx* c, const PairDev* d_pairs, const Item* d_items, const Tile* d_tiles, int n_tiles,
                          const TileCaps& caps,
                          const float4* label_field, float* out, hipStream_t s, double alg_bytes, int64_t evals,
-                         int64_t n_items) {
+                         int64_t n_items, int pair_hint = -1, int direct = 0) {
   if (n_tiles <= 0) return LEXP_OK;
   const int ring = lexp::unary_ring_rows(c->r);
   const size_t lds = lexp::unary_lds_bytes(ring, caps.wp, caps.tw, caps.ws);
@@ -349,7 +358,7 @@ lexp_status launch_unary(lexp_ctx* c, const PairDev* d_pairs, const Item* d_item
   const int nseg = (caps.ws + 31) / 32, nc = (std::max(caps.wp, caps.tw) + 31) / 32;
 #define LEXP_LAUNCH(M, S, C)                                                                                       \
   hipLaunchKernelGGL((lexp::k_unary<M, S, C>), dim3(grid), dim3(lexp::kWaves * 64), lds, s, d_pairs, d_items,      \
-                     d_tiles, n_tiles, label_field, out, ring, caps.wp, caps.tw, caps.ws)
+                     d_tiles, n_tiles, label_field, out, ring, caps.wp, caps.tw, caps.ws, pair_hint, direct)
 #define LEXP_LAUNCH_C(M, S)  \
   if (nc <= 1) {             \
     LEXP_LAUNCH(M, S, 1);    \
@@ -711,8 +720,9 @@ lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const 
                         lexp_ctx** out) {
   if (!params || !left_hwc || !right_hwc || !out) return fail(LEXP_EINVAL, "null argument");
   const lexp_params& p = *params;
-  if (p.width <= 0 || p.height <= 0 || (int64_t)p.width * p.height > (1ll << 30))
-    return fail(LEXP_EINVAL, "bad image size %dx%d", p.width, p.height);
+  // the fused kernel addresses the packed images with 32-bit byte offsets
+  if (p.width <= 0 || p.height <= 0 || (int64_t)p.width * p.height >= (1ll << 27))
+    return fail(LEXP_EINVAL, "bad image size %dx%d (at most 2^27 - 1 pixels)", p.width, p.height);
   if (p.gf_radius < 1 || p.gf_radius > 32) return fail(LEXP_EINVAL, "gf_radius %d outside [1, 32]", p.gf_radius);
   if (p.neighbours != 4 && p.neighbours != 8) return fail(LEXP_EINVAL, "neighbours must be 4 or 8");
   if (!(p.gf_eps > 0.0) || !(p.gamma > 0.0) || !(p.lambda >= 0.0) || !(p.tau_dis >= 0.0) || !(p.w_floor >= 0.0) ||
@@ -754,7 +764,10 @@ lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const 
   const size_t n = (size_t)c->W * c->H;
   HIP_TRY(hipMalloc((void**)&c->left4, n * sizeof(float4)));
   HIP_TRY(hipMalloc((void**)&c->left4T, n * sizeof(float4)));
-  HIP_TRY(hipMalloc((void**)&c->right4, n * sizeof(float4)));
+  // one zeroed pixel after the right image: the fused kernel's second
+  // interpolation tap may read it (with weight zero)
+  HIP_TRY(hipMalloc((void**)&c->right4, (n + 1) * sizeof(float4)));
+  HIP_TRY(hipMemsetAsync(c->right4 + n, 0, sizeof(float4), s));
   HIP_TRY(hipMalloc((void**)&c->guide, n * 9 * sizeof(float)));
   HIP_TRY(hipMalloc((void**)&c->wts, n * 4 * sizeof(double)));
   double* tmp = nullptr;
@@ -844,7 +857,7 @@ lexp_status lexp_unary_cost(lexp_ctx* c, int32_t n, const lexp_rect* rects, cons
     evals += (int64_t)c->h_items.p[i].rw * c->h_items.p[i].rh;
   }
   st = launch_unary<0>(c, c->d_pair.p, c->d_items.p, c->d_tiles.p, (int)tiles.size(), caps, nullptr, out_cost, s,
-                       bytes, evals, n);
+                       bytes, evals, n, 0, tiles_direct(tiles.data(), tiles.size(), (size_t)n));
   if (st) return st;
   HIP_TRY(hipEventRecord(c->staging_done, s));
   return LEXP_OK;
@@ -870,7 +883,7 @@ lexp_status lexp_guided_coeffs(lexp_ctx* c, int32_t n, const lexp_rect* rects, c
   if (!tiles.empty())
     HIP_TRY(hipMemcpyAsync(c->d_tiles.p, c->h_tiles.p, sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, s));
   st = launch_unary<1>(c, c->d_pair.p, c->d_items.p, c->d_tiles.p, (int)tiles.size(), caps, nullptr, out_ab, s, 0.0,
-                       0, n);
+                       0, n, 0, tiles_direct(tiles.data(), tiles.size(), (size_t)n));
   if (st) return st;
   HIP_TRY(hipEventRecord(c->staging_done, s));
   return LEXP_OK;
@@ -1079,6 +1092,8 @@ struct Part {
   TileCaps caps;
   double bytes = 0.0;
   bool device_cut = false;  // minimum cuts by the device max-flow
+  int pair_hint = -1;       // the pair of every item, if they share one
+  int direct = 0;           // tile i is the only tile of item i
   hipGraphExec_t graph = nullptr;  // captured device sequence of one step of this part (graph mode)
 };
 
@@ -1186,7 +1201,7 @@ lexp_status part_device_work(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const P
   const int n = (int)P.items.size();
   HIP_TRY(hipMemcpyAsync(B.d_items.p, B.h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
   lexp_status st = launch_unary<0>(c, d_pairs, B.d_items.p, d_tiles + P.tile_off, (int)P.n_tiles, P.caps, nullptr,
-                                   B.d_phi.p, s, P.bytes, P.n_px, n);
+                                   B.d_phi.p, s, P.bytes, P.n_px, n, P.pair_hint, P.direct);
   if (st) return st;
   if (P.device_cut) {
     int* flag = reinterpret_cast<int*>(B.d_res.p);
@@ -1491,6 +1506,10 @@ void assign_parts(const RunPair* pairs, const GroupPlan& g, double share, Part* 
       Q.cj.push_back(g.cj[q]);
     }
     Q.n_tiles = t_at - Q.tile_off;
+    Q.direct = tiles_direct(table + Q.tile_off, Q.n_tiles, Q.items.size());
+    Q.pair_hint = Q.items.empty() ? -1 : Q.items[0].pair;
+    for (const Item& it : Q.items)
+      if (it.pair != Q.pair_hint) Q.pair_hint = -1;
   }
   P[0].device_cut = share >= 0 && !P[0].items.empty();
 }

@@ -60,15 +60,16 @@ struct Tile {
 // plus the rows one stage may run ahead of the next (two pipeline steps).
 inline int unary_ring_rows(int r) { return 2 * r + 1 + 2 * kChunk; }
 
-// LDS of one fused-cost workgroup: rings (R+ and R widths), two buffers of
-// coefficient rows, one scan row per wave and the vertical-sum carries
-// (float4 each); FP32 counts of the scan rows and carries; byte counts of the
-// ring and coefficient entries.
+// LDS of one fused-cost workgroup: rings (R+ and R widths, each with one more
+// row that stays zero), two buffers of coefficient rows, one scan row per wave
+// and the vertical-sum carries (float4 each); FP32 counts of the scan rows and
+// carries; byte counts of the ring and coefficient entries.
 inline size_t unary_lds_bytes(int ring, int wp_cap, int tw_cap, int ws_cap) {
-  const size_t f4 = (size_t)ring * wp_cap + (size_t)2 * kChunk * wp_cap + (size_t)ring * tw_cap +
-                    (size_t)kWaves * ws_cap + (size_t)wp_cap + (size_t)tw_cap;
+  const size_t rows = (size_t)ring + 1;
+  const size_t f4 = rows * wp_cap + (size_t)2 * kChunk * wp_cap + rows * tw_cap + (size_t)kWaves * ws_cap +
+                    (size_t)wp_cap + (size_t)tw_cap;
   const size_t f1 = (size_t)kWaves * ws_cap + (size_t)wp_cap + (size_t)tw_cap;
-  const size_t b1 = (size_t)ring * wp_cap + (size_t)2 * kChunk * wp_cap + (size_t)ring * tw_cap;
+  const size_t b1 = rows * wp_cap + (size_t)2 * kChunk * wp_cap + rows * tw_cap;
   return f4 * 16 + f1 * 4 + b1;
 }
 
@@ -80,7 +81,8 @@ constexpr int kMaxTW = 128;
 
 template <int MODE, int NSEG, int NC>
 __global__ void k_unary(const PairDev* pairs, const Item* items, const Tile* tiles, int n_tiles,
-                        const float4* label_field, float* out, int ring, int wp_cap, int tw_cap, int ws_cap);
+                        const float4* label_field, float* out, int ring, int wp_cap, int tw_cap, int ws_cap,
+                        int pair_hint, int direct);
 __global__ void k_pack(const float* img, float4* out, float4* outT, int W, int H, int mirror);
 __global__ void k_guide_h(const float4* left4, double* tmp, int W, int H, int r);
 __global__ void k_guide_v(const double* tmp, float* guide, int W, int H, int r, double eps);

@@ -140,13 +140,13 @@ __global__ void k_weights(const float* __restrict__ img, double* __restrict__ wt
 //      over the pair's pixels, then an in-place prefix along each row (serial
 //      runs per lane, DPP scan over 32 lanes), then horizontal window sums at
 //      the R+ columns -> ring1
-//   C  (all waves, 4 columns x 16 rows each) vertical window sums (carried
-//      sum of the previous row, plus the row that entered, minus the row that
-//      left) -> means over W'_k
+//   C  (waves 8-15, 4 columns x 16 rows per column group) vertical window
+//      sums (carried sum of the previous row, plus the row that entered,
+//      minus the row that left) -> means over W'_k
 //      -> a_k = (Sigma_k + eU)^-1 (mean(I rho) - mu mean(rho)), b_k
-//   E  (waves 8-15, two coefficient rows each) in-place prefix of the rows,
+//   E  (waves 0-7, two coefficient rows each) in-place prefix of the rows,
 //      window sums at the R columns -> ring3
-//   G  (all waves, as C) vertical window sums -> phi = abar^T I_p + bbar + rho_max
+//   G  (waves 8-15, as C) vertical window sums -> phi = abar^T I_p + bbar + rho_max
 // Global operands of a step (image taps, guide statistics, I_p) are loaded
 // one step ahead with clamped, unconditional loads; barriers wait on LDS
 // traffic only.  A fifth channel counts samples with rho' != 0 exactly (a
@@ -199,6 +199,30 @@ __device__ inline int slot_of(int y, int base_row, int base_slot, int ring) {
 
 // A wave's pair of M rows, flattened: segment s, lane l holds pixel
 // t = 64 s + l of the two rows laid end to end (row t / wM, column t % wM).
+// What depends on the tile only is set once per lane.
+template <int NSEG>
+struct RowLanes {
+  float uf[NSEG];  // column u of the pixel
+  int h[NSEG];     // 1 on the pair's second row
+  int xl16[NSEG];  // byte offset of column min(u, W-1) within an image row
+  int lds[NSEG];   // index of the pixel in the wave's scan rows; -1 past the M columns
+};
+
+template <int NSEG>
+__device__ inline void row_lanes(RowLanes<NSEG>& rl, int w2, int xm0, int wM, int W, int ws_cap, int lane) {
+#pragma unroll
+  for (int s = 0; s < NSEG; ++s) {
+    const int t = s * 64 + lane;
+    const int h = t >= wM ? 1 : 0;
+    const int xi = t - h * wM;
+    const int x = xm0 + xi;
+    rl.uf[s] = (float)x;
+    rl.h[s] = h;
+    rl.xl16[s] = (x < W - 1 ? x : W - 1) * 16;
+    rl.lds[s] = xi < wM ? (w2 + h) * ws_cap + xi : -1;
+  }
+}
+
 template <int NSEG>
 struct RowTaps {  // prefetched operands of the pair, per lane
   float4 L[NSEG], R0[NSEG], R1[NSEG];
@@ -206,37 +230,36 @@ struct RowTaps {  // prefetched operands of the pair, per lane
   bool ok[NSEG];
 };
 
-// Loads of a row pair starting at row y: always issued (row and column
-// indices clamped into the image), so the number of loads in flight is known
-// to the compiler.
+// Loads of a row pair starting at row y: always issued (rows clamped into the
+// image, out-of-view samples read column 0), so the number of loads in flight
+// is known to the compiler.  Addresses are 32-bit byte offsets from the image
+// bases (images below 2^27 pixels).  The second tap is the pixel after the
+// first: where the first is a row's last pixel its weight is exactly zero and
+// the read lands on the next row or on the zeroed pixel after the image.
 template <int NSEG>
-__device__ inline void load_rows2(RowTaps<NSEG>& tp, int y, int xm0, int wM, int W, int H, float la, float lb,
-                                  float lc, int lane, const float4* __restrict__ left4,
-                                  const float4* __restrict__ right4) {
+__device__ inline void load_rows2(RowTaps<NSEG>& tp, const RowLanes<NSEG>& rl, int y, int W, int H, float la,
+                                  float lb, float lc, const char* __restrict__ left_b,
+                                  const char* __restrict__ right_b) {
   const float fW1 = (float)(W - 1);
+  const int W16 = W * 16;
+  // row offsets as scalars (kept from being folded into a per-lane product)
+  const int ro0 = __builtin_amdgcn_readfirstlane((y < H - 1 ? y : H - 1) * W16);
+  const int ro1 = __builtin_amdgcn_readfirstlane((y + 1 < H - 1 ? y + 1 : H - 1) * W16);
+  const float s0 = fmaf(lb, (float)y, lc), s1 = fmaf(lb, (float)(y + 1), lc);
 #pragma unroll
   for (int s = 0; s < NSEG; ++s) {
-    const int t = s * 64 + lane;
-    const int h = t >= wM ? 1 : 0;
-    const int xi = t - h * wM;
-    const int yy = y + h;
-    const int yc = yy < H - 1 ? yy : H - 1;
-    const size_t row = (size_t)yc * W;
-    const float vf = (float)yy;
-    const int x = xm0 + xi;
-    const float uf = (float)x;
-    const float d = fmaf(la, uf, fmaf(lb, vf, lc));
-    const float xs = uf - d;
-    const bool ok = xi < wM && xs >= 0.f && xs <= fW1;
-    const float xf = floorf(ok ? xs : 0.f);
-    int i0 = (int)xf;
-    float tt = (ok ? xs : 0.f) - xf;
-    int i1 = i0 + 1;
-    if (i0 >= W - 1) { i0 = W - 1; i1 = W - 1; tt = 0.f; }
-    tp.R0[s] = right4[row + i0];
-    tp.R1[s] = right4[row + i1];
-    tp.L[s] = left4[row + (x < W - 1 ? x : W - 1)];
-    tp.t[s] = tt;
+    const bool h = rl.h[s] != 0;
+    const int ro = h ? ro1 : ro0;
+    const float d = fmaf(la, rl.uf[s], h ? s1 : s0);
+    const float xs = rl.uf[s] - d;
+    const bool ok = rl.lds[s] >= 0 && xs >= 0.f && xs <= fW1;
+    const float xc = ok ? xs : 0.f;
+    const float xf = floorf(xc);
+    const unsigned a = (unsigned)((int)xf * 16 + ro);
+    tp.R0[s] = *reinterpret_cast<const float4*>(right_b + a);
+    tp.R1[s] = *reinterpret_cast<const float4*>(right_b + a + 16);
+    tp.L[s] = *reinterpret_cast<const float4*>(left_b + (unsigned)(rl.xl16[s] + ro));
+    tp.t[s] = xc - xf;
     tp.ok[s] = ok;
   }
 }
@@ -257,7 +280,8 @@ template <int MODE, int NSEG, int NC>
 __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pairs, const Item* __restrict__ items,
                                                const Tile* __restrict__ tiles, int n_tiles,
                                                const float4* __restrict__ label_field, float* __restrict__ out,
-                                               int ring, int wp_cap, int tw_cap, int ws_cap) {
+                                               int ring, int wp_cap, int tw_cap, int ws_cap, int pair_hint,
+                                               int direct) {
   extern __shared__ float4 smem4[];
   // blocks are dispatched round-robin over the 8 XCDs; give every XCD a
   // contiguous run of tiles so neighbouring tiles share its L2
@@ -265,14 +289,25 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
   const int t_id = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
   if (t_id >= n_tiles) return;
 
-  // MODE 2 covers every pixel of pair 0 (one 1x1 region per tile)
+  // MODE 2 covers every pixel of pair 0 (one 1x1 region per tile).  The
+  // descriptor loads overlap where the launch allows: the pair table entry
+  // with the tile when every tile is of pair pair_hint (>= 0), the item with
+  // the tile when tile t is the only tile of item t (direct != 0).
+  const bool hinted = MODE == 2 || pair_hint >= 0;
+  PairDev pd{};
+  if (hinted) pd = pair_of(pairs, MODE == 2 ? 0 : pair_hint);
   Tile tl{};
   Item it{};
   if (MODE != 2) {
-    tl = tiles[t_id];
-    it = items[tl.item];
+    if (direct) {
+      tl = tiles[t_id];
+      it = items[t_id];
+    } else {
+      tl = tiles[t_id];
+      it = items[tl.item];
+    }
   }
-  const PairDev pd = pair_of(pairs, MODE == 2 ? 0 : it.pair);
+  if (!hinted) pd = pair_of(pairs, it.pair);
   const DevParams P = pd.P;
   const float4* __restrict__ left4 = pd.left4;
   const float4* __restrict__ left4T = pd.left4T;
@@ -310,27 +345,37 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
   const int own_u0 = (flags & kFirstCol) ? xp0 : tu0, own_u1 = (flags & kLastCol) ? xp1 : tu1;
   const int own_v0 = (flags & kFirstRow) ? yp0 : tv0, own_v1 = (flags & kLastRow) ? yp1 : tv1;
 
-  // shared memory: float4 arrays, float arrays, then byte counts
+  // shared memory: float4 arrays, float arrays, then byte counts.  Slot
+  // `ring` of each ring stays zero: the vertical sums read it for rows
+  // outside a window.
   float4* ring1v = smem4;
-  float4* coefv = ring1v + (size_t)ring * wp_cap;
+  float4* coefv = ring1v + (size_t)(ring + 1) * wp_cap;
   float4* ring3v = coefv + (size_t)2 * kChunk * wp_cap;
-  float4* scanv = ring3v + (size_t)ring * tw_cap;
+  float4* scanv = ring3v + (size_t)(ring + 1) * tw_cap;
   float4* car1v = scanv + (size_t)kChunk * ws_cap;
   float4* car2v = car1v + (size_t)wp_cap;
   float* scanc = reinterpret_cast<float*>(car2v + (size_t)tw_cap);
   float* car1c = scanc + (size_t)kChunk * ws_cap;
   float* car2c = car1c + (size_t)wp_cap;
   uint8_t* ring1c = reinterpret_cast<uint8_t*>(car2c + (size_t)tw_cap);
-  uint8_t* coefc = ring1c + (size_t)ring * wp_cap;
+  uint8_t* coefc = ring1c + (size_t)(ring + 1) * wp_cap;
   uint8_t* ring3c = coefc + (size_t)2 * kChunk * wp_cap;
 
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
+  // the wave index is uniform: say so, so that what derives from it stays scalar
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const float inv255 = 1.0f / 255.0f;
   const size_t hw = (size_t)W * H;
 
-  for (int i = tid; i < wp_cap; i += kWaves * 64) { car1v[i] = make_float4(0.f, 0.f, 0.f, 0.f); car1c[i] = 0.f; }
-  for (int i = tid; i < tw_cap; i += kWaves * 64) { car2v[i] = make_float4(0.f, 0.f, 0.f, 0.f); car2c[i] = 0.f; }
+  const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int i = tid; i < wp_cap; i += kWaves * 64) {
+    car1v[i] = zero4; car1c[i] = 0.f;
+    ring1v[(size_t)ring * wp_cap + i] = zero4; ring1c[(size_t)ring * wp_cap + i] = 0;
+  }
+  for (int i = tid; i < tw_cap; i += kWaves * 64) {
+    car2v[i] = zero4; car2c[i] = 0.f;
+    ring3v[(size_t)ring * tw_cap + i] = zero4; ring3c[(size_t)ring * tw_cap + i] = 0;
+  }
 
   // Pipeline schedule (wave-uniform scalars).  Both wave groups below run
   // the same recurrence, so they meet the same barriers.  Rings hold M rows
@@ -346,13 +391,20 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
   int pc = 0;                    // coefficient buffer parity
   int nA = 0, nC = 0, nG = 0;
   auto finished = [&]() { return MODE == 1 ? (kv >= own_v1) : (pv >= tv1); };
+  // Rows each stage takes this step.  Row k's window reaches row min(k+r, H-1),
+  // which grows with k, so the rows whose windows are complete form a prefix:
+  // every remaining row once the image's last row is in, else rows k < in - r.
+  // (Closed forms: every wave evaluates them, on the one scalar unit of the CU.)
   auto count_rows = [&]() {
     nA = min(kChunk, ym1 - produced);
-    nC = 0;  // R+ rows whose window rows are all in ring1
-    while (nC < kChunk && kv + nC < yp1 && (kv + nC + r < H - 1 ? kv + nC + r : H - 1) < produced) ++nC;
+    // R+ rows whose window rows are all in ring1
+    nC = min(kChunk, yp1 - kv);
+    if (produced <= H - 1) nC = max(0, min(nC, produced - r - kv));
     nG = 0;  // R rows whose window rows are all in ring3
-    if (MODE != 1)
-      while (pv + nG < tv1 && (pv + nG + r < H - 1 ? pv + nG + r : H - 1) < kv_e) ++nG;
+    if (MODE != 1) {
+      nG = tv1 - pv;
+      if (kv_e <= H - 1) nG = max(0, min(nG, kv_e - r - pv));
+    }
   };
   auto advance = [&]() {
     const int emitted_first = kv;
@@ -380,8 +432,12 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
   if (wave < kWaves / 2) {
     // ======== waves 0-7: stage A, M rows 2w and 2w+1 of each step ========
     const int w2 = 2 * wave;
+    const char* left_b = reinterpret_cast<const char*>(left4);
+    const char* right_b = reinterpret_cast<const char*>(right4);
+    RowLanes<NSEG> rl;
+    row_lanes<NSEG>(rl, w2, xm0, wM, W, ws_cap, lane);
     RowTaps<NSEG> taps;
-    load_rows2<NSEG>(taps, produced + w2, xm0, wM, W, H, la, lb, lc, lane, left4, right4);
+    load_rows2<NSEG>(taps, rl, produced + w2, W, H, la, lb, lc, left_b, right_b);
     lds_barrier();
     while (!finished()) {
       count_rows();
@@ -389,9 +445,6 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
         // raw cost of the pair's pixels -> scan rows 2w, 2w+1 (private to this wave)
 #pragma unroll
         for (int s = 0; s < NSEG; ++s) {
-          const int t = s * 64 + lane;
-          const int h = t >= wM ? 1 : 0;
-          const int xi = t - h * wM;
           // out-of-view samples cost rho_max: rho' = 0
           const float tt = taps.t[s];
           const float4 L = taps.L[s], R0 = taps.R0[s], R1 = taps.R1[s];
@@ -403,15 +456,15 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
           const float q = rp * inv255;
           const float4 val = make_float4(rp, q * L.x, q * L.y, q * L.z);
           const float nz = rp != 0.f ? 1.f : 0.f;
-          if (xi < wM) {
-            const size_t o = (size_t)(w2 + h) * ws_cap + xi;
+          const int o = rl.lds[s];
+          if (o >= 0) {
             scanv[o] = val;
             scanc[o] = nz;
           }
         }
         // next step's image taps, in flight from here
         if (produced + nA < ym1)
-          load_rows2<NSEG>(taps, produced + nA + w2, xm0, wM, W, H, la, lb, lc, lane, left4, right4);
+          load_rows2<NSEG>(taps, rl, produced + nA + w2, W, H, la, lb, lc, left_b, right_b);
         // in-place prefix along each row: lane (h, l) runs over columns
         // NSEG*l .. NSEG*l + NSEG-1 of row 2w+h (serial prefix of the run,
         // scan of the run totals over the 32 lanes of the row, offset added)
@@ -526,7 +579,7 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
       lds_barrier();
     }
   } else {
-    // ======== waves 8-15: stages C, E and G ========
+    // ======== waves 8-15: stages C and G ========
     // C and G lanes: column j*32 + 4*cw + lane/16, row lane%16 of the step.
     const int cw = wave - kWaves / 2;
     const int q16 = lane & 15;
@@ -586,9 +639,9 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
         const bool rowok = q16 < nC;
         const int ent = k + r, lev = k - r - 1;
         const bool has_ent = rowok && ent <= H - 1, has_lev = rowok && lev >= ym0;
-        // slots of rows outside the window are never used; read slot 0 there
-        const int sl_ent = has_ent ? slot_of(ent, lo_c, sb1, ring) : 0;
-        const int sl_lev = has_lev ? slot_of(lev, lo_c, sb1, ring) : 0;
+        // rows outside the window read the zero slot
+        const int sl_ent = has_ent ? slot_of(ent, lo_c, sb1, ring) : ring;
+        const int sl_lev = has_lev ? slot_of(lev, lo_c, sb1, ring) : ring;
         const float rows = (float)((k + r < H - 1 ? k + r : H - 1) - (k - r > 0 ? k - r : 0) + 1);
         float4 V[NC], Cv[NC];
         float Vc[NC], Cc[NC];
@@ -602,10 +655,9 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
           const float4 ev = ring1v[(size_t)sl_ent * wp_cap + cr[j]], lv = ring1v[(size_t)sl_lev * wp_cap + cr[j]];
           const float ec = (float)ring1c[(size_t)sl_ent * wp_cap + cr[j]];
           const float lcn = (float)ring1c[(size_t)sl_lev * wp_cap + cr[j]];
-          const bool ue = colok && has_ent, ul = colok && has_lev;
-          V[j] = make_float4((ue ? ev.x : 0.f) - (ul ? lv.x : 0.f), (ue ? ev.y : 0.f) - (ul ? lv.y : 0.f),
-                             (ue ? ev.z : 0.f) - (ul ? lv.z : 0.f), (ue ? ev.w : 0.f) - (ul ? lv.w : 0.f));
-          Vc[j] = (ue ? ec : 0.f) - (ul ? lcn : 0.f);
+          // (columns past the R+ row compute values nobody stores)
+          V[j] = f4sub(ev, lv);
+          Vc[j] = ec - lcn;
         }
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
@@ -690,8 +742,8 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
           const bool rowok = q0 + q16 < nG;
           const int ent = p + r, lev = p - r - 1;
           const bool has_ent = rowok && ent <= H - 1, has_lev = rowok && lev >= yp0;
-          const int sl_ent = has_ent ? slot_of(ent, lo2_base, sb3, ring) : 0;
-          const int sl_lev = has_lev ? slot_of(lev, lo2_base, sb3, ring) : 0;
+          const int sl_ent = has_ent ? slot_of(ent, lo2_base, sb3, ring) : ring;
+          const int sl_lev = has_lev ? slot_of(lev, lo2_base, sb3, ring) : ring;
           const float rows = (float)((p + r < H - 1 ? p + r : H - 1) - (p - r > 0 ? p - r : 0) + 1);
           const int last = (nG - q0 < kChunk ? nG - q0 : kChunk) - 1;
           float4 V2[NC], Cv[NC];
@@ -706,10 +758,8 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
             const float4 ev = ring3v[(size_t)sl_ent * tw_cap + cr[j]], lv = ring3v[(size_t)sl_lev * tw_cap + cr[j]];
             const float ec = (float)ring3c[(size_t)sl_ent * tw_cap + cr[j]];
             const float lcn = (float)ring3c[(size_t)sl_lev * tw_cap + cr[j]];
-            const bool ue = colok && has_ent, ul = colok && has_lev;
-            V2[j] = make_float4((ue ? ev.x : 0.f) - (ul ? lv.x : 0.f), (ue ? ev.y : 0.f) - (ul ? lv.y : 0.f),
-                                (ue ? ev.z : 0.f) - (ul ? lv.z : 0.f), (ue ? ev.w : 0.f) - (ul ? lv.w : 0.f));
-            V2c[j] = (ue ? ec : 0.f) - (ul ? lcn : 0.f);
+            V2[j] = f4sub(ev, lv);
+            V2c[j] = ec - lcn;
           }
 #pragma unroll
           for (int j = 0; j < NC; ++j) {
@@ -774,7 +824,7 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
 
 #define LEXP_UNARY_INST(M, S, C)                                                                                    \
   template __global__ void k_unary<M, S, C>(const PairDev*, const Item*, const Tile*, int, const float4*, float*, \
-                                            int, int, int, int);
+                                            int, int, int, int, int, int);
 LEXP_UNARY_INST(0, 1, 1)
 LEXP_UNARY_INST(0, 2, 1)
 LEXP_UNARY_INST(0, 2, 2)
