@@ -236,7 +236,10 @@ struct RowTaps {  // prefetched operands of the pair, per lane
 // bases (images below 2^27 pixels).  The second tap is the pixel after the
 // first: where the first is a row's last pixel its weight is exactly zero and
 // the read lands on the next row or on the zeroed pixel after the image.
-template <int NSEG>
+// Segments [S0, S1) only: a step issues its loads in a few such runs between
+// its LDS phases, so that waiting for the memory pipeline to take them
+// overlaps other work.
+template <int NSEG, int S0 = 0, int S1 = NSEG>
 __device__ inline void load_rows2(RowTaps<NSEG>& tp, const RowLanes<NSEG>& rl, int y, int W, int H, float la,
                                   float lb, float lc, const char* __restrict__ left_b,
                                   const char* __restrict__ right_b) {
@@ -247,7 +250,7 @@ __device__ inline void load_rows2(RowTaps<NSEG>& tp, const RowLanes<NSEG>& rl, i
   const int ro1 = __builtin_amdgcn_readfirstlane((y + 1 < H - 1 ? y + 1 : H - 1) * W16);
   const float s0 = fmaf(lb, (float)y, lc), s1 = fmaf(lb, (float)(y + 1), lc);
 #pragma unroll
-  for (int s = 0; s < NSEG; ++s) {
+  for (int s = S0; s < S1; ++s) {
     const bool h = rl.h[s] != 0;
     const int ro = h ? ro1 : ro0;
     const float d = fmaf(la, rl.uf[s], h ? s1 : s0);
@@ -462,9 +465,16 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
             scanc[o] = nz;
           }
         }
-        // next step's image taps, in flight from here
-        if (produced + nA < ym1)
-          load_rows2<NSEG>(taps, rl, produced + nA + w2, W, H, la, lb, lc, left_b, right_b);
+        // next step's image taps, in flight from here (issued in three runs).
+        // The taps of this step are consumed: wait for them explicitly
+        // (vmcnt 0, other counters untouched) so that no wait on the runs
+        // issued below is needed before the next run.
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        constexpr int kL1 = (NSEG + 2) / 3, kL2 = (2 * NSEG + 2) / 3;
+        const bool more = produced + nA < ym1;
+        const int y_next = produced + nA + w2;
+        if (more) load_rows2<NSEG, 0, kL1>(taps, rl, y_next, W, H, la, lb, lc, left_b, right_b);
+        asm volatile("" ::: "memory");
         // in-place prefix along each row: lane (h, l) runs over columns
         // NSEG*l .. NSEG*l + NSEG-1 of row 2w+h (serial prefix of the run,
         // scan of the run totals over the 32 lanes of the row, offset added)
@@ -494,6 +504,9 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
             if (c < wM) { rv[c] = f4add(v[i], ex); rc[c] = n[i] + exn; }
           }
         }
+        asm volatile("" ::: "memory");
+        if (more) load_rows2<NSEG, kL1, kL2>(taps, rl, y_next, W, H, la, lb, lc, left_b, right_b);
+        asm volatile("" ::: "memory");
         // window sums at the R+ columns of both rows (pixel t of the pair's R+ rows)
 #pragma unroll
         for (int m = 0; m < NC; ++m) {
@@ -517,6 +530,8 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
             ring1c[(size_t)slot * wp_cap + xi] = (uint8_t)hc;
           }
         }
+        asm volatile("" ::: "memory");
+        if (more) load_rows2<NSEG, kL2, NSEG>(taps, rl, y_next, W, H, la, lb, lc, left_b, right_b);
       }
       if (MODE != 1) {
         // ---- E: horizontal sums of (a, b) at the R columns ----------------
