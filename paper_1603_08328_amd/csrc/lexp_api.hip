@@ -345,6 +345,11 @@ lexp_status launch_unary(lexp_ctx* c, const PairDev* d_pairs, const Item* d_item
   if (lds > c->lds_limit || caps.wp > lexp::kMaxWP || caps.tw > lexp::kMaxTW || caps.ws > lexp::kMaxWM)
     return fail(LEXP_EINVAL, "tile exceeds kernel limits (lds %zu > %zu or width)", lds, c->lds_limit);
   const int grid = ((n_tiles + 7) / 8) * 8;
+  // region costs: waves 8-15 also run stage A in a tile's first step when
+  // their scan rows (16 rows of M, float4 and FP32 count) fit in the ring-1
+  // slots past the first 32 rows
+  const int fill2 = MODE == 0 && (size_t)lexp::kChunk * caps.ws * 20 <=
+                                     (size_t)(ring - 2 * lexp::kChunk) * caps.wp * 16 ? 1 : 0;
   // timing covers the region-cost launches (MODE 0), the hot loop of the method
   const bool timed = c->timing && MODE == 0;
   hipEvent_t ea = nullptr, eb = nullptr;
@@ -358,7 +363,7 @@ lexp_status launch_unary(lexp_ctx* c, const PairDev* d_pairs, const Item* d_item
   const int nseg = (caps.ws + 31) / 32, nc = (std::max(caps.wp, caps.tw) + 31) / 32;
 #define LEXP_LAUNCH(M, S, C)                                                                                       \
   hipLaunchKernelGGL((lexp::k_unary<M, S, C>), dim3(grid), dim3(lexp::kWaves * 64), lds, s, d_pairs, d_items,      \
-                     d_tiles, n_tiles, label_field, out, ring, caps.wp, caps.tw, caps.ws, pair_hint, direct)
+                     d_tiles, n_tiles, label_field, out, ring, caps.wp, caps.tw, caps.ws, pair_hint, direct, fill2)
 #define LEXP_LAUNCH_C(M, S)  \
   if (nc <= 1) {             \
     LEXP_LAUNCH(M, S, 1);    \

@@ -82,7 +82,7 @@ constexpr int kMaxTW = 128;
 template <int MODE, int NSEG, int NC>
 __global__ void k_unary(const PairDev* pairs, const Item* items, const Tile* tiles, int n_tiles,
                         const float4* label_field, float* out, int ring, int wp_cap, int tw_cap, int ws_cap,
-                        int pair_hint, int direct);
+                        int pair_hint, int direct, int fill2);
 __global__ void k_pack(const float* img, float4* out, float4* outT, int W, int H, int mirror);
 __global__ void k_guide_h(const float4* left4, double* tmp, int W, int H, int r);
 __global__ void k_guide_v(const double* tmp, float* guide, int W, int H, int r, double eps);

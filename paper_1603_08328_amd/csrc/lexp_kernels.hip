@@ -267,6 +267,96 @@ __device__ inline void load_rows2(RowTaps<NSEG>& tp, const RowLanes<NSEG>& rl, i
   }
 }
 
+// Stage A of the fused kernel, in three phases over a wave's pair of M rows
+// (scan rows w2 and w2+1 of a scan buffer):
+// raw cost rho' and rho' * I of the pair's pixels into the scan rows ...
+template <int NSEG>
+__device__ inline void a_raw(const DevParams& P, const RowTaps<NSEG>& taps, const RowLanes<NSEG>& rl,
+                             float4* scanv, float* scanc) {
+  const float inv255 = 1.0f / 255.0f;
+#pragma unroll
+  for (int s = 0; s < NSEG; ++s) {
+    // out-of-view samples cost rho_max: rho' = 0
+    const float tt = taps.t[s];
+    const float4 L = taps.L[s], R0 = taps.R0[s], R1 = taps.R1[s];
+    const float col = fabsf(L.x - fmaf(tt, R1.x - R0.x, R0.x)) + fabsf(L.y - fmaf(tt, R1.y - R0.y, R0.y)) +
+                      fabsf(L.z - fmaf(tt, R1.z - R0.z, R0.z));
+    const float gr = fabsf(L.w - fmaf(tt, R1.w - R0.w, R0.w));
+    const float rp0 = P.oma * (fminf(col, P.tc) - P.tc) + P.al * (fminf(gr, P.tg) - P.tg);
+    const float rp = taps.ok[s] ? rp0 : 0.f;
+    const float q = rp * inv255;
+    const float4 val = make_float4(rp, q * L.x, q * L.y, q * L.z);
+    const float nz = rp != 0.f ? 1.f : 0.f;
+    const int o = rl.lds[s];
+    if (o >= 0) {
+      scanv[o] = val;
+      scanc[o] = nz;
+    }
+  }
+}
+
+// ... an in-place prefix along each scan row: lane (h, l) runs over columns
+// NSEG*l .. NSEG*l + NSEG-1 of row w2+h (serial prefix of the run, scan of the
+// run totals over the 32 lanes of the row, offset added) ...
+template <int NSEG>
+__device__ inline void a_prefix(float4* scanv, float* scanc, int w2, int ws_cap, int wM, int lane) {
+  const int h = lane >> 5, l = lane & 31;
+  float4* rv = scanv + (size_t)(w2 + h) * ws_cap;
+  float* rc = scanc + (size_t)(w2 + h) * ws_cap;
+  float4 v[NSEG];
+  float n[NSEG];
+#pragma unroll
+  for (int i = 0; i < NSEG; ++i) {
+    const int c = l * NSEG + i;
+    v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    n[i] = 0.f;
+    if (c < wM) { v[i] = rv[c]; n[i] = rc[c]; }
+  }
+#pragma unroll
+  for (int i = 1; i < NSEG; ++i) { v[i] = f4add(v[i - 1], v[i]); n[i] = n[i - 1] + n[i]; }
+  const float4 tot = v[NSEG - 1];
+  const float nt = n[NSEG - 1];
+  const float4 ex = make_float4(half_scan(tot.x) - tot.x, half_scan(tot.y) - tot.y, half_scan(tot.z) - tot.z,
+                                half_scan(tot.w) - tot.w);
+  const float exn = half_scan(nt) - nt;
+#pragma unroll
+  for (int i = 0; i < NSEG; ++i) {
+    const int c = l * NSEG + i;
+    if (c < wM) { rv[c] = f4add(v[i], ex); rc[c] = n[i] + exn; }
+  }
+}
+
+// ... and horizontal window sums at the R+ columns of the first `rows` rows of
+// the pair (pixel t of the pair's R+ rows), into ring 1 at the slots of image
+// rows row0 and row0+1.
+template <int NC>
+__device__ inline void a_wsum(const float4* scanv, const float* scanc, int w2, int rows, int ws_cap, int wP, int xp0,
+                              int xm0, int r, int W, int row0, int lo_c, int sb1, int ring, float4* ring1v,
+                              uint8_t* ring1c, int wp_cap, int lane) {
+#pragma unroll
+  for (int m = 0; m < NC; ++m) {
+    const int t = m * 64 + lane;
+    const int h = t >= wP ? 1 : 0;
+    const int xi = t - h * wP;
+    if (xi < wP && h < rows) {
+      const float4* rv = scanv + (size_t)(w2 + h) * ws_cap;
+      const float* rc = scanc + (size_t)(w2 + h) * ws_cap;
+      const int x = xp0 + xi;
+      const int lo = (x - r > 0 ? x - r : 0) - xm0;
+      const int hi = (x + r < W - 1 ? x + r : W - 1) - xm0;
+      const int lm = lo > 0 ? lo - 1 : 0;
+      const float4 a = rv[hi], b = rv[lm];
+      const float ac = rc[hi], bc = rc[lm];
+      float4 hs = lo > 0 ? f4sub(a, b) : a;
+      const float hc = lo > 0 ? ac - bc : ac;
+      if (hc == 0.f) hs = make_float4(0.f, 0.f, 0.f, 0.f);
+      const int slot = slot_of(row0 + h, lo_c, sb1, ring);
+      ring1v[(size_t)slot * wp_cap + xi] = hs;
+      ring1c[(size_t)slot * wp_cap + xi] = (uint8_t)hc;
+    }
+  }
+}
+
 // Entry i of a pair table, read through the constant address space: the
 // compiler then takes the pointers it holds for global memory and loads
 // through them with global (not flat) instructions.  The table is not written
@@ -284,7 +374,7 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
                                                const Tile* __restrict__ tiles, int n_tiles,
                                                const float4* __restrict__ label_field, float* __restrict__ out,
                                                int ring, int wp_cap, int tw_cap, int ws_cap, int pair_hint,
-                                               int direct) {
+                                               int direct, int fill2) {
   extern __shared__ float4 smem4[];
   // blocks are dispatched round-robin over the 8 XCDs; give every XCD a
   // contiguous run of tiles so neighbouring tiles share its L2
@@ -398,8 +488,9 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
   // which grows with k, so the rows whose windows are complete form a prefix:
   // every remaining row once the image's last row is in, else rows k < in - r.
   // (Closed forms: every wave evaluates them, on the one scalar unit of the CU.)
+  // (with fill2, waves 8-15 take rows 16-31 of the first step as stage A)
   auto count_rows = [&]() {
-    nA = min(kChunk, ym1 - produced);
+    nA = min(fill2 && produced == ym0 ? 2 * kChunk : kChunk, ym1 - produced);
     // R+ rows whose window rows are all in ring1
     nC = min(kChunk, yp1 - kv);
     if (produced <= H - 1) nC = max(0, min(nC, produced - r - kv));
@@ -446,25 +537,7 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
       count_rows();
       if (w2 < nA) {
         // raw cost of the pair's pixels -> scan rows 2w, 2w+1 (private to this wave)
-#pragma unroll
-        for (int s = 0; s < NSEG; ++s) {
-          // out-of-view samples cost rho_max: rho' = 0
-          const float tt = taps.t[s];
-          const float4 L = taps.L[s], R0 = taps.R0[s], R1 = taps.R1[s];
-          const float col = fabsf(L.x - fmaf(tt, R1.x - R0.x, R0.x)) + fabsf(L.y - fmaf(tt, R1.y - R0.y, R0.y)) +
-                            fabsf(L.z - fmaf(tt, R1.z - R0.z, R0.z));
-          const float gr = fabsf(L.w - fmaf(tt, R1.w - R0.w, R0.w));
-          const float rp0 = P.oma * (fminf(col, P.tc) - P.tc) + P.al * (fminf(gr, P.tg) - P.tg);
-          const float rp = taps.ok[s] ? rp0 : 0.f;
-          const float q = rp * inv255;
-          const float4 val = make_float4(rp, q * L.x, q * L.y, q * L.z);
-          const float nz = rp != 0.f ? 1.f : 0.f;
-          const int o = rl.lds[s];
-          if (o >= 0) {
-            scanv[o] = val;
-            scanc[o] = nz;
-          }
-        }
+        a_raw<NSEG>(P, taps, rl, scanv, scanc);
         // next step's image taps, in flight from here (issued in three runs).
         // The taps of this step are consumed: wait for them explicitly
         // (vmcnt 0, other counters untouched) so that no wait on the runs
@@ -475,61 +548,12 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
         const int y_next = produced + nA + w2;
         if (more) load_rows2<NSEG, 0, kL1>(taps, rl, y_next, W, H, la, lb, lc, left_b, right_b);
         asm volatile("" ::: "memory");
-        // in-place prefix along each row: lane (h, l) runs over columns
-        // NSEG*l .. NSEG*l + NSEG-1 of row 2w+h (serial prefix of the run,
-        // scan of the run totals over the 32 lanes of the row, offset added)
-        {
-          const int h = lane >> 5, l = lane & 31;
-          float4* rv = scanv + (size_t)(w2 + h) * ws_cap;
-          float* rc = scanc + (size_t)(w2 + h) * ws_cap;
-          float4 v[NSEG];
-          float n[NSEG];
-#pragma unroll
-          for (int i = 0; i < NSEG; ++i) {
-            const int c = l * NSEG + i;
-            v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-            n[i] = 0.f;
-            if (c < wM) { v[i] = rv[c]; n[i] = rc[c]; }
-          }
-#pragma unroll
-          for (int i = 1; i < NSEG; ++i) { v[i] = f4add(v[i - 1], v[i]); n[i] = n[i - 1] + n[i]; }
-          const float4 tot = v[NSEG - 1];
-          const float nt = n[NSEG - 1];
-          const float4 ex = make_float4(half_scan(tot.x) - tot.x, half_scan(tot.y) - tot.y, half_scan(tot.z) - tot.z,
-                                        half_scan(tot.w) - tot.w);
-          const float exn = half_scan(nt) - nt;
-#pragma unroll
-          for (int i = 0; i < NSEG; ++i) {
-            const int c = l * NSEG + i;
-            if (c < wM) { rv[c] = f4add(v[i], ex); rc[c] = n[i] + exn; }
-          }
-        }
+        a_prefix<NSEG>(scanv, scanc, w2, ws_cap, wM, lane);
         asm volatile("" ::: "memory");
         if (more) load_rows2<NSEG, kL1, kL2>(taps, rl, y_next, W, H, la, lb, lc, left_b, right_b);
         asm volatile("" ::: "memory");
-        // window sums at the R+ columns of both rows (pixel t of the pair's R+ rows)
-#pragma unroll
-        for (int m = 0; m < NC; ++m) {
-          const int t = m * 64 + lane;
-          const int h = t >= wP ? 1 : 0;
-          const int xi = t - h * wP;
-          if (xi < wP && w2 + h < nA) {
-            const float4* rv = scanv + (size_t)(w2 + h) * ws_cap;
-            const float* rc = scanc + (size_t)(w2 + h) * ws_cap;
-            const int x = xp0 + xi;
-            const int lo = (x - r > 0 ? x - r : 0) - xm0;
-            const int hi = (x + r < W - 1 ? x + r : W - 1) - xm0;
-            const int lm = lo > 0 ? lo - 1 : 0;
-            const float4 a = rv[hi], b = rv[lm];
-            const float ac = rc[hi], bc = rc[lm];
-            float4 hs = lo > 0 ? f4sub(a, b) : a;
-            const float hc = lo > 0 ? ac - bc : ac;
-            if (hc == 0.f) hs = make_float4(0.f, 0.f, 0.f, 0.f);
-            const int slot = slot_of(produced + w2 + h, lo_c, sb1, ring);
-            ring1v[(size_t)slot * wp_cap + xi] = hs;
-            ring1c[(size_t)slot * wp_cap + xi] = (uint8_t)hc;
-          }
-        }
+        a_wsum<NC>(scanv, scanc, w2, nA - w2, ws_cap, wP, xp0, xm0, r, W, produced + w2, lo_c, sb1, ring, ring1v,
+                   ring1c, wp_cap, lane);
         asm volatile("" ::: "memory");
         if (more) load_rows2<NSEG, kL2, NSEG>(taps, rl, y_next, W, H, la, lb, lc, left_b, right_b);
       }
@@ -635,9 +659,35 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
         lp[j] = left4T[(size_t)(tu0 + (ci < tw - 1 ? ci : tw - 1)) * H + pc_];
       }
     };
-    load_guide(kv);
-    if (MODE != 1) load_left(pv);
-    lds_barrier();
+    if (fill2 && !finished()) {
+      // First step: nothing for C and G yet, so these waves run stage A on
+      // rows 16-31 of the step, with scan rows in ring-1 slots 32 and up
+      // (rows of later steps only).  Their taps and registers die here.
+      const int w2c = 2 * cw;
+      float4* sv = ring1v + (size_t)2 * kChunk * wp_cap;
+      float* sc = reinterpret_cast<float*>(sv + (size_t)kChunk * ws_cap);
+      RowLanes<NSEG> rlc;
+      row_lanes<NSEG>(rlc, w2c, xm0, wM, W, ws_cap, lane);
+      RowTaps<NSEG> tc;
+      load_rows2<NSEG>(tc, rlc, produced + kChunk + w2c, W, H, la, lb, lc, reinterpret_cast<const char*>(left4),
+                       reinterpret_cast<const char*>(right4));
+      lds_barrier();
+      count_rows();
+      if (kChunk + w2c < nA) {
+        a_raw<NSEG>(P, tc, rlc, sv, sc);
+        a_prefix<NSEG>(sv, sc, w2c, ws_cap, wM, lane);
+        a_wsum<NC>(sv, sc, w2c, nA - kChunk - w2c, ws_cap, wP, xp0, xm0, r, W, produced + kChunk + w2c, lo_c, sb1,
+                   ring, ring1v, ring1c, wp_cap, lane);
+      }
+      load_guide(kv + nC);
+      if (MODE != 1) load_left(pv + nG);
+      advance();
+      lds_barrier();
+    } else {
+      load_guide(kv);
+      if (MODE != 1) load_left(pv);
+      lds_barrier();
+    }
     while (!finished()) {
       count_rows();
 
@@ -839,7 +889,7 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
 
 #define LEXP_UNARY_INST(M, S, C)                                                                                    \
   template __global__ void k_unary<M, S, C>(const PairDev*, const Item*, const Tile*, int, const float4*, float*, \
-                                            int, int, int, int, int, int);
+                                            int, int, int, int, int, int, int);
 LEXP_UNARY_INST(0, 1, 1)
 LEXP_UNARY_INST(0, 2, 1)
 LEXP_UNARY_INST(0, 2, 2)
