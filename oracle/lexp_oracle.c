@@ -411,7 +411,7 @@ void ora_filter_map(const ora_ctx* c, const double* rho, double* out) {
   filter_rect(c, R, rho, R, out, NULL);
 }
 
-/* Per-pixel unary phi_p(f_p) with every pixel's own label (Alg. 2 line 2 state):
+/* Per-pixel unary phi_p(f_p) with every pixel's own label (the state after the initialisation of Alg. 2):
  * each pixel is a 1x1 region. */
 void ora_pixel_costs(const ora_ctx* c, const float* labels, const uint8_t* mask, double* out) {
   int n = c->W * c->H;
@@ -763,7 +763,7 @@ uint64_t ora_rng_key(uint64_t seed, const uint64_t* fields, int nfields) {
   return key_chain(seed, fields, nfields);
 }
 
-/* Random initialisation (Alg. 2 line 2): z0 ~ U[0, dispmax], n uniform on the
+/* Random initialisation (Alg. 2): z0 ~ U[0, dispmax], n uniform on the
  * upper unit hemisphere, plane through (p_u, p_v, z0) with normal n. */
 void ora_init_labels(const ora_ctx* c, uint64_t seed, float* labels) {
   int W = c->W, H = c->H;

@@ -1619,7 +1619,7 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     HIP_TRY(hipMemsetAsync(B.d_res.p, 0, sizeof(int), s));
   }
 
-  // Alg. 2 line 2: random initial labels and their per-pixel costs.
+  // Alg. 2, initialisation: random labels and their per-pixel costs.
   for (int p = 0; p < np; ++p) {
     RunPair& rp = pairs[p];
     lexp_ctx* pc = rp.c;
@@ -1632,7 +1632,7 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
   }
   if (time_trace) time_trace[0] = now_s();
 
-  double scale = 1.0;  // Alg. 2 line 3: (r_d, r_n) = (disp_max / 2, 1) times scale
+  double scale = 1.0;  // Alg. 2: perturbation sizes (r_d, r_n) = (disp_max / 2, 1) times scale
   for (int it = 0; it < sch->iterations; ++it) {
     for (int h = 0; h < sch->n_levels; ++h) {
       const int K = sch->k_prop[h] + sch->k_rans[h] + sch->k_rand[h];
@@ -1679,7 +1679,7 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     // group's captured graphs are replayed by the later iterations
     if (use_graph)
       for (CutBalance& b : balance) b.tune = false;
-    scale *= 0.5;  // Alg. 2 line 12
+    scale *= 0.5;  // Alg. 2: the perturbation sizes halve after every iteration
     for (int p = 0; p < np; ++p) {
       RunPair& rp = pairs[p];
       if (rp.energy_trace)

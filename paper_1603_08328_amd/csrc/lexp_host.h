@@ -19,7 +19,7 @@ uint64_t key_chain(uint64_t seed, const uint64_t* fields, int n);
 double u01_open1(uint64_t x);    // [0, 1)
 double u01_open0(uint64_t x);    // (0, 1]
 
-// Random initial label of pixel (u, v) (Alg. 2 line 2).
+// Random initial label of pixel (u, v) (Alg. 2, initialisation).
 void init_label(int width, int u, int v, double disp_max, uint64_t seed, float out[3]);
 
 // Candidate label of one alpha_ij-expansion step (Alg. 1), in its order:
