@@ -681,6 +681,24 @@ def test_optimize_batch_rejects_mixed_radius_and_shared_buffers(tiny):
     ctx2.close()
 
 
+def test_create_rejects_images_past_the_offset_limit(tiny):
+    """The fused kernel addresses packed images with 32-bit byte offsets, so a
+    context takes at most 2^27 - 1 pixels; larger sizes are refused before any
+    allocation (the image pointers are not read)."""
+    lib = L.load_library()
+    p = tiny.p
+    buf = torch.zeros(3, device="cuda")
+    for w, h in [(16384, 8192), (1 << 27, 1)]:
+        P = L.lexp_params(w, h, float(p["disp_max"]), float(p["alpha"]), float(p["tau_col"]), float(p["tau_grad"]),
+                          int(p["gf_radius"]), float(p["gf_eps"]), float(p["lam"]), float(p["tau_dis"]),
+                          float(p["w_floor"]), float(p["gamma"]), int(p["neighbours"]), 0, 1, 0, 0)
+        out = L.C.c_void_p()
+        st = lib.lexp_create(L.C.byref(P), L.C.c_void_p(buf.data_ptr()), L.C.c_void_p(buf.data_ptr()), None,
+                             L.C.byref(out))
+        assert st == L.LEXP_EINVAL and not out.value, (w, h, st)
+        assert b"2^27" in lib.lexp_last_error()
+
+
 # ---------------------------------------------------------------------------
 # Right view and post-processing.
 def _right_view(P):
