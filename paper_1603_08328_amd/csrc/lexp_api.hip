@@ -1,6 +1,7 @@
 // C ABI of the local-expansion-move library: context, argument validation,
 // kernel launches, one batch of disjoint local expansions, and the
 // optimisation procedure (Alg. 2 with Alg. 1 per cell).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -351,19 +352,29 @@ lexp_status launch_unary(lexp_ctx* c, const PairDev* d_pairs, const Item* d_item
   const int fill2 = MODE == 0 && (size_t)lexp::kChunk * caps.ws * 20 <=
                                      (size_t)(ring - 2 * lexp::kChunk) * caps.wp * 16 ? 1 : 0;
   // timing covers the region-cost launches (MODE 0), the hot loop of the method
+  // (timed launches go through hipExtLaunchKernel, whose two events take the
+  // kernel's own start and end on the stream)
   const bool timed = c->timing && MODE == 0;
   hipEvent_t ea = nullptr, eb = nullptr;
   if (timed) {
     ea = take_event(c);
     eb = take_event(c);
-    if (ea && eb) HIP_TRY(hipEventRecord(ea, s));
   }
+  const bool tev = timed && ea && eb;
   // instance by the 32-column segments of an M row (64-lane segments of a row
   // pair) and of an R+ row
   const int nseg = (caps.ws + 31) / 32, nc = (std::max(caps.wp, caps.tw) + 31) / 32;
-#define LEXP_LAUNCH(M, S, C)                                                                                       \
-  hipLaunchKernelGGL((lexp::k_unary<M, S, C>), dim3(grid), dim3(lexp::kWaves * 64), lds, s, d_pairs, d_items,      \
-                     d_tiles, n_tiles, label_field, out, ring, caps.wp, caps.tw, caps.ws, pair_hint, direct, fill2)
+#define LEXP_LAUNCH(M, S, C)                                                                                      \
+  do {                                                                                                            \
+    if (tev)                                                                                                      \
+      hipExtLaunchKernelGGL((lexp::k_unary<M, S, C>), dim3(grid), dim3(lexp::kWaves * 64), (uint32_t)lds, s, ea, eb, \
+                            0u, d_pairs, d_items, d_tiles, n_tiles, label_field, out, ring, caps.wp, caps.tw,     \
+                            caps.ws, pair_hint, direct, fill2);                                                   \
+    else                                                                                                          \
+      hipLaunchKernelGGL((lexp::k_unary<M, S, C>), dim3(grid), dim3(lexp::kWaves * 64), lds, s, d_pairs, d_items,  \
+                         d_tiles, n_tiles, label_field, out, ring, caps.wp, caps.tw, caps.ws, pair_hint, direct,  \
+                         fill2);                                                                                  \
+  } while (0)
 #define LEXP_LAUNCH_C(M, S)  \
   if (nc <= 1) {             \
     LEXP_LAUNCH(M, S, 1);    \
@@ -398,8 +409,7 @@ lexp_status launch_unary(lexp_ctx* c, const PairDev* d_pairs, const Item* d_item
 #undef LEXP_LAUNCH_C
 #undef LEXP_LAUNCH
   HIP_TRY(hipGetLastError());
-  if (timed && ea && eb) {
-    HIP_TRY(hipEventRecord(eb, s));
+  if (tev) {
     c->ev_pending.push_back({ea, eb, alg_bytes});
     c->stats.unary_launches += 1;
     c->stats.unary_alg_bytes += alg_bytes;
