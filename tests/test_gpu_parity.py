@@ -162,6 +162,25 @@ def test_unary_lowres_random_rects(lowres, size):
         assert_cost_close(g, P.ora.unary_region(rc, lab).reshape(-1), P.rho_max, f"rect {rc} label {lab}")
 
 
+def test_unary_highres_group_launches_sampled():
+    """1500x1000 workload: every region of one cell group per level in one
+    launch, as the optimisation's launches at that size (hundreds to
+    thousands of tiles, several rounds per CU), and a sample of the regions
+    against the oracle."""
+    P = Pair("highres-1500x1000")
+    rng = np.random.default_rng(77)
+    for cell in (5, 15, 25):
+        nci, ncj = -(-P.W // cell), -(-P.H // cell)
+        cells = [(i, j) for j in range(1, ncj, 4) for i in range(2, nci, 4)]
+        rects = [((i - 1) * cell, (j - 1) * cell, (i + 2) * cell, (j + 2) * cell) for i, j in cells]
+        labs = _label_mix(P, rng, len(rects))
+        got = _unary(P, rects, labs)
+        for q in rng.choice(len(rects), 8, replace=False):
+            ref = P.ora.unary_region(rects[q], labs[q]).reshape(-1)
+            assert_cost_close(got[q], ref, P.rho_max, f"cell {cell} rect {rects[q]} label {labs[q]}")
+    P.ctx.close()
+
+
 def test_unary_whole_image_one_item(lowres):
     P = lowres
     lab = P.gt[200, 220]
