@@ -126,7 +126,7 @@ typedef struct {
   int64_t unary_launches;   /* launches of the fused cost kernel */
   int64_t unary_items;      /* (region, label) items evaluated */
   int64_t unary_evals;      /* phi_p evaluations (sum of clipped |R|) */
-  double unary_kernel_ms;   /* sum of kernel durations (HIP events on the launch stream) */
+  double unary_kernel_ms;   /* sum of the timed launches' kernel durations (HIP events on the launch stream) */
   double unary_alg_bytes;   /* algorithmic bytes: sum over items of 16|M| + 16|M| + 36|R+| + 4|R| */
   int64_t expand_calls;     /* group steps (one batch of disjoint expansions) */
   double host_cut_ms;       /* host max-flow time, or with the device cut the host time after
@@ -142,6 +142,9 @@ typedef struct {
   int32_t device_cut_block[4];  /* lexp_optimize: threads per region the device max-flow's launch-shape
                                    tuner chose per level (0: not tuned; every shape gives the same cut) */
   int32_t device_cut_relabel[4];/* its rounds between global relabels */
+  int64_t unary_timed_launches; /* fused-kernel launches timed (every N-th, see lexp_set_timing) */
+  double unary_timed_alg_bytes; /* their algorithmic bytes */
+  int64_t unary_timed_evals;    /* their phi_p evaluations */
 } lexp_stats;
 
 /* Creates a context for one stereo pair and runs the label-independent set-up
@@ -309,8 +312,12 @@ lexp_status lexp_net_train_step(lexp_net* net, lexp_ctx* ctx, const float* label
 /* The network lexp_optimize uses when schedule->learned is 1 (NULL: none). */
 lexp_status lexp_set_net(lexp_ctx* ctx, lexp_net* net);
 
-/* Timing of the fused cost kernel (HIP events around each launch on its
- * stream) and host phases.  enable != 0 turns it on; reset clears counters. */
+/* Timing of the fused cost kernel and of the host phases.  enable = N > 0
+ * turns it on: every launch is counted, and every N-th fused launch (N = 1:
+ * all) is launched with two HIP events on its stream that take the kernel's
+ * own start and end (their host cost is about 12 us per launch, so a sample
+ * keeps the whole job's time close to an untimed run); 0 turns it off,
+ * negative values are LEXP_EINVAL.  reset clears the counters. */
 lexp_status lexp_set_timing(lexp_ctx* ctx, int32_t enable);
 lexp_status lexp_get_stats(lexp_ctx* ctx, lexp_stats* out);
 lexp_status lexp_reset_stats(lexp_ctx* ctx);

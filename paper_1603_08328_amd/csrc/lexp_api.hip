@@ -137,6 +137,8 @@ struct lexp_ctx {
   std::unique_ptr<lexp::ThreadPool> pool;
   std::vector<std::unique_ptr<lexp::BKSolver>> solvers;
   bool timing = false;
+  int time_every = 1;    // time every time_every-th fused launch
+  int64_t time_seq = 0;  // fused launches since timing was turned on
   lexp_stats stats{};
   std::vector<hipEvent_t> ev_free;
   struct Pending { hipEvent_t a, b; double bytes; };
@@ -356,11 +358,16 @@ lexp_status launch_unary(lexp_ctx* c, const PairDev* d_pairs, const Item* d_item
   // kernel's own start and end on the stream)
   const bool timed = c->timing && MODE == 0;
   hipEvent_t ea = nullptr, eb = nullptr;
-  if (timed) {
+  if (timed && c->time_seq++ % c->time_every == 0) {
     ea = take_event(c);
     eb = take_event(c);
+    if (!(ea && eb)) {  // (no events to be had: this launch goes untimed)
+      if (ea) c->ev_free.push_back(ea);
+      if (eb) c->ev_free.push_back(eb);
+      ea = eb = nullptr;
+    }
   }
-  const bool tev = timed && ea && eb;
+  const bool tev = ea && eb;
   // instance by the 32-column segments of an M row (64-lane segments of a row
   // pair) and of an R+ row
   const int nseg = (caps.ws + 31) / 32, nc = (std::max(caps.wp, caps.tw) + 31) / 32;
@@ -409,12 +416,17 @@ lexp_status launch_unary(lexp_ctx* c, const PairDev* d_pairs, const Item* d_item
 #undef LEXP_LAUNCH_C
 #undef LEXP_LAUNCH
   HIP_TRY(hipGetLastError());
-  if (tev) {
-    c->ev_pending.push_back({ea, eb, alg_bytes});
+  if (timed) {
     c->stats.unary_launches += 1;
     c->stats.unary_alg_bytes += alg_bytes;
     c->stats.unary_evals += evals;
     c->stats.unary_items += n_items;
+  }
+  if (tev) {
+    c->ev_pending.push_back({ea, eb, alg_bytes});
+    c->stats.unary_timed_launches += 1;
+    c->stats.unary_timed_alg_bytes += alg_bytes;
+    c->stats.unary_timed_evals += evals;
   }
   return LEXP_OK;
 }
@@ -1961,7 +1973,10 @@ lexp_status lexp_set_net(lexp_ctx* c, lexp_net* net) {
 
 lexp_status lexp_set_timing(lexp_ctx* c, int32_t enable) {
   if (!c) return fail(LEXP_EINVAL, "null context");
+  if (enable < 0) return fail(LEXP_EINVAL, "timing period %d < 0", enable);
   c->timing = enable != 0;
+  c->time_every = enable > 0 ? enable : 1;
+  c->time_seq = 0;
   return LEXP_OK;
 }
 

@@ -56,7 +56,9 @@ class lexp_stats(C.Structure):
                 ("host_enqueue_ms", C.c_double), ("host_update_ms", C.c_double),
                 ("host_cut_level_ms", C.c_double * 4), ("device_cut_fallbacks", C.c_int64),
                 ("device_cut_share", C.c_double * 4), ("graphs_captured", C.c_int64),
-                ("device_cut_block", C.c_int32 * 4), ("device_cut_relabel", C.c_int32 * 4)]
+                ("device_cut_block", C.c_int32 * 4), ("device_cut_relabel", C.c_int32 * 4),
+                ("unary_timed_launches", C.c_int64), ("unary_timed_alg_bytes", C.c_double),
+                ("unary_timed_evals", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -469,8 +471,9 @@ def lexp_set_net(ctx, net):
     ctx._net = net  # keep the network alive as long as the context uses it
 
 
-def lexp_set_timing(ctx, enable: bool):
-    _check(load_library().lexp_set_timing(ctx.handle, int(bool(enable))))
+def lexp_set_timing(ctx, enable):
+    """enable: False/0 off; True/1 time every fused launch; N > 1 every N-th."""
+    _check(load_library().lexp_set_timing(ctx.handle, int(enable)))
 
 
 def lexp_get_stats(ctx) -> dict:
