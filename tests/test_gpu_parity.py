@@ -700,6 +700,32 @@ def test_optimize_batch_rejects_mixed_radius_and_shared_buffers(tiny):
     ctx2.close()
 
 
+def test_sampled_timing_counts_every_launch_and_times_every_nth(tiny):
+    """lexp_set_timing(ctx, N): every fused launch is counted, every N-th is
+    timed (events at the kernel's own start and end), with its bytes and
+    evaluations; N = 1 times them all; negative periods are refused."""
+    P = tiny
+    lab = torch.zeros((P.H, P.W, 4), device="cuda")
+    cost = torch.zeros((P.H, P.W), device="cuda")
+    for every in (1, 3):
+        L.lexp_set_timing(P.ctx, every)
+        L.lexp_reset_stats(P.ctx)
+        L.lexp_optimize(P.ctx, [(5, 1, 3)], 1, 0, lab, cost)
+        st = L.lexp_get_stats(P.ctx)
+        n = st["unary_launches"]
+        assert n > 0 and st["unary_timed_launches"] == (n + every - 1) // every
+        assert st["unary_kernel_ms"] > 0
+        if every == 1:
+            assert st["unary_timed_alg_bytes"] == st["unary_alg_bytes"]
+            assert st["unary_timed_evals"] == st["unary_evals"]
+        else:
+            assert 0 < st["unary_timed_alg_bytes"] < st["unary_alg_bytes"]
+            assert 0 < st["unary_timed_evals"] < st["unary_evals"]
+    with pytest.raises(L.LexpError):
+        L.lexp_set_timing(P.ctx, -1)
+    L.lexp_set_timing(P.ctx, 0)
+
+
 def test_create_rejects_images_past_the_offset_limit(tiny):
     """The fused kernel addresses packed images with 32-bit byte offsets, so a
     context takes at most 2^27 - 1 pixels; larger sizes are refused before any
