@@ -1060,8 +1060,8 @@ lexp_status net_forward(lexp_net* net, lexp_ctx* c, const float* labels, hipStre
   const int n = W * H;
   hipLaunchKernelGGL(lexp::k_net_input, dim3((n + 255) / 256), dim3(256), 0, s, c->left4, c->right4,
                      (const float4*)labels, W, H, (double)c->prm.disp_max, net->act[0]);
-  const int runs = ((W + 63) / 64) * H;  // 64-pixel row runs, four per workgroup
-  const dim3 grid((runs + 3) / 4);
+  // forward: a workgroup per four rows of a 64-column run
+  const dim3 grid(((W + 63) / 64) * ((H + 3) / 4));
   for (int l = 0; l < lexp_net::kLayers; ++l) {
     const uint16_t* w16 = net->w16 + net->w16_off[l];
     const float* b = net->prm + net->b_off[l];
@@ -1914,8 +1914,8 @@ lexp_status lexp_net_train_step(lexp_net* net, lexp_ctx* c, const float* labels,
   uint16_t* g = net->gbuf[0];
   hipLaunchKernelGGL(lexp::k_net_loss, dim3(nb), dim3(256), 0, s, net->y, (const float4*)target, W, H,
                      (double)c->prm.disp_max, g, net->part_loss);
-  const int runs = ((W + 63) / 64) * H;  // 64-pixel row runs, four per workgroup
-  const dim3 grid((runs + 3) / 4);
+  // input gradients: a workgroup per four rows of a 64-column run
+  const dim3 grid(((W + 63) / 64) * ((H + 3) / 4));
   // backward through the layers: weight gradients, then the gradient of the
   // layer's input (through the ReLU that produced it)
   for (int l = lexp_net::kLayers - 1; l >= 0; --l) {

@@ -103,18 +103,51 @@ __global__ void k_net_input(const float4* __restrict__ left4, const float4* __re
 // once and used for all of them.
 constexpr int kSegs = 4;
 
-// Forward convolution of one layer: each wave computes kSegs x 16 pixels of a
-// row (all output channels); bias, then ReLU and BF16 (hidden layers) or FP32
-// output (last layer).
+// Patch of a pixel-major BF16 map with C channels that a workgroup's four
+// rows v0..v0+3 of one run of kSegs x 16 columns read through 3x3 taps: rows
+// v0-1..v0+4, columns u0-1..u0+16 kSegs, zero outside the image, a pixel's
+// channels kPatchPad elements apart (the 16 pixels of a fragment then fall in
+// distinct LDS banks).  Coalesced 16-byte loads, 8-byte LDS stores.
+constexpr int kPatchW = 16 * kSegs + 2;
+constexpr int kPatchR = 4 + 2;
+constexpr int kPatchPad = 4;
+
+template <int C>
+__device__ inline void stage_patch(const uint16_t* __restrict__ src, int W, int H, int u0, int v0,
+                                   uint16_t* patch) {
+  constexpr int kPS = C + kPatchPad;
+  constexpr int kPieces = C / 8;
+  for (int i = threadIdx.x; i < kPatchR * kPatchW * kPieces; i += blockDim.x) {
+    const int pc = i % kPieces, px = i / kPieces;
+    const int col = px % kPatchW, row = px / kPatchW;
+    const int yy = v0 - 1 + row, xx = u0 - 1 + col;
+    uint4 val = make_uint4(0u, 0u, 0u, 0u);
+    if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+      val = *reinterpret_cast<const uint4*>(src + ((size_t)yy * W + xx) * C + pc * 8);
+    uint2* dst = reinterpret_cast<uint2*>(patch + (size_t)px * kPS + pc * 8);
+    dst[0] = make_uint2(val.x, val.y);
+    dst[1] = make_uint2(val.z, val.w);
+  }
+}
+
+// Forward convolution of one layer.  A workgroup takes four rows v0..v0+3 of
+// one run of kSegs x 16 columns: it stages the input patch those rows read in
+// LDS, then each wave computes one row of the run (all output channels) from
+// LDS fragments.  Bias, then ReLU and BF16 (hidden layers) or FP32 output
+// (last layer).
 template <int CI, int CO, bool LAST>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w16,
                                                   const float* __restrict__ bias, int W, int H,
                                                   uint16_t* __restrict__ xo, float* __restrict__ yo) {
-  const int lane = threadIdx.x & 63;
-  const int runs = (W + 16 * kSegs - 1) / (16 * kSegs);
-  const int run = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (run >= runs * H) return;
-  const int v = run / runs, u0 = (run % runs) * 16 * kSegs;
+  constexpr int kPW = kPatchW, kPS = CI + kPatchPad;
+  __shared__ __align__(16) uint16_t patch[kPatchR * kPatchW * kPS];
+  const int nrun = (W + 16 * kSegs - 1) / (16 * kSegs);
+  const int u0 = (blockIdx.x % nrun) * 16 * kSegs, v0 = (blockIdx.x / nrun) * 4;
+  stage_patch<CI>(x, W, H, u0, v0, patch);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int v = v0 + wv;
+  if (v >= H) return;
   const int m = lane & 15, kq = (lane >> 4) * 4;
   f32x4 acc[kSegs][CO / 16];
 #pragma unroll
@@ -123,8 +156,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
     for (int nb = 0; nb < CO / 16; ++nb) acc[sg][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
-    const int yy = v + tap / 3 - 1;
-    const bool row_in = yy >= 0 && yy < H;
+    const int prow = wv + tap / 3;  // patch row of image row v + tap/3 - 1
 #pragma unroll
     for (int cb = 0; cb < CI / 16; ++cb) {
       bf16x4 b[CO / 16];
@@ -132,10 +164,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
       for (int nb = 0; nb < CO / 16; ++nb) b[nb] = load4(w16 + ((size_t)tap * CO + nb * 16 + m) * CI + cb * 16 + kq);
 #pragma unroll
       for (int sg = 0; sg < kSegs; ++sg) {
-        const int xx = u0 + sg * 16 + m + tap % 3 - 1;
-        const bool in = row_in && xx >= 0 && xx < W;
-        const size_t q = in ? (size_t)yy * W + xx : 0;  // an address inside the image either way
-        const bf16x4 a = in ? load4(x + q * CI + cb * 16 + kq) : zero4();
+        // patch column of image column u0 + 16 sg + m + tap%3 - 1
+        const bf16x4 a = load4(patch + ((size_t)prow * kPW + sg * 16 + m + tap % 3) * kPS + cb * 16 + kq);
 #pragma unroll
         for (int nb = 0; nb < CO / 16; ++nb)
           acc[sg][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[nb], acc[sg][nb], 0, 0, 0);
@@ -164,16 +194,21 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
 
 // Gradient of a layer's input: dx(p) = sum over taps and output channels of
 // W[tap][o][i] g(p - offset)[o], then gp = BF16(dx * [x(p) > 0]) (the input
-// came from a ReLU).  kSegs x 16 pixels of a row per wave.
+// came from a ReLU).  Workgroups as in the forward convolution, with the
+// patch of g (the taps mirrored).
 template <int CI, int CO>
 __global__ __launch_bounds__(256) void k_conv_bwd_x(const uint16_t* __restrict__ g, const uint16_t* __restrict__ wt16,
                                                     const uint16_t* __restrict__ x, int W, int H,
                                                     uint16_t* __restrict__ gp) {
-  const int lane = threadIdx.x & 63;
-  const int runs = (W + 16 * kSegs - 1) / (16 * kSegs);
-  const int run = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (run >= runs * H) return;
-  const int v = run / runs, u0 = (run % runs) * 16 * kSegs;
+  constexpr int kPW = kPatchW, kPS = CO + kPatchPad;
+  __shared__ __align__(16) uint16_t patch[kPatchR * kPatchW * kPS];
+  const int nrun = (W + 16 * kSegs - 1) / (16 * kSegs);
+  const int u0 = (blockIdx.x % nrun) * 16 * kSegs, v0 = (blockIdx.x / nrun) * 4;
+  stage_patch<CO>(g, W, H, u0, v0, patch);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int v = v0 + wv;
+  if (v >= H) return;
   const int m = lane & 15, kq = (lane >> 4) * 4;
   f32x4 acc[kSegs][CI / 16];
 #pragma unroll
@@ -182,8 +217,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_x(const uint16_t* __restrict__
     for (int nb = 0; nb < CI / 16; ++nb) acc[sg][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
-    const int yy = v - (tap / 3 - 1);
-    const bool row_in = yy >= 0 && yy < H;
+    const int prow = wv + 2 - tap / 3;  // patch row of image row v - (tap/3 - 1)
 #pragma unroll
     for (int cb = 0; cb < CO / 16; ++cb) {
       bf16x4 b[CI / 16];
@@ -191,10 +225,8 @@ __global__ __launch_bounds__(256) void k_conv_bwd_x(const uint16_t* __restrict__
       for (int nb = 0; nb < CI / 16; ++nb) b[nb] = load4(wt16 + ((size_t)tap * CI + nb * 16 + m) * CO + cb * 16 + kq);
 #pragma unroll
       for (int sg = 0; sg < kSegs; ++sg) {
-        const int xx = u0 + sg * 16 + m - (tap % 3 - 1);
-        const bool in = row_in && xx >= 0 && xx < W;
-        const size_t q = in ? (size_t)yy * W + xx : 0;  // an address inside the image either way
-        const bf16x4 a = in ? load4(g + q * CO + cb * 16 + kq) : zero4();
+        // patch column of image column u0 + 16 sg + m - (tap%3 - 1)
+        const bf16x4 a = load4(patch + ((size_t)prow * kPW + sg * 16 + m + 2 - tap % 3) * kPS + cb * 16 + kq);
 #pragma unroll
         for (int nb = 0; nb < CI / 16; ++nb)
           acc[sg][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[nb], acc[sg][nb], 0, 0, 0);
@@ -221,11 +253,19 @@ __global__ __launch_bounds__(256) void k_conv_bwd_x(const uint16_t* __restrict__
 // Weight and bias gradients of one layer, partial sums per pixel chunk:
 // part_w[chunk][tap][o][i] = sum over the chunk's pixels p of g(p)[o]
 // x(p + offset(tap))[i]; part_b[chunk][o] (tap-0 workgroups) = sum of g(p)[o].
-// Grid (chunks, 9 taps); four waves split the chunk's 16-pixel blocks.
+// Grid (chunks, 9 taps).  The chunk goes through LDS in tiles of kTile
+// pixels (g and the shifted x, pixel-major, coalesced 16-byte loads, the next
+// tile's loads in flight during this tile's products); wave w takes the
+// 16-pixel blocks w, w+4, ... of the chunk, in order.
 template <int CI, int CO>
 __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__ g, const uint16_t* __restrict__ x,
                                                     int W, int H, int chunk_px, float* __restrict__ part_w,
                                                     float* __restrict__ part_b) {
+  constexpr int kTile = 256;
+  constexpr int kGS = CO + 8, kXS = CI + 8;  // LDS elements per pixel (16-byte aligned rows)
+  constexpr int kGP = kTile * CO / 8 / 256, kXP = kTile * CI / 8 / 256;  // 16-byte pieces per thread
+  __shared__ __align__(16) uint16_t gs[kTile * kGS];
+  __shared__ __align__(16) uint16_t xs[kTile * kXS];
   __shared__ float red[4][CO * CI];
   __shared__ float redb[4][CO];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -234,6 +274,25 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
   const int p0 = chunk * chunk_px, p1 = min(p0 + chunk_px, P);
   const int dy = tap / 3 - 1, dx = tap % 3 - 1;
   const int m = lane & 15, kq = (lane >> 4) * 4;
+  uint4 gv[kGP], xv[kXP];
+  auto fetch = [&](int t0) {
+#pragma unroll
+    for (int k = 0; k < kGP; ++k) {
+      const int piece = threadIdx.x + k * 256;
+      const int p = t0 + piece / (CO / 8), c8 = piece % (CO / 8);
+      gv[k] = p < p1 ? *reinterpret_cast<const uint4*>(g + (size_t)p * CO + c8 * 8) : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int k = 0; k < kXP; ++k) {
+      const int piece = threadIdx.x + k * 256;
+      const int p = t0 + piece / (CI / 8), c8 = piece % (CI / 8);
+      const int u = p % W, v = p / W;
+      const int xx = u + dx, yy = v + dy;
+      const bool in = p < p1 && xx >= 0 && xx < W && yy >= 0 && yy < H;
+      xv[k] = in ? *reinterpret_cast<const uint4*>(x + ((size_t)yy * W + xx) * CI + c8 * 8)
+                 : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
   f32x4 acc[CO / 16][CI / 16];
 #pragma unroll
   for (int mb = 0; mb < CO / 16; ++mb)
@@ -242,32 +301,43 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
   float bsum[CO / 16];
 #pragma unroll
   for (int mb = 0; mb < CO / 16; ++mb) bsum[mb] = 0.f;
-  for (int k0 = p0 + wave * 16; k0 < p1; k0 += 64) {
-    // this lane's four pixels of the 16-pixel block
-    bf16x4 a[CO / 16], b[CI / 16];
+  fetch(p0);
+  for (int t0 = p0; t0 < p1; t0 += kTile) {
+    __syncthreads();  // the previous tile's fragments are read
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int p = k0 + kq + i;
-      const bool pin = p < p1;
-      const int u = pin ? p % W : 0, v = pin ? p / W : 0;
-      const int xx = u + dx, yy = v + dy;
-      const bool xin = pin && xx >= 0 && xx < W && yy >= 0 && yy < H;
-#pragma unroll
-      for (int mb = 0; mb < CO / 16; ++mb) {
-        const uint16_t gv = pin ? g[(size_t)p * CO + mb * 16 + m] : (uint16_t)0;
-        a[mb][i] = (short)gv;
-        if (tap == 0) bsum[mb] += from_bf16(gv);
-      }
-#pragma unroll
-      for (int nb = 0; nb < CI / 16; ++nb)
-        b[nb][i] = (short)(xin ? x[((size_t)yy * W + xx) * CI + nb * 16 + m] : (uint16_t)0);
+    for (int k = 0; k < kGP; ++k) {
+      const int piece = threadIdx.x + k * 256;
+      *reinterpret_cast<uint4*>(gs + (piece / (CO / 8)) * kGS + (piece % (CO / 8)) * 8) = gv[k];
     }
-    // A[o][pixel] and B[pixel][i]: lane m is the row of A and the column of B
 #pragma unroll
-    for (int mb = 0; mb < CO / 16; ++mb)
+    for (int k = 0; k < kXP; ++k) {
+      const int piece = threadIdx.x + k * 256;
+      *reinterpret_cast<uint4*>(xs + (piece / (CI / 8)) * kXS + (piece % (CI / 8)) * 8) = xv[k];
+    }
+    __syncthreads();
+    if (t0 + kTile < p1) fetch(t0 + kTile);
+    for (int bl = wave; bl < kTile / 16 && t0 + bl * 16 < p1; bl += 4) {
+      // this lane's four pixels of the block (zero past the chunk)
+      bf16x4 a[CO / 16], b[CI / 16];
 #pragma unroll
-      for (int nb = 0; nb < CI / 16; ++nb)
-        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+      for (int i = 0; i < 4; ++i) {
+        const int px = bl * 16 + kq + i;
+#pragma unroll
+        for (int mb = 0; mb < CO / 16; ++mb) {
+          const uint16_t gq = gs[px * kGS + mb * 16 + m];
+          a[mb][i] = (short)gq;
+          if (tap == 0) bsum[mb] += from_bf16(gq);
+        }
+#pragma unroll
+        for (int nb = 0; nb < CI / 16; ++nb) b[nb][i] = (short)xs[px * kXS + nb * 16 + m];
+      }
+      // A[o][pixel] and B[pixel][i]: lane m is the row of A and the column of B
+#pragma unroll
+      for (int mb = 0; mb < CO / 16; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < CI / 16; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int mb = 0; mb < CO / 16; ++mb)
