@@ -130,10 +130,25 @@ __device__ inline void stage_patch(const uint16_t* __restrict__ src, int W, int 
   }
 }
 
+// A layer's BF16 weights, rows of K elements ([tap][row][K] for 9 x R rows),
+// copied to LDS with rows K+4 elements apart (the 16 rows of a fragment then
+// fall in distinct banks).
+template <int R, int K>
+__device__ inline void stage_weights(const uint16_t* __restrict__ w, uint16_t* ws) {
+  constexpr int kPieces = K / 8;
+  for (int i = threadIdx.x; i < 9 * R * kPieces; i += blockDim.x) {
+    const int row = i / kPieces, pc = i % kPieces;
+    const uint4 val = *reinterpret_cast<const uint4*>(w + (size_t)row * K + pc * 8);
+    uint2* dst = reinterpret_cast<uint2*>(ws + (size_t)row * (K + 4) + pc * 8);
+    dst[0] = make_uint2(val.x, val.y);
+    dst[1] = make_uint2(val.z, val.w);
+  }
+}
+
 // Forward convolution of one layer.  A workgroup takes four rows v0..v0+3 of
-// one run of kSegs x 16 columns: it stages the input patch those rows read in
-// LDS, then each wave computes one row of the run (all output channels) from
-// LDS fragments.  Bias, then ReLU and BF16 (hidden layers) or FP32 output
+// one run of kSegs x 16 columns: it stages the input patch those rows read and
+// the layer's weights in LDS, then each wave computes one row of the run (all
+// output channels) from LDS fragments.  Bias, then ReLU and BF16 (hidden layers) or FP32 output
 // (last layer).
 template <int CI, int CO, bool LAST>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w16,
@@ -141,9 +156,11 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
                                                   uint16_t* __restrict__ xo, float* __restrict__ yo) {
   constexpr int kPW = kPatchW, kPS = CI + kPatchPad;
   __shared__ __align__(16) uint16_t patch[kPatchR * kPatchW * kPS];
+  __shared__ __align__(16) uint16_t wsh[9 * CO * (CI + 4)];
   const int nrun = (W + 16 * kSegs - 1) / (16 * kSegs);
   const int u0 = (blockIdx.x % nrun) * 16 * kSegs, v0 = (blockIdx.x / nrun) * 4;
   stage_patch<CI>(x, W, H, u0, v0, patch);
+  stage_weights<CO, CI>(w16, wsh);
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int v = v0 + wv;
@@ -161,7 +178,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
     for (int cb = 0; cb < CI / 16; ++cb) {
       bf16x4 b[CO / 16];
 #pragma unroll
-      for (int nb = 0; nb < CO / 16; ++nb) b[nb] = load4(w16 + ((size_t)tap * CO + nb * 16 + m) * CI + cb * 16 + kq);
+      for (int nb = 0; nb < CO / 16; ++nb) b[nb] = load4(wsh + (tap * CO + nb * 16 + m) * (CI + 4) + cb * 16 + kq);
 #pragma unroll
       for (int sg = 0; sg < kSegs; ++sg) {
         // patch column of image column u0 + 16 sg + m + tap%3 - 1
@@ -202,9 +219,11 @@ __global__ __launch_bounds__(256) void k_conv_bwd_x(const uint16_t* __restrict__
                                                     uint16_t* __restrict__ gp) {
   constexpr int kPW = kPatchW, kPS = CO + kPatchPad;
   __shared__ __align__(16) uint16_t patch[kPatchR * kPatchW * kPS];
+  __shared__ __align__(16) uint16_t wsh[9 * CI * (CO + 4)];
   const int nrun = (W + 16 * kSegs - 1) / (16 * kSegs);
   const int u0 = (blockIdx.x % nrun) * 16 * kSegs, v0 = (blockIdx.x / nrun) * 4;
   stage_patch<CO>(g, W, H, u0, v0, patch);
+  stage_weights<CI, CO>(wt16, wsh);
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int v = v0 + wv;
@@ -222,7 +241,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_x(const uint16_t* __restrict__
     for (int cb = 0; cb < CO / 16; ++cb) {
       bf16x4 b[CI / 16];
 #pragma unroll
-      for (int nb = 0; nb < CI / 16; ++nb) b[nb] = load4(wt16 + ((size_t)tap * CI + nb * 16 + m) * CO + cb * 16 + kq);
+      for (int nb = 0; nb < CI / 16; ++nb) b[nb] = load4(wsh + (tap * CI + nb * 16 + m) * (CO + 4) + cb * 16 + kq);
 #pragma unroll
       for (int sg = 0; sg < kSegs; ++sg) {
         // patch column of image column u0 + 16 sg + m - (tap%3 - 1)
