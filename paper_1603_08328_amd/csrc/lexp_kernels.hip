@@ -816,6 +816,7 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
           int cr[NC];
 #pragma unroll
           for (int j = 0; j < NC; ++j) {
+            if (j * 32 + cw * 4 >= tw) break;  // no column of this wave in group j (uniform)
             const bool colok = cl[j] < tw;
             cr[j] = colok ? cl[j] : 0;
             Cv[j] = car2v[cr[j]];  // carried sums (zero before the first rows)
@@ -828,6 +829,7 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
           }
 #pragma unroll
           for (int j = 0; j < NC; ++j) {
+            if (j * 32 + cw * 4 >= tw) break;  // no column of this wave in group j (uniform)
             V2[j].x = row_scan16(V2[j].x);
             V2[j].y = row_scan16(V2[j].y);
             V2[j].z = row_scan16(V2[j].z);
@@ -839,6 +841,7 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
             const int i_hi = tv0 - 1 + r < H - 1 ? tv0 - 1 + r : H - 1;
 #pragma unroll
             for (int j = 0; j < NC; ++j) {
+              if (j * 32 + cw * 4 >= tw) break;  // no column of this wave in group j (uniform)
               float4 I = make_float4(0.f, 0.f, 0.f, 0.f);
               float Ic = 0.f;
               if (cl[j] < tw)
@@ -858,12 +861,14 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
           } else {
 #pragma unroll
             for (int j = 0; j < NC; ++j) {
+              if (j * 32 + cw * 4 >= tw) break;  // no column of this wave in group j (uniform)
               V2[j] = f4add(Cv[j], V2[j]);
               V2c[j] = Cc[j] + V2c[j];
             }
           }
 #pragma unroll
           for (int j = 0; j < NC; ++j) {
+            if (j * 32 + cw * 4 >= tw) break;  // no column of this wave in group j (uniform)
             const float4 L = lp[j];
             const float phi = (V2[j].x * (L.x * inv255) + V2[j].y * (L.y * inv255) + V2[j].z * (L.z * inv255) +
                                V2[j].w) * __builtin_amdgcn_rcpf(ncG[j] * rows);
