@@ -735,23 +735,32 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
         if (kv == yp0) {  // first rows of the tile (uniform branch)
           const int i_lo = yp0 - 1 - r > ym0 ? yp0 - 1 - r : ym0;
           const int i_hi = yp0 - 1 + r < H - 1 ? yp0 - 1 + r : H - 1;
+          // the column groups' reads of one row are issued together (columns
+          // past the R+ row read column 0; nobody stores their sums)
+          float4 I[NC];
+          float Ic[NC];
 #pragma unroll
           for (int j = 0; j < NC; ++j) {
-            float4 I = make_float4(0.f, 0.f, 0.f, 0.f);
-            float Ic = 0.f;
-            if (cl[j] < wP)
-              for (int y = i_lo + q16; y <= i_hi; y += 16) {
-                const int sl = slot_of(y, lo_c, sb1, ring);
-                I = f4add(I, ring1v[(size_t)sl * wp_cap + cl[j]]);
-                Ic += (float)ring1c[(size_t)sl * wp_cap + cl[j]];
-              }
-            I.x = row_last(row_scan16(I.x), lane);
-            I.y = row_last(row_scan16(I.y), lane);
-            I.z = row_last(row_scan16(I.z), lane);
-            I.w = row_last(row_scan16(I.w), lane);
-            Ic = row_last(row_scan16(Ic), lane);
-            V[j] = f4add(I, V[j]);
-            Vc[j] = Ic + Vc[j];
+            I[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+            Ic[j] = 0.f;
+          }
+          for (int y = i_lo + q16; y <= i_hi; y += 16) {
+            const int sl = slot_of(y, lo_c, sb1, ring);
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+              I[j] = f4add(I[j], ring1v[(size_t)sl * wp_cap + cr[j]]);
+              Ic[j] += (float)ring1c[(size_t)sl * wp_cap + cr[j]];
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            I[j].x = row_last(row_scan16(I[j].x), lane);
+            I[j].y = row_last(row_scan16(I[j].y), lane);
+            I[j].z = row_last(row_scan16(I[j].z), lane);
+            I[j].w = row_last(row_scan16(I[j].w), lane);
+            Ic[j] = row_last(row_scan16(Ic[j]), lane);
+            V[j] = f4add(I[j], V[j]);
+            Vc[j] = Ic[j] + Vc[j];
           }
         } else {
 #pragma unroll
