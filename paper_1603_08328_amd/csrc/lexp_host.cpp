@@ -3,7 +3,10 @@
 // double-precision proposer arithmetic is rounded exactly as written.
 #include "lexp_host.h"
 
+#include <sched.h>
+
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -505,29 +508,78 @@ ThreadPool::ThreadPool(int n_threads) {
 ThreadPool::~ThreadPool() {
   {
     std::lock_guard<std::mutex> lk(mu_);
-    stop_ = true;
+    stop_.store(true);
   }
   cv_start_.notify_all();
   for (auto& t : workers_) t.join();
 }
 
+// A worker waits for the next job by polling the generation for up to
+// kSpinUs (the method's steps follow each other within that), then sleeps on
+// the condition variable: a sleeping worker takes tens of microseconds to
+// wake, a polling one a fraction of one.  At most one poller per CPU the
+// process may run on, less one, across all pools; the others sleep at once.
+// A poller yields its CPU between polls, so a thread with work (a woken
+// worker of another pool, the caller) is not kept from running.  The caller
+// waits for the workers the same way.
+static constexpr double kSpinUs = 2000.0;
+static std::atomic<int> g_pollers{0};
+
+static int poller_cap() {
+  static const int cap = [] {
+    cpu_set_t set;
+    const int n = sched_getaffinity(0, sizeof(set), &set) == 0 ? CPU_COUNT(&set)
+                                                                 : (int)std::thread::hardware_concurrency();
+    return std::max(0, n - 1);
+  }();
+  return cap;
+}
+
+static inline void cpu_pause(int k) {
+  if ((k & 15) == 0) {
+    sched_yield();
+  } else {
+#if defined(__x86_64__) || defined(__i386__)
+    __builtin_ia32_pause();
+#endif
+  }
+}
+
 void ThreadPool::worker_loop(int id) {
   uint64_t seen = 0;
   for (;;) {
-    const std::function<void(int, int)>* job;
-    int n;
-    {
-      std::unique_lock<std::mutex> lk(mu_);
-      cv_start_.wait(lk, [&] { return stop_ || generation_ != seen; });
-      if (stop_) return;
-      seen = generation_;
-      job = job_;
-      n = n_items_;
+    uint64_t g = generation_.load(std::memory_order_acquire);
+    if (g == seen) {
+      bool sleep = true;
+      if (g_pollers.fetch_add(1, std::memory_order_relaxed) < poller_cap()) {
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int k = 1;; ++k) {
+          g = generation_.load(std::memory_order_acquire);
+          if (g != seen || stop_.load(std::memory_order_relaxed)) {
+            sleep = false;
+            break;
+          }
+          cpu_pause(k);
+          if ((k & 127) == 0 &&
+              std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() > kSpinUs)
+            break;
+        }
+      }
+      g_pollers.fetch_sub(1, std::memory_order_relaxed);
+      if (sleep) {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_start_.wait(lk, [&] { return stop_.load() || generation_.load() != seen; });
+        g = generation_.load(std::memory_order_acquire);
+      }
     }
+    if (stop_.load(std::memory_order_acquire)) return;
+    seen = g;
+    const std::function<void(int, int)>* job = job_;
+    const int n = n_items_;
     for (int it = next_.fetch_add(1); it < n; it = next_.fetch_add(1)) (*job)(it, id);
-    {
+    if (pending_.fetch_sub(1, std::memory_order_acq_rel) == 1) {
       std::lock_guard<std::mutex> lk(mu_);
-      if (--pending_ == 0) cv_done_.notify_one();
+      cv_done_.notify_one();
     }
   }
 }
@@ -538,18 +590,26 @@ void ThreadPool::parallel_for(int n, const std::function<void(int, int)>& fn) {
     for (int i = 0; i < n; ++i) fn(i, 0);
     return;
   }
+  job_ = &fn;
+  n_items_ = n;
+  next_.store(0, std::memory_order_relaxed);
+  pending_.store((int)workers_.size(), std::memory_order_relaxed);
+  generation_.fetch_add(1, std::memory_order_release);
   {
-    std::lock_guard<std::mutex> lk(mu_);
-    job_ = &fn;
-    n_items_ = n;
-    next_.store(0);
-    pending_ = (int)workers_.size();
-    ++generation_;
+    std::lock_guard<std::mutex> lk(mu_);  // orders the new generation before a sleeper's check
   }
   cv_start_.notify_all();
   for (int it = next_.fetch_add(1); it < n; it = next_.fetch_add(1)) fn(it, 0);
-  std::unique_lock<std::mutex> lk(mu_);
-  cv_done_.wait(lk, [&] { return pending_ == 0; });
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int k = 1; pending_.load(std::memory_order_acquire) != 0; ++k) {
+    cpu_pause(k);
+    if ((k & 127) == 0 &&
+        std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() > kSpinUs) {
+      std::unique_lock<std::mutex> lk(mu_);
+      cv_done_.wait(lk, [&] { return pending_.load(std::memory_order_acquire) == 0; });
+      break;
+    }
+  }
 }
 
 }  // namespace lexp

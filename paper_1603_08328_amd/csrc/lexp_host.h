@@ -94,9 +94,9 @@ class ThreadPool {
   const std::function<void(int, int)>* job_ = nullptr;
   int n_items_ = 0;
   std::atomic<int> next_{0};
-  int pending_ = 0;
-  uint64_t generation_ = 0;
-  bool stop_ = false;
+  std::atomic<int> pending_{0};
+  std::atomic<uint64_t> generation_{0};
+  std::atomic<bool> stop_{false};
 };
 
 }  // namespace lexp

@@ -51,11 +51,6 @@ __device__ inline bf16x4 load4(const uint16_t* p) {
   return r;
 }
 
-__device__ inline bf16x4 zero4() {
-  bf16x4 r = {0, 0, 0, 0};
-  return r;
-}
-
 }  // namespace
 
 // Network input, 16 BF16 channels per pixel: RGB/255 of the context's left
