@@ -12,7 +12,7 @@ Prints one JSON line.  ``value`` is cost evaluations (phi_p for one pixel
 under one candidate label, including the per-pixel initial costs) per second
 of whole-job wall time, in Gpix*labels/s.  ``roofline`` reports the fused
 cost kernel: algorithmic bytes per launch over its HIP-event duration on its
-launch stream (every third launch of the timed steps).  ``cpu_baseline`` times the FP64 oracle on a bounded sample of
+launch stream (every seventh launch of the timed steps).  ``cpu_baseline`` times the FP64 oracle on a bounded sample of
 the same workload on the host cores and extrapolates to the same unit.
 """
 from __future__ import annotations
@@ -37,7 +37,7 @@ HBM_PEAK_GBPS = 8000.0
 # taken at the kernel's own start and end: a systematic sample over all
 # levels, groups and both parts of a group step (an odd period alternates the
 # parts); timing every launch would add its host cost to the whole job.
-TIME_EVERY = 3
+TIME_EVERY = 7
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_unary_lowres-450x375_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1603_08328_amd", "csrc", "lexp_kernels.hip")
 
