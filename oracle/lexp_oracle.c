@@ -702,8 +702,8 @@ int64_t ora_solve_bruteforce(int rw, int rh, int neighbours, const int64_t* U, c
 /* One expansion: computes phi(alpha) over R, builds and solves the binary
  * problem, applies it to labels/costs.  Returns the quantised energy change
  * (<= 0) and the number of pixels that took alpha. */
-int64_t ora_expand(const ora_ctx* c, float* labels, double* costs, int u0, int v0, int u1, int v1,
-                   const float* alpha, int bruteforce, int32_t* n_changed) {
+static int64_t expand_one(const ora_ctx* c, float* labels, double* costs, int u0, int v0, int u1, int v1,
+                          const float* alpha, int bruteforce, int32_t* n_changed, double* phi_out) {
   rect_t R = clip_dilate(c, u0, v0, u1, v1, 0);
   int rw = R.u1 - R.u0, rh = R.v1 - R.v0, W = c->W;
   if (n_changed) *n_changed = 0;
@@ -728,8 +728,42 @@ int64_t ora_expand(const ora_ctx* c, float* labels, double* costs, int u0, int v
     ++nc;
   }
   if (n_changed) *n_changed = nc;
+  if (phi_out) memcpy(phi_out, phi, sizeof(double) * n);
   free(phi); free(U); free(w4); free(x);
   return de;
+}
+
+int64_t ora_expand(const ora_ctx* c, float* labels, double* costs, int u0, int v0, int u1, int v1,
+                   const float* alpha, int bruteforce, int32_t* n_changed) {
+  return expand_one(c, labels, costs, u0, v0, u1, v1, alpha, bruteforce, n_changed, NULL);
+}
+
+/* One step of a group (Alg. 2: the same step of Alg. 1 for every cell of a
+ * group at once): ora_expand on each of n regions with its own candidate.
+ * The regions must be pairwise separated by a pixel (Lemma 3: the moves are
+ * then independent), so they run in parallel.  rects: n x (u0, v0, u1, v1);
+ * alphas: n x 3.  phi_out (may be NULL) receives phi_p(alpha) of Eq. (6) over
+ * each clipped region, row-major, regions back to back; dEq and n_changed
+ * (may be NULL) one value per region. */
+void ora_expand_step(const ora_ctx* c, float* labels, double* costs, int n, const int32_t* rects,
+                     const float* alphas, double* phi_out, int64_t* dEq, int32_t* n_changed) {
+  int64_t* off = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  off[0] = 0;
+  for (int q = 0; q < n; ++q) {
+    rect_t R = clip_dilate(c, rects[4 * q], rects[4 * q + 1], rects[4 * q + 2], rects[4 * q + 3], 0);
+    int64_t a = (int64_t)imax(R.u1 - R.u0, 0) * imax(R.v1 - R.v0, 0);
+    off[q + 1] = off[q] + a;
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int q = 0; q < n; ++q) {
+    const int32_t* rc = rects + 4 * q;
+    int32_t nc = 0;
+    int64_t de = expand_one(c, labels, costs, rc[0], rc[1], rc[2], rc[3], alphas + 3 * q, 0, &nc,
+                            phi_out ? phi_out + off[q] : NULL);
+    if (dEq) dEq[q] = de;
+    if (n_changed) n_changed[q] = nc;
+  }
+  free(off);
 }
 
 /* ---------------------------------------------------------------------------

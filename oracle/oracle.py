@@ -66,6 +66,8 @@ def lib():
     L.ora_solve_maxflow.argtypes = [C.c_int, C.c_int, C.c_int, i64, i64, u8]
     L.ora_solve_bruteforce.restype = C.c_int64
     L.ora_solve_bruteforce.argtypes = [C.c_int, C.c_int, C.c_int, i64, i64, u8]
+    L.ora_expand_step.restype = None
+    L.ora_expand_step.argtypes = [vp, f32, f64, C.c_int, _P(np.int32), f32, vp, vp, vp]
     L.ora_expand.restype = C.c_int64
     L.ora_expand.argtypes = [vp, f32, f64, C.c_int, C.c_int, C.c_int, C.c_int, f32, C.c_int,
                              C.POINTER(C.c_int32)]
@@ -253,6 +255,29 @@ class Oracle:
         nc = C.c_int32()
         de = self._L.ora_expand(self.ctx, labels, costs, *map(int, rect), _lab(alpha), int(bruteforce), C.byref(nc))
         return de, nc.value
+
+    def expand_step(self, labels, costs, rects, alphas, want_phi=False):
+        """One step of a group: ora_expand on every region (pairwise separated
+        by a pixel, so independent by Lemma 3) in parallel, in place on labels
+        and costs.  Returns (dEq [n], n_changed [n], phi) with phi the
+        concatenated phi(alpha) of the clipped regions (row-major) or None."""
+        assert labels.dtype == np.float32 and labels.flags.c_contiguous
+        assert costs.dtype == np.float64 and costs.flags.c_contiguous
+        rects = np.ascontiguousarray(np.asarray(rects, dtype=np.int32).reshape(-1, 4))
+        alphas = np.ascontiguousarray(np.asarray(alphas, dtype=np.float32).reshape(-1, 3))
+        n = len(rects)
+        de = np.zeros(n, np.int64)
+        nc = np.zeros(n, np.int32)
+        phi = None
+        if want_phi:
+            tot = 0
+            for u0, v0, u1, v1 in rects:
+                a0, b0, a1, b1 = self._clip(self.W, self.H, (u0, v0, u1, v1))
+                tot += max(a1 - a0, 0) * max(b1 - b0, 0)
+            phi = np.zeros(max(tot, 1))
+        self._L.ora_expand_step(self.ctx, labels, costs, n, rects, alphas,
+                                None if phi is None else phi.ctypes.data, de.ctypes.data, nc.ctypes.data)
+        return de, nc, phi
 
     # --- randomness, proposals, driver ----------------------------------------------
     def rng_key(self, seed, fields):

@@ -348,11 +348,16 @@ lexp_status launch_unary(lexp_ctx* c, const PairDev* d_pairs, const Item* d_item
   if (lds > c->lds_limit || caps.wp > lexp::kMaxWP || caps.tw > lexp::kMaxTW || caps.ws > lexp::kMaxWM)
     return fail(LEXP_EINVAL, "tile exceeds kernel limits (lds %zu > %zu or width)", lds, c->lds_limit);
   const int grid = ((n_tiles + 7) / 8) * 8;
-  // region costs: waves 8-15 also run stage A in a tile's first step when
-  // their scan rows (16 rows of M, float4 and FP32 count) fit in the ring-1
-  // slots past the first 32 rows
-  const int fill2 = MODE == 0 && (size_t)lexp::kChunk * caps.ws * 20 <=
-                                     (size_t)(ring - 2 * lexp::kChunk) * caps.wp * 16 ? 1 : 0;
+  // Region costs with r >= 20: waves 8-15 also run stage A in a tile's first
+  // step (32 rows instead of 16).  The choice changes the tile's row schedule
+  // and so the rounding of its vertical sums; it depends on r alone, never on
+  // the launch.  Their scan rows (16 rows of M, float4 and FP32 count) go to
+  // the ring-1 slots past the first 32 rows: 320 ws <= 16 (2r+1) wp, which
+  // holds for every tile once r >= 20 (the M width exceeds the R+ width by at
+  // most r on each side where R+ itself extends r past the tile).
+  const int fill2 = MODE == 0 && c->r >= 20 ? 1 : 0;
+  if (fill2 && (size_t)lexp::kChunk * caps.ws * 20 > (size_t)(ring - 2 * lexp::kChunk) * caps.wp * 16)
+    return fail(LEXP_EINVAL, "internal: first-step scan rows exceed the ring (ws %d, wp %d)", caps.ws, caps.wp);
   // timing covers the region-cost launches (MODE 0), the hot loop of the method
   // (timed launches go through hipExtLaunchKernel, whose two events take the
   // kernel's own start and end on the stream)
@@ -1405,9 +1410,11 @@ struct GroupPlan {
 // The pair's cells (Eq. (15): group 4 (j mod 4) + (i mod 4)) are ordered
 // largest region first; when the pair has more than four regions per host
 // thread in the group they alternate between two parts, otherwise all are in
-// part 0.  Tiles are planned per pair and part, so a region gets the same
-// tiles (and the same rounding) whether its pair runs alone or batched, and
-// whichever part of the run's group step it is put in.
+// part 0.  Tiles are planned once for all of the pair's regions of the group,
+// so a region's tiles (and with them the rounding of its costs) depend on the
+// pair, the level and the group only: not on the host threads, not on which
+// part of the run's group step it is put in, not on other pairs batched with
+// it.
 void plan_pair_group(const lexp_ctx* c, int pair, int cell, int k, GroupPlan& g) {
   const int nci = (c->W + cell - 1) / cell, ncj = (c->H + cell - 1) / cell;
   std::vector<std::pair<int, int>> cells;
@@ -1421,42 +1428,38 @@ void plan_pair_group(const lexp_ctx* c, int pair, int cell, int k, GroupPlan& g)
   std::stable_sort(cells.begin(), cells.end(),
                    [&](const std::pair<int, int>& x, const std::pair<int, int>& y) { return area(x) > area(y); });
   const bool split = cells.size() > (size_t)4 * c->n_threads;
-  for (int hp = 0; hp < 2; ++hp) {
-    std::vector<Item> mine;
-    std::vector<std::pair<int, int>> mine_cells;
-    for (size_t q = split ? (size_t)hp : 0; q < (split || hp == 0 ? cells.size() : 0); q += split ? 2 : 1) {
-      int u0, v0, u1, v1;
-      cell_region(c, cell, cells[q].first, cells[q].second, &u0, &v0, &u1, &v1);
-      Item it{};
-      it.ru0 = u0; it.rv0 = v0; it.rw = u1 - u0; it.rh = v1 - v0;
-      it.pair = pair;
-      mine.push_back(it);
-      mine_cells.push_back(cells[q]);
-    }
-    std::vector<Tile> t;
-    TileCaps unused;
-    plan_tiles(c, mine.data(), (int)mine.size(), t, unused);
-    const size_t base = g.items.size();
-    for (size_t q = 0; q < mine.size(); ++q) {
-      g.items.push_back(mine[q]);
-      g.ci.push_back(mine_cells[q].first);
-      g.cj.push_back(mine_cells[q].second);
-      g.pair_part.push_back(hp);
-      g.tiles.emplace_back();
-      g.caps.emplace_back();
-      g.n_px += (int64_t)mine[q].rw * mine[q].rh;
-    }
-    for (Tile tl : t) {
-      const size_t q = base + (size_t)tl.item;
-      tl.item = 0;
-      TileCaps& cp = g.caps[q];
-      cp.wp = std::max(cp.wp, std::min(tl.tu1 + c->r, c->W) - std::max(tl.tu0 - c->r, 0));
-      cp.tw = std::max(cp.tw, tl.tu1 - tl.tu0);
-      const int wm = std::min(tl.tu1 + 2 * c->r, c->W) - std::max(tl.tu0 - 2 * c->r, 0);
-      cp.ws = std::max(cp.ws, std::max(wm, cp.wp));
-      g.tiles[q].push_back(tl);
-      g.n_tiles += 1;
-    }
+  std::vector<Item> mine;
+  for (const auto& q : cells) {
+    int u0, v0, u1, v1;
+    cell_region(c, cell, q.first, q.second, &u0, &v0, &u1, &v1);
+    Item it{};
+    it.ru0 = u0; it.rv0 = v0; it.rw = u1 - u0; it.rh = v1 - v0;
+    it.pair = pair;
+    mine.push_back(it);
+  }
+  std::vector<Tile> t;
+  TileCaps unused;
+  plan_tiles(c, mine.data(), (int)mine.size(), t, unused);
+  const size_t base = g.items.size();
+  for (size_t q = 0; q < mine.size(); ++q) {
+    g.items.push_back(mine[q]);
+    g.ci.push_back(cells[q].first);
+    g.cj.push_back(cells[q].second);
+    g.pair_part.push_back(split ? (int)(q & 1) : 0);
+    g.tiles.emplace_back();
+    g.caps.emplace_back();
+    g.n_px += (int64_t)mine[q].rw * mine[q].rh;
+  }
+  for (Tile tl : t) {
+    const size_t q = base + (size_t)tl.item;
+    tl.item = 0;
+    TileCaps& cp = g.caps[q];
+    cp.wp = std::max(cp.wp, std::min(tl.tu1 + c->r, c->W) - std::max(tl.tu0 - c->r, 0));
+    cp.tw = std::max(cp.tw, tl.tu1 - tl.tu0);
+    const int wm = std::min(tl.tu1 + 2 * c->r, c->W) - std::max(tl.tu0 - 2 * c->r, 0);
+    cp.ws = std::max(cp.ws, std::max(wm, cp.wp));
+    g.tiles[q].push_back(tl);
+    g.n_tiles += 1;
   }
 }
 

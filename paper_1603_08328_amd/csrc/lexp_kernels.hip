@@ -296,10 +296,13 @@ __device__ inline void a_raw(const DevParams& P, const RowTaps<NSEG>& taps, cons
 }
 
 // ... an in-place prefix along each scan row: lane (h, l) runs over columns
-// NSEG*l .. NSEG*l + NSEG-1 of row w2+h (serial prefix of the run, scan of the
-// run totals over the 32 lanes of the row, offset added) ...
+// run*l .. run*l + run-1 of row w2+h (serial prefix of the run, scan of the
+// run totals over the 32 lanes of the row, offset added).  run = ceil(wM/32)
+// is the tile's own (at most NSEG): the order of the sums, and so their
+// rounding, depends on the tile alone, not on the instance a launch picks for
+// its widest tile.  Entries past the run add +0, which changes no sum ...
 template <int NSEG>
-__device__ inline void a_prefix(float4* scanv, float* scanc, int w2, int ws_cap, int wM, int lane) {
+__device__ inline void a_prefix(float4* scanv, float* scanc, int w2, int ws_cap, int wM, int run, int lane) {
   const int h = lane >> 5, l = lane & 31;
   float4* rv = scanv + (size_t)(w2 + h) * ws_cap;
   float* rc = scanc + (size_t)(w2 + h) * ws_cap;
@@ -307,10 +310,10 @@ __device__ inline void a_prefix(float4* scanv, float* scanc, int w2, int ws_cap,
   float n[NSEG];
 #pragma unroll
   for (int i = 0; i < NSEG; ++i) {
-    const int c = l * NSEG + i;
+    const int c = l * run + i;
     v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     n[i] = 0.f;
-    if (c < wM) { v[i] = rv[c]; n[i] = rc[c]; }
+    if (i < run && c < wM) { v[i] = rv[c]; n[i] = rc[c]; }
   }
 #pragma unroll
   for (int i = 1; i < NSEG; ++i) { v[i] = f4add(v[i - 1], v[i]); n[i] = n[i - 1] + n[i]; }
@@ -321,8 +324,8 @@ __device__ inline void a_prefix(float4* scanv, float* scanc, int w2, int ws_cap,
   const float exn = half_scan(nt) - nt;
 #pragma unroll
   for (int i = 0; i < NSEG; ++i) {
-    const int c = l * NSEG + i;
-    if (c < wM) { rv[c] = f4add(v[i], ex); rc[c] = n[i] + exn; }
+    const int c = l * run + i;
+    if (i < run && c < wM) { rv[c] = f4add(v[i], ex); rc[c] = n[i] + exn; }
   }
 }
 
@@ -434,6 +437,9 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
   const int xm0 = tu0 - 2 * r > 0 ? tu0 - 2 * r : 0, xm1 = tu1 + 2 * r < W ? tu1 + 2 * r : W;
   const int ym0 = tv0 - 2 * r > 0 ? tv0 - 2 * r : 0, ym1 = tv1 + 2 * r < H ? tv1 + 2 * r : H;
   const int wM = xm1 - xm0, wP = xp1 - xp0, tw = tu1 - tu0;
+  // serial runs of the in-place row prefixes (stage A over M rows, stage E
+  // over R+ rows), from the tile's own widths
+  const int runA = (wM + 31) >> 5, runE = (wP + 31) >> 5;
   // R+ part this tile reports in MODE 1 (column / row strips own disjoint parts)
   const int own_u0 = (flags & kFirstCol) ? xp0 : tu0, own_u1 = (flags & kLastCol) ? xp1 : tu1;
   const int own_v0 = (flags & kFirstRow) ? yp0 : tv0, own_v1 = (flags & kLastRow) ? yp1 : tv1;
@@ -548,7 +554,7 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
         const int y_next = produced + nA + w2;
         if (more) load_rows2<NSEG, 0, kL1>(taps, rl, y_next, W, H, la, lb, lc, left_b, right_b);
         asm volatile("" ::: "memory");
-        a_prefix<NSEG>(scanv, scanc, w2, ws_cap, wM, lane);
+        a_prefix<NSEG>(scanv, scanc, w2, ws_cap, wM, runA, lane);
         asm volatile("" ::: "memory");
         if (more) load_rows2<NSEG, kL1, kL2>(taps, rl, y_next, W, H, la, lb, lc, left_b, right_b);
         asm volatile("" ::: "memory");
@@ -571,10 +577,10 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
             float n[NC];
 #pragma unroll
             for (int i = 0; i < NC; ++i) {
-              const int c = l * NC + i;
+              const int c = l * runE + i;
               v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
               n[i] = 0.f;
-              if (c < wP) { v[i] = cv[c]; n[i] = (float)cc[c]; }
+              if (i < runE && c < wP) { v[i] = cv[c]; n[i] = (float)cc[c]; }
             }
 #pragma unroll
             for (int i = 1; i < NC; ++i) { v[i] = f4add(v[i - 1], v[i]); n[i] = n[i - 1] + n[i]; }
@@ -585,9 +591,9 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
             const float exn = half_scan(nt) - nt;
 #pragma unroll
             for (int i = 0; i < NC; ++i) {
-              const int c = l * NC + i;
+              const int c = l * runE + i;
               // prefix counts stay below 256: an R+ row is at most kMaxWP wide
-              if (c < wP) { cv[c] = f4add(v[i], ex); cc[c] = (uint8_t)(n[i] + exn); }
+              if (i < runE && c < wP) { cv[c] = f4add(v[i], ex); cc[c] = (uint8_t)(n[i] + exn); }
             }
           }
 #pragma unroll
@@ -675,7 +681,7 @@ __global__ __launch_bounds__(1024) void k_unary(const PairDev* __restrict__ pair
       count_rows();
       if (kChunk + w2c < nA) {
         a_raw<NSEG>(P, tc, rlc, sv, sc);
-        a_prefix<NSEG>(sv, sc, w2c, ws_cap, wM, lane);
+        a_prefix<NSEG>(sv, sc, w2c, ws_cap, wM, runA, lane);
         a_wsum<NC>(sv, sc, w2c, nA - kChunk - w2c, ws_cap, wP, xp0, xm0, r, W, produced + kChunk + w2c, lo_c, sb1,
                    ring, ring1v, ring1c, wp_cap, lane);
       }

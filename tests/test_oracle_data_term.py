@@ -11,6 +11,18 @@ import pytest
 from oracle import Oracle
 from _util import base_params, texture
 
+# The C library's fmaf (correctly rounded single-precision fused multiply-add),
+# used only to reproduce the FP32 position the contract forms.
+import ctypes as _C
+import ctypes.util as _CU
+_libm = _C.CDLL(_CU.find_library("m"))
+_libm.fmaf.restype = _C.c_float
+_libm.fmaf.argtypes = [_C.c_float, _C.c_float, _C.c_float]
+
+
+def _FMA(p, q, s):
+    return _libm.fmaf(float(p), float(q), float(s))
+
 
 def _u(h, w):
     return np.broadcast_to(np.arange(w, dtype=np.float64)[None, :], (h, w))
@@ -217,3 +229,109 @@ def test_coefficients_match_whole_image_definition(rng):
         b = y.mean() - a @ X.mean(0)
         got = ab[kv - 1, ku - 2]
         assert np.allclose(got[:3], a, atol=1e-8) and got[3] == pytest.approx(b, abs=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# The warp of Eq. (8) in single precision (the position that selects the
+# interpolation taps and the in-view test is formed in FP32 on both sides)
+# against the same warp in FP64.
+# ---------------------------------------------------------------------------
+def _ulp32(x):
+    """Spacing of float32 at |x| (rounded up to the next binade edge)."""
+    a = np.abs(np.asarray(x, np.float64)) * (1.0 + 2.0 ** -20) + 1e-30
+    return 2.0 ** (np.floor(np.log2(a)) - 23.0)
+
+
+def _rho_fp64_warp(o, left, right, f, alpha=0.9, tau_col=10.0, tau_grad=2.0):
+    """Eqs. (8), (9) with x = u - (a u + b v + c) in FP64 from the FP32 label:
+    the raw cost per pixel, the taps' floor, the in-view flag and the local
+    slope |d rho / d x| bound at the taps."""
+    h, w = left.shape[:2]
+    gl, gr = o.grads()
+    a, b, c = (float(t) for t in np.asarray(f, np.float32))
+    v, u = np.mgrid[0:h, 0:w].astype(np.float64)
+    x = u - (a * u + b * v + c)
+    inview = (x >= 0.0) & (x <= w - 1)
+    xc = np.where(inview, x, 0.0)
+    i0 = np.floor(xc).astype(np.int64)
+    t = xc - i0
+    i1 = np.minimum(i0 + 1, w - 1)
+    t = np.where(i0 >= w - 1, 0.0, t)
+    rows = v.astype(np.int64)
+    R0, R1 = right[rows, i0].astype(np.float64), right[rows, i1].astype(np.float64)
+    J = (1.0 - t)[..., None] * R0 + t[..., None] * R1
+    col = np.abs(left.astype(np.float64) - J).sum(-1)
+    K = (1.0 - t) * gr[rows, i0] + t * gr[rows, i1]
+    grd = np.abs(gl - K)
+    rho = (1.0 - alpha) * np.minimum(col, tau_col) + alpha * np.minimum(grd, tau_grad)
+    rho = np.where(inview, rho, (1.0 - alpha) * tau_col + alpha * tau_grad)
+    slope = (1.0 - alpha) * np.abs(R1 - R0).sum(-1) + alpha * np.abs(gr[rows, i1] - gr[rows, i0])
+    # error of the FP32 contract: the inner and the outer fused multiply-add
+    # and the subtraction each round once to float32
+    eps = 0.5 * (_ulp32(b * v + c) + _ulp32(a * u + b * v + c) + _ulp32(x)) + 1e-12
+    return rho, x, inview, i0, slope, eps
+
+
+def test_fp32_warp_contract_against_fp64_warp(rng):
+    """The oracle forms the sample position in FP32 (the same contract as the
+    device).  Against the warp in FP64: wherever the in-view test and the taps
+    agree, rho differs by at most the local slope times the FP32 rounding of
+    the position; wherever they disagree, the FP64 position lies within that
+    rounding of an integer, of 0 or of W-1.  The change this makes to phi is
+    bounded through the direct weights of Eq. (7)."""
+    h, w, r = 12, 450, 5
+    left, right = texture(rng, h, w), texture(rng, h, w)
+    o = Oracle(base_params(w, h, r, disp_max=60.0), left, right)
+    labels = [rng.uniform([-0.3, -0.3, 0.0], [0.3, 0.3, 60.0]) for _ in range(12)]
+    labels += [rng.uniform([-3.0, -3.0, -100.0], [3.0, 3.0, 100.0]) for _ in range(6)]
+    # fronto-parallel labels one ulp away from an integer shift (positions a
+    # rounding away from the taps' edges) and labels whose warp ends near the
+    # image's last column
+    for k in (3.0, 17.0, 41.0):
+        labels += [[0.0, 0.0, np.nextafter(np.float32(k), np.float32(0))],
+                   [0.0, 0.0, np.nextafter(np.float32(k), np.float32(100))]]
+    labels += [[1.0 - 2.0 ** -12, 0.0, -(w - 1) * 2.0 ** -12], [2.0 ** -13, 1e-4, 0.0]]
+    n_diff = n_all = 0
+    worst_rel = 0.0
+    dphi_max = 0.0
+    for f in labels:
+        f = np.asarray(f, np.float32)
+        rho32 = o.rho_map(f)
+        rho64, x64, in64, i0_64, slope, eps = _rho_fp64_warp(o, left, right, f)
+        # the oracle's own decision at each pixel, recovered from its rho: a
+        # sample it takes in view costs what FP64 computes at the taps floor(x32)
+        a, b, c = (np.float32(t) for t in f)
+        fmaf = np.frompyfunc(lambda p, q, s: float(np.float32(_FMA(np.float32(p), np.float32(q), np.float32(s)))),
+                             3, 1)
+        v, u = np.mgrid[0:h, 0:w].astype(np.float32)
+        d32 = fmaf(a, u, fmaf(b, v, c)).astype(np.float32)
+        x32 = (u - d32).astype(np.float32).astype(np.float64)
+        assert np.all(np.abs(x32 - x64) <= eps), "FP32 position beyond its rounding bound"
+        in32 = (x32 >= 0.0) & (x32 <= w - 1)
+        i0_32 = np.floor(np.where(in32, x32, 0.0))
+        agree = (in32 == in64) & (~in64 | (i0_32 == i0_64))
+        n_all += agree.size
+        n_diff += int((~agree).sum())
+        # same decisions: rho differs by the slope times the position's rounding
+        err = np.abs(rho32 - rho64)
+        assert np.all(err[agree] <= slope[agree] * np.abs(x32 - x64)[agree] + 1e-9)
+        worst_rel = max(worst_rel, float(np.max(np.abs(x32 - x64) / np.maximum(eps, 1e-30))))
+        # different decisions: only within the rounding of an edge
+        dist = np.minimum(np.abs(x64 - np.round(x64)), np.minimum(np.abs(x64), np.abs(x64 - (w - 1))))
+        assert np.all(dist[~agree] <= eps[~agree]), "a decision differs away from a tap or image edge"
+        # phi at sampled pixels: |phi32 - phi64| <= sum_s |w_ps| |rho32 - rho64|
+        for pu, pv in [(5, 3), (200, 6), (w - 3, 9), (37, 0)]:
+            wts = o.gf_weights(pu, pv)
+            s0u, s0v = pu - 2 * r, pv - 2 * r
+            vs, us = np.mgrid[0:wts.shape[0], 0:wts.shape[1]]
+            su, sv = us + s0u, vs + s0v
+            ok = (su >= 0) & (su < w) & (sv >= 0) & (sv < h)
+            d32p = float(np.sum(wts[ok] * rho32[sv[ok], su[ok]]))
+            d64p = float(np.sum(wts[ok] * rho64[sv[ok], su[ok]]))
+            bound = float(np.sum(np.abs(wts[ok]) * err[sv[ok], su[ok]]))
+            assert abs(d32p - d64p) <= bound + 1e-12
+            assert d32p == pytest.approx(o.unary_direct(pu, pv, f), abs=1e-10)
+            dphi_max = max(dphi_max, abs(d32p - d64p))
+    assert n_diff > 0, "no sample near a tap edge: the classification above was never exercised"
+    print(f"\nFP32 warp vs FP64: {n_diff} of {n_all} samples decided differently (all within rounding of an "
+          f"edge); largest |x32 - x64| / bound {worst_rel:.2f}; largest |phi32 - phi64| {dphi_max:.2e}")

@@ -330,3 +330,32 @@ def test_plain_method_tiny_energy_decreases_and_counts(tiny_oracle, tiny_pair):
     assert np.allclose(costs, o.pixel_costs(labels), atol=1e-10)
     e_check = o.energy(labels, costs)[0]
     assert e_check == pytest.approx(energy[-1], rel=1e-12)
+
+
+def test_expand_step_equals_one_by_one_and_returns_phi(tiny_oracle):
+    # One step of a group in parallel (Lemma 3) equals the same expansions one
+    # by one in reverse order, and the phi it returns is the region's data
+    # term of Eq. (6) as unary_region computes it.
+    o = tiny_oracle
+    seed, cell = 5, 5
+    lab = o.init_labels(seed)
+    cost = o.pixel_costs(lab)
+    for group in (0, 6, 15):
+        gi, gj = group % 4, group // 4
+        cells = [(i, j) for j in range(gj, 10, 4) for i in range(gi, 13, 4)]
+        rects = [((i - 1) * cell, (j - 1) * cell, (i + 2) * cell, (j + 2) * cell) for i, j in cells]
+        alphas = np.array([o.propose(lab, seed, 0, 0, cell, i, j, 1, 1, 8.0, 1.0) for i, j in cells], np.float32)
+        la, ca = lab.copy(), cost.copy()
+        de, nc, phi = o.expand_step(la, ca, rects, alphas, want_phi=True)
+        lb, cb = lab.copy(), cost.copy()
+        for q in reversed(range(len(rects))):
+            d1, n1 = o.expand(lb, cb, rects[q], alphas[q])
+            assert d1 == de[q] and n1 == nc[q]
+        assert np.array_equal(la, lb) and np.array_equal(ca, cb)
+        at = 0
+        for rc, a in zip(rects, alphas):
+            ref = o.unary_region(rc, a).reshape(-1)
+            assert np.array_equal(phi[at:at + len(ref)], ref)
+            at += len(ref)
+        assert at == len(phi)
+        assert nc.sum() > 0 and np.all(de <= 0)
