@@ -220,6 +220,21 @@ lexp_status lexp_pairwise(lexp_ctx* ctx, int32_t pu, int32_t pv, int32_t qu, int
 lexp_status lexp_energy(lexp_ctx* ctx, const float* labels, const float* cur_cost, double* total,
                         double* unary, double* pairwise, void* hip_stream);
 
+/* lexp_energy for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, the same values bit for bit (the same per-block partial sums,
+ * added in the same order), and no allocation of any kind.  The partial sums
+ * and totals live in a fixed device array of the library, one per GPU, held
+ * from the first lexp_create on that GPU until the process ends (about
+ * 128 KB).  Images of at most LEXP_NOALLOC_MAX_PIXELS pixels (LEXP_EINVAL
+ * beyond, before any work).  Every call on one GPU uses that GPU's array and
+ * leaves its contents there, so calls that overlap on one GPU (other streams
+ * or host threads) race; nothing in the array needs to start at zero.
+ * Synchronises hip_stream. */
+#define LEXP_NOALLOC_MAX_PIXELS 2097152
+lexp_status lexp_energy_noalloc(lexp_ctx* ctx, const float* labels, const float* cur_cost, double* total,
+                                double* unary, double* pairwise, void* hip_stream);
+
 /* Random initialisation of Alg. 2 (plane through (p, z0), z0 ~ U[0, disp_max],
  * normal uniform on the upper hemisphere) from a counter-based generator
  * keyed by (seed, pixel).  labels: device HxWx4. */

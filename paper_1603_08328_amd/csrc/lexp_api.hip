@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <sched.h>
 #include <string>
 #include <thread>
@@ -45,6 +46,34 @@ lexp_status fail(lexp_status s, const char* fmt, ...) {
     hipError_t e_ = (expr);                                                              \
     if (e_ != hipSuccess) return fail(LEXP_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
+
+// Device scratch of lexp_energy_noalloc (for callers that cannot allocate):
+// k_energy's partial sums, two doubles per block of 256 pixels, then the two
+// totals.  Every GPU the library runs on holds its own copy until the process
+// ends.  In host code the array's name is not a device address: host code
+// uses the address hipGetSymbolAddress gives for the current device, looked
+// up once per device (at lexp_create) and kept in g_scratch_addr.
+constexpr int kNoAllocBlocks = LEXP_NOALLOC_MAX_PIXELS / 256;
+static __device__ __align__(256) double scratch[2 * kNoAllocBlocks + 2];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up the
+// first time a context is created on that device (with the device current).
+lexp_status scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(LEXP_EDEVICE, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LEXP_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_addr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return LEXP_OK;
+}
 
 // grow-only device buffer
 template <class T>
@@ -89,6 +118,7 @@ struct PinBuf {
 };
 
 constexpr int kMaxTileRows = 128;  // bounds the length of the running sums
+
 
 struct TileCaps {
   int wp = 1, tw = 1, ws = 1;
@@ -169,6 +199,7 @@ struct lexp_ctx {
   size_t res_items = 0;  // status slots in the result buffers
   lexp_net* net = nullptr;  // learned proposals for lexp_optimize (not owned)
   hipStream_t capture_stream = nullptr;  // graph mode: work is captured here, replayed on the caller's stream
+  double* noalloc_scratch = nullptr;     // this context's device's copy of `scratch`
 };
 
 // The learned proposal network (five 3x3 convolutions, channels 16 -> 32 ->
@@ -783,6 +814,10 @@ lexp_status lexp_create(const lexp_params* params, const float* left_hwc, const 
   d.lam = p.lambda; d.tau_dis = p.tau_dis; d.w_floor = p.w_floor;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
+  {
+    const lexp_status st = scratch_address(dev, &c->noalloc_scratch);
+    if (st != LEXP_OK) return st;
+  }
   int lds = 0;
   HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   c->lds_limit = (size_t)std::max(lds, 16384);
@@ -1001,6 +1036,32 @@ lexp_status lexp_energy(lexp_ctx* c, const float* labels, const float* cur_cost,
                         double* pairwise, void* hip_stream) {
   if (!c || !labels || !cur_cost) return fail(LEXP_EINVAL, "null argument");
   return energy_impl(c, labels, cur_cost, total, unary, pairwise, (hipStream_t)hip_stream);
+}
+
+lexp_status lexp_energy_noalloc(lexp_ctx* c, const float* labels, const float* cur_cost, double* total,
+                                double* unary, double* pairwise, void* hip_stream) {
+  if (!c || !labels || !cur_cost) return fail(LEXP_EINVAL, "null argument");
+  const int64_t n = (int64_t)c->W * c->H;
+  if (n > LEXP_NOALLOC_MAX_PIXELS)
+    return fail(LEXP_EINVAL, "image of %lld pixels: the no-allocation energy holds at most %d", (long long)n,
+                LEXP_NOALLOC_MAX_PIXELS);
+  if (!c->noalloc_scratch) return fail(LEXP_ESTATE, "no scratch address for the context's device");
+  const int nb = (int)((n + 255) / 256);
+  hipStream_t s = (hipStream_t)hip_stream;
+  double* partial = c->noalloc_scratch;
+  double* totals = partial + 2 * kNoAllocBlocks;
+  // every partial read is written first, and so are the totals: nothing needs clearing
+  hipLaunchKernelGGL(lexp::k_energy, dim3(nb), dim3(256), 0, s, c->dp, (const float4*)labels, cur_cost, c->wts,
+                     partial);
+  hipLaunchKernelGGL(lexp::k_energy_total, dim3(1), dim3(256), 0, s, (const double*)partial, nb, totals);
+  HIP_TRY(hipGetLastError());
+  double host[2] = {0.0, 0.0};
+  HIP_TRY(hipMemcpyAsync(host, totals, sizeof(host), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (total) *total = host[0] + host[1];
+  if (unary) *unary = host[0];
+  if (pairwise) *pairwise = host[1];
+  return LEXP_OK;
 }
 
 lexp_status lexp_view_labels(lexp_ctx* c, const float* labels_in, float* labels_out, void* hip_stream) {

@@ -100,6 +100,7 @@ __global__ void k_graph_terms(const PairDev* pairs, const Item* items, const flo
 __global__ void k_apply(const PairDev* pairs, const Item* items, const uint8_t* x, const float* phi_alpha);
 __global__ void k_energy(DevParams P, const float4* labels, const float* cur_cost, const double* wts,
                          double* partial);
+__global__ void k_energy_total(const double* partial, int n_blocks, double* out);
 struct FullLayout;
 struct CompactLayout;
 template <class Layout, int BLOCK>

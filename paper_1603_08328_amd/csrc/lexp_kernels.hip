@@ -1059,6 +1059,30 @@ __global__ void k_energy(DevParams P, const float4* __restrict__ labels, const f
   }
 }
 
+// Totals of k_energy's per-block partial sums, added in block order (the
+// order in which the host adds them for lexp_energy, so the sums are the same
+// bit for bit): out[0] the unary part, out[1] the pairwise part.  One
+// workgroup of 256 threads stages runs of partials in LDS; thread 0 adds them.
+__global__ void k_energy_total(const double* __restrict__ partial, int n_blocks, double* __restrict__ out) {
+  __shared__ double run[2 * 1024];
+  double eu = 0.0, ep = 0.0;
+  for (int b0 = 0; b0 < n_blocks; b0 += 1024) {
+    const int nb = n_blocks - b0 < 1024 ? n_blocks - b0 : 1024;
+    for (int i = threadIdx.x; i < 2 * nb; i += blockDim.x) run[i] = partial[(size_t)2 * b0 + i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int b = 0; b < nb; ++b) {
+        eu += run[2 * b];
+        ep += run[2 * b + 1];
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = eu;
+    out[1] = ep;
+  }
+}
+
 // One smoothness term through the device path (inspection).
 __global__ void k_pair1(DevParams P, const double* __restrict__ wts, int pu, int pv, int qu, int qv, float4 fp,
                         float4 fq, double* out) {

@@ -82,6 +82,7 @@ _SIGS = {
     "lexp_graph_terms": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "lexp_pairwise": (_i32, [_vp, _i32, _i32, _i32, _i32, lexp_plane, lexp_plane, C.POINTER(_f64)]),
     "lexp_energy": (_i32, [_vp, _vp, _vp, C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64), _vp]),
+    "lexp_energy_noalloc": (_i32, [_vp, _vp, _vp, C.POINTER(_f64), C.POINTER(_f64), C.POINTER(_f64), _vp]),
     "lexp_init_labels": (_i32, [_vp, _u64, _vp, _vp]),
     "lexp_optimize": (_i32, [_vp, C.POINTER(lexp_schedule), _u64, _vp, _vp, _vp, _vp, _vp]),
     "lexp_view_labels": (_i32, [_vp, _vp, _vp, _vp]),
@@ -310,6 +311,18 @@ def lexp_energy(ctx, labels, cur_cost, stream=None):
     t, u, p = C.c_double(), C.c_double(), C.c_double()
     _check(load_library().lexp_energy(ctx.handle, lp, cp, C.byref(t), C.byref(u), C.byref(p),
                                       _stream_ptr(stream)))
+    return t.value, u.value, p.value
+
+
+def lexp_energy_noalloc(ctx, labels, cur_cost, stream=None):
+    """lexp_energy without allocation (the library's fixed per-GPU array).
+    Returns (total, unary, pairwise)."""
+    torch = _torch()
+    lp = _dev(labels, torch.float32, (ctx.height, ctx.width, 4), name="labels")
+    cp = _dev(cur_cost, torch.float32, (ctx.height, ctx.width), name="cur_cost")
+    t, u, p = C.c_double(), C.c_double(), C.c_double()
+    _check(load_library().lexp_energy_noalloc(ctx.handle, lp, cp, C.byref(t), C.byref(u), C.byref(p),
+                                              _stream_ptr(stream)))
     return t.value, u.value, p.value
 
 
