@@ -991,6 +991,30 @@ void ora_propose(const ora_ctx* c, const float* labels, uint64_t seed, int itera
   (void)H; (void)cc;
 }
 
+/* Candidate of one step with learned proposals (a proposer of alpha_ij, which
+ * Alg. 1 leaves open): a refinement step whose refinement index (step - k_prop
+ * - k_rans) is odd takes planes[r], the plane a network proposes at the pixel
+ * r the step draws (draw 0 of the step's key, as above); every other step is
+ * ora_propose's.  planes: H*W*3 floats (a, b, c) or NULL (no learned steps). */
+void ora_propose_learned(const ora_ctx* c, const float* labels, const float* planes, uint64_t seed,
+                         int iteration, int level, int cell, int ci, int cj, int step, int k_prop, int k_rans,
+                         double r_d, double r_n, float* alpha) {
+  int first = k_prop + k_rans;
+  if (planes && step >= first && ((step - first) % 2) == 1) {
+    int W = c->W, H = c->H;
+    int cu0 = ci * cell, cv0 = cj * cell;
+    int cw = imin(cu0 + cell, W) - cu0, ch = imin(cv0 + cell, H) - cv0;
+    uint64_t f[7] = {TAG_PROP, (uint64_t)iteration, (uint64_t)level, (uint64_t)ci, (uint64_t)cj, (uint64_t)step, 0};
+    int64_t npx = (int64_t)cw * ch;
+    int64_t idx = (int64_t)(u01(key_chain(seed, f, 7)) * (double)npx);
+    if (idx >= npx) idx = npx - 1;
+    int ru = cu0 + (int)(idx % cw), rv = cv0 + (int)(idx / cw);
+    memcpy(alpha, planes + ((size_t)rv * W + ru) * 3, sizeof(float) * 3);
+    return;
+  }
+  ora_propose(c, labels, seed, iteration, level, cell, ci, cj, step, k_prop, k_rans, r_d, r_n, alpha);
+}
+
 /* ---------------------------------------------------------------------------
  * Optimisation procedure (Alg. 2 with Alg. 1 per cell).  Grid level h has
  * cells of `cells[h]` pixels; cell (i, j) (i = column index, j = row index)

@@ -76,6 +76,8 @@ def lib():
     L.ora_init_labels.argtypes = [vp, C.c_uint64, f32]
     L.ora_propose.argtypes = [vp, f32, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                               C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, f32]
+    L.ora_propose_learned.argtypes = [vp, f32, vp, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                      C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, f32]
     L.ora_run_group.restype = C.c_int64
     L.ora_run_group.argtypes = [vp, f32, f64, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int,
                                 C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_int64)]
@@ -296,6 +298,31 @@ class Oracle:
         self._L.ora_propose(self.ctx, np.ascontiguousarray(labels, dtype=np.float32), C.c_uint64(seed),
                             iteration, level, cell, ci, cj, step, k_prop, k_rans, float(r_d), float(r_n), out)
         return out
+
+    def propose_learned(self, labels, planes, seed, iteration, level, cell, ci, cj, step, k_prop, r_d, r_n,
+                        k_rans=0):
+        """Candidate with learned proposals: refinement steps with an odd
+        refinement index take planes[r] (planes: HxWx3 float32, the plane a
+        network proposes at each pixel; None: no learned step)."""
+        out = np.zeros(3, dtype=np.float32)
+        pl = None if planes is None else np.ascontiguousarray(planes, dtype=np.float32)
+        assert pl is None or pl.shape == (self.H, self.W, 3)
+        self._L.ora_propose_learned(self.ctx, np.ascontiguousarray(labels, dtype=np.float32),
+                                    None if pl is None else pl.ctypes.data, C.c_uint64(seed), iteration, level,
+                                    cell, ci, cj, step, k_prop, k_rans, float(r_d), float(r_n), out)
+        return out
+
+    def planes_from_net_output(self, y):
+        """Planes of the proposal network's output (HxWx16; channels 0-2 are
+        a, b and d / disp_max at the pixel): the plane with slopes (a, b)
+        through disparity d at (u, v), c = d - a u - b v, in FP64 from the FP32
+        outputs, rounded once to FP32."""
+        y = np.asarray(y, dtype=np.float32)
+        v, u = np.mgrid[0:self.H, 0:self.W].astype(np.float64)
+        a = y[..., 0].astype(np.float64)
+        b = y[..., 1].astype(np.float64)
+        c = (y[..., 2].astype(np.float64) * float(self.p["disp_max"]) - a * u) - b * v
+        return np.stack([a, b, c], axis=-1).astype(np.float32)
 
     def run_group(self, labels, costs, seed, iteration, level, cell, k_prop, k_rand, r_d, r_n, group, k_rans=0):
         de = C.c_int64(0)

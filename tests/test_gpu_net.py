@@ -147,3 +147,50 @@ def test_optimize_with_learned_proposals(setup):
     with pytest.raises(L.LexpError):
         L.lexp_set_net(ctx, None)
         L.lexp_optimize(ctx, [(5, 1, 3)], 1, 0, labs[0], costs[0], learned=True)
+
+
+def test_optimize_learned_equals_oracle_driven_by_the_networks_output(setup):
+    """lexp_optimize with learned proposals against Alg. 2 run by the oracle
+    with the same proposer rule (odd refinement steps from the second
+    iteration on take the network's plane at the step's pixel).  The oracle is
+    given the device network's output on the oracle's own labels at the start
+    of each level pass: that output is an input of the proposer, like its
+    random numbers (the network itself is checked against its CPU reference
+    above).  Labels bit-identical, energy to 1e-5."""
+    from oracle import Oracle
+    pair, prm, ctx, _, net, _, _ = setup
+    ora = Oracle(prm, pair.left, pair.right)
+    L.lexp_set_net(ctx, net)
+    H, W = 48, 64
+    seed, grids, iters = 0, [(5, 1, 3)], 3
+    labs = torch.zeros((H, W, 4), device="cuda")
+    cost = torch.zeros((H, W), device="cuda")
+    e, _ = L.lexp_optimize(ctx, grids, iters, seed, labs, cost, learned=True)
+    olab = ora.init_labels(seed)
+    ocost = ora.pixel_costs(olab)
+    r_d, r_n = prm["disp_max"] / 2.0, 1.0
+    n_learned = 0
+    for it in range(iters):
+        for h, (cell, kp, kr) in enumerate(grids):
+            planes = None
+            if it >= 1:
+                l4 = np.zeros((H, W, 4), np.float32)
+                l4[..., :3] = olab
+                y = L.lexp_net_forward(net, ctx, _cuda(l4))
+                planes = ora.planes_from_net_output(y.cpu().numpy())
+            nci, ncj = -(-W // cell), -(-H // cell)
+            for k in range(16):
+                cells = [(i, j) for j in range(k // 4, ncj, 4) for i in range(k % 4, nci, 4)]
+                rects = [((i - 1) * cell, (j - 1) * cell, (i + 2) * cell, (j + 2) * cell) for i, j in cells]
+                for step in range(kp + kr):
+                    alphas = [ora.propose_learned(olab, planes, seed, it, h, cell, i, j, step, kp, r_d, r_n)
+                              for i, j in cells]
+                    if planes is not None and step >= kp and (step - kp) % 2 == 1:
+                        n_learned += len(cells)
+                    ora.expand_step(olab, ocost, rects, alphas)
+        r_d *= 0.5
+        r_n *= 0.5
+    g3 = labs.cpu().numpy()[..., :3]
+    assert n_learned > 0
+    assert np.array_equal(g3.view(np.uint32), olab.view(np.uint32)), f"{np.any(g3 != olab, axis=-1).sum()} differ"
+    assert ora.energy(olab, ocost)[0] == pytest.approx(e[-1], rel=1e-5)

@@ -100,3 +100,46 @@ def test_first_adam_step_moves_by_lr_times_sign():
     for (w0, b0), (w1, b1), (gw, gb) in zip(before, ps, grads):
         assert torch.allclose(w1 - w0, -1e-3 * gw / (gw.abs() + 1e-8), atol=1e-12)
         assert torch.allclose(b1 - b0, -1e-3 * gb / (gb.abs() + 1e-8), atol=1e-12)
+
+
+def test_learned_step_takes_the_plane_at_the_steps_own_pixel(tiny_oracle):
+    """Every pixel carries its own fronto-parallel label, so a label names its
+    pixel.  With zero perturbation sizes a refinement step returns f_r of its
+    drawn pixel r (the perturbation round-trips); a learned refinement step
+    (odd refinement index) returns planes[r] of the same pixel; every other
+    step is the plain proposer's."""
+    o = tiny_oracle
+    H, W = o.H, o.W
+    lab = np.zeros((H, W, 3), np.float32)
+    lab[..., 2] = np.arange(H * W, dtype=np.float32).reshape(H, W)
+    planes = np.zeros((H, W, 3), np.float32)
+    planes[..., 0] = 1.0
+    planes[..., 2] = lab[..., 2] + 0.5
+    for (ci, cj) in [(0, 0), (3, 2), (12, 9)]:
+        for step in range(6):
+            plain = o.propose(lab, 3, 1, 0, 5, ci, cj, step, 1, 0.0, 0.0)
+            learned = o.propose_learned(lab, planes, 3, 1, 0, 5, ci, cj, step, 1, 0.0, 0.0)
+            assert np.array_equal(o.propose_learned(lab, None, 3, 1, 0, 5, ci, cj, step, 1, 0.0, 0.0), plain)
+            px = int(plain[2])
+            u, v = px % W, px // W
+            assert ci * 5 <= u < ci * 5 + 5 and cj * 5 <= v < cj * 5 + 5
+            if step >= 1 and (step - 1) % 2 == 1:
+                assert np.array_equal(learned, planes[v, u])
+            else:
+                assert np.array_equal(learned, plain)
+
+
+def test_planes_from_net_output_pass_through_the_predicted_disparity(tiny_oracle):
+    o = tiny_oracle
+    rng = np.random.default_rng(3)
+    y = np.zeros((o.H, o.W, 16), np.float32)
+    y[..., 0] = rng.uniform(-0.5, 0.5, (o.H, o.W))
+    y[..., 1] = rng.uniform(-0.5, 0.5, (o.H, o.W))
+    y[..., 2] = rng.uniform(0.0, 1.0, (o.H, o.W))
+    pl = o.planes_from_net_output(y)
+    v, u = np.mgrid[0:o.H, 0:o.W]
+    d = pl[..., 0].astype(np.float64) * u + pl[..., 1].astype(np.float64) * v + pl[..., 2].astype(np.float64)
+    d_pred = y[..., 2].astype(np.float64) * o.p["disp_max"]
+    # c is rounded once to FP32 (|c| < 64 here)
+    assert np.all(np.abs(d - d_pred) <= 2.0 ** -24 * 64)
+    assert np.array_equal(pl[..., :2], y[..., :2])
