@@ -481,6 +481,9 @@ def main():
         "host_enqueue_ms_per_step": g["stats"]["host_enqueue_ms"],
         "host_update_ms_per_step": g["stats"]["host_update_ms"],
         "host_cut_level_ms_per_step": [round(x, 2) for x in g["stats"]["host_cut_level_ms"]],
+        "host_solve_cpu_level_ms_per_step": [round(x, 2) for x in g["stats"]["host_solve_level_ms"]],
+        "host_solves_per_step": list(g["stats"]["host_solves"]),
+        "device_cut_fallbacks_per_step": g["stats"]["device_cut_fallbacks"],
         "device_cut_share": [round(x, 3) for x in g["stats"]["device_cut_share"]],
         "device_cut_shape": [[b, e] for b, e in zip(g["stats"]["device_cut_block"], g["stats"]["device_cut_relabel"])],
     }

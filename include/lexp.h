@@ -145,6 +145,9 @@ typedef struct {
   int64_t unary_timed_launches; /* fused-kernel launches timed (every N-th, see lexp_set_timing) */
   double unary_timed_alg_bytes; /* their algorithmic bytes */
   int64_t unary_timed_evals;    /* their phi_p evaluations */
+  double host_solve_level_ms[4];/* lexp_optimize: host max-flow time per level summed over regions (CPU time of
+                                   the solves, all threads; against host_cut_level_ms: the pool's efficiency) */
+  int64_t host_solves[4];       /* lexp_optimize: regions cut on the host, per level */
 } lexp_stats;
 
 /* Creates a context for one stereo pair and runs the label-independent set-up

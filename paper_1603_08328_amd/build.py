@@ -35,27 +35,29 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, csrc: str = CSRC, out: str = LIB) -> str:
+    """Compiles the sources in `csrc` into the shared library `out` (default:
+    the package's sources and its in-tree library)."""
     hipcc = _hipcc()
     tmp = tempfile.mkdtemp(prefix="lexp_build_")
     try:
         host_obj = os.path.join(tmp, "lexp_host.o")
         _run(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-              "-I", INCLUDE, "-c", os.path.join(CSRC, "lexp_host.cpp"), "-o", host_obj], verbose)
+              "-I", INCLUDE, "-c", os.path.join(csrc, "lexp_host.cpp"), "-o", host_obj], verbose)
         objs = [host_obj]
         for src in ("lexp_kernels.hip", "lexp_cut.hip", "lexp_post.hip", "lexp_net.hip", "lexp_api.hip"):
             obj = os.path.join(tmp, src.replace(".hip", ".o"))
             _run([hipcc, "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
                   "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                  "-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", CSRC,
-                  "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+                  "-Wall", "-Wno-unused-result", "-I", INCLUDE, "-I", csrc,
+                  "-c", os.path.join(csrc, src), "-o", obj], verbose)
             objs.append(obj)
-        out_tmp = LIB + ".tmp"
+        out_tmp = out + ".tmp"
         _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp] + objs + ["-lpthread"], verbose)
-        os.replace(out_tmp, LIB)
+        os.replace(out_tmp, out)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
-    return LIB
+    return out
 
 
 if __name__ == "__main__":

@@ -1404,12 +1404,18 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
     if (!host_cut.empty()) HIP_TRY(hipStreamSynchronize(s));
     c->stats.device_cut_fallbacks += (int64_t)host_cut.size();
   }
+  // per-worker CPU time of the solves (summed into the statistics below)
+  double solve_ms[lexp::kMaxPoolThreads] = {};
+  int64_t solves[lexp::kMaxPoolThreads] = {};
   auto host_solve = [&](int i, int worker) {
+    const auto s0 = std::chrono::steady_clock::now();
     const Item& it = P.items[i];
     const int* t = terms + (size_t)it.aux_off * 5;
     lexp::BKSolver& bk = *c->solvers[worker];
     bk.load<int32_t>(it.rw, it.rh, nf, t, 5, t + 1, 5);
     bk.solve(xs + it.aux_off);
+    solve_ms[worker] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - s0).count();
+    solves[worker] += 1;
   };
   if (dev && !host_cut.empty())
     pool.parallel_for((int)host_cut.size(), [&](int q, int worker) { host_solve(host_cut[q], worker); });
@@ -1445,6 +1451,10 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
   c->stats.host_wait_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
   c->stats.host_cut_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
   c->stats.host_cut_level_ms[a.level] += std::chrono::duration<double, std::milli>(t2 - t1).count();
+  for (int w = 0; w < pool.size(); ++w) {
+    c->stats.host_solve_level_ms[a.level] += solve_ms[w];
+    c->stats.host_solves[a.level] += solves[w];
+  }
   c->stats.host_update_ms += std::chrono::duration<double, std::milli>(t3 - t2).count();
   return LEXP_OK;
 }

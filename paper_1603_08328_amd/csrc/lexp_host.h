@@ -78,6 +78,8 @@ class BKSolver {
 };
 
 // ---- thread pool -----------------------------------------------------------
+constexpr int kMaxPoolThreads = 64;  // threads of one pool (the caller is worker 0)
+
 class ThreadPool {
  public:
   explicit ThreadPool(int n_threads);

@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblexp.so")
+# the in-tree build; LEXP_LIBRARY names another build of the same library (comparisons of builds)
+LIB_PATH = os.environ.get("LEXP_LIBRARY") or os.path.join(_HERE, "liblexp.so")
 
 LEXP_OK, LEXP_EINVAL, LEXP_ENOMEM, LEXP_EDEVICE, LEXP_ESTATE = 0, -1, -2, -3, -4
 LEXP_QUANTUM = 2.0 ** -20
@@ -58,7 +59,8 @@ class lexp_stats(C.Structure):
                 ("device_cut_share", C.c_double * 4), ("graphs_captured", C.c_int64),
                 ("device_cut_block", C.c_int32 * 4), ("device_cut_relabel", C.c_int32 * 4),
                 ("unary_timed_launches", C.c_int64), ("unary_timed_alg_bytes", C.c_double),
-                ("unary_timed_evals", C.c_int64)]
+                ("unary_timed_evals", C.c_int64), ("host_solve_level_ms", C.c_double * 4),
+                ("host_solves", C.c_int64 * 4)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -66,6 +68,8 @@ class lexp_stats(C.Structure):
         d["device_cut_share"] = list(d["device_cut_share"])
         d["device_cut_block"] = list(d["device_cut_block"])
         d["device_cut_relabel"] = list(d["device_cut_relabel"])
+        d["host_solve_level_ms"] = list(d["host_solve_level_ms"])
+        d["host_solves"] = list(d["host_solves"])
         return d
 
 
