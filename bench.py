@@ -296,6 +296,68 @@ def run_graph_compare(steps: int, seed: int = 0):
     return out
 
 
+def run_batch_cycle(name: str, steps: int, n_pairs: int = 0, seed: int = 0):
+    """The plain method against the batch cycle (every candidate of a group
+    step from the labels at its start, one fused launch per group step for all
+    regions and candidates): energy against wall time, and the time each needs
+    to reach the plain method's final energy (exactly, and within 0.5%).  With
+    n_pairs > 0: that many pairs of the many-pair recipe batched in one run
+    (energies summed over the pairs)."""
+    import torch
+
+    import paper_1603_08328_amd.lexp as L
+    from synth import PAPER_PARAMS, make_pair, make_workload_pair, params_for, workload
+    from synth.workloads import many_pair_scenes
+
+    wl = workload(name)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    if n_pairs:
+        scenes = []
+        for sc in many_pair_scenes(n_pairs):
+            pr = make_pair(**sc)
+            prm = dict(PAPER_PARAMS, width=sc["width"], height=sc["height"], disp_max=sc["disp_max"], gf_radius=20)
+            scenes.append((prm, pr))
+    else:
+        scenes = [(params_for(name), make_workload_pair(name))]
+    ctxs = [L.lexp_create(p, torch.from_numpy(pr.left).to(dev), torch.from_numpy(pr.right).to(dev), stream)
+            for p, pr in scenes]
+    labs = [torch.zeros((p["height"], p["width"], 4), device=dev) for p, _ in scenes]
+    costs = [torch.zeros((p["height"], p["width"]), device=dev) for p, _ in scenes]
+    out = {}
+    for mode in ("plain", "batch_cycle", "plain", "batch_cycle")[: 2 * max(steps, 1)]:
+        L.lexp_set_timing(ctxs[0], 1)
+        L.lexp_reset_stats(ctxs[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        es, ts = L.lexp_optimize_batch(ctxs, wl["grids"], wl["iterations"], [seed + i for i in range(len(ctxs))],
+                                       labs, costs, stream, batch_cycle=(mode == "batch_cycle"))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = L.lexp_get_stats(ctxs[0])
+        e = np.sum(es, axis=0)
+        rec = dict(wall_s=wall, energy=[float(x) for x in e], time_s=[float(x) for x in ts],
+                   unary_launches=st["unary_launches"], unary_kernel_ms=st["unary_kernel_ms"],
+                   unary_alg_bytes=st["unary_alg_bytes"],
+                   frac_hbm=(st["unary_alg_bytes"] / (st["unary_kernel_ms"] / 1e3) / 1e9 / HBM_PEAK_GBPS)
+                   if st["unary_kernel_ms"] > 0 else None)
+        if mode not in out or wall < out[mode]["wall_s"]:
+            out[mode] = rec
+    for c in ctxs:
+        c.close()
+    target = out["plain"]["energy"][-1]
+    for rec in out.values():
+        def first(limit):
+            for e, t in zip(rec["energy"], rec["time_s"]):
+                if e <= limit:
+                    return t
+            return None
+        rec["time_to_plain_final_s"] = first(target)
+        rec["time_to_within_0.5pct_s"] = first(target * 1.005)
+    return dict(workload=(f"{n_pairs} pairs of the many-pair recipe" if n_pairs else name),
+                iterations=wl["iterations"], plain_final_energy=target, **out)
+
+
 def run_cpu_baseline():
     """The oracle on a bounded sample of the same workload: initial per-pixel
     costs of the regions of every cell of eight groups (group offsets
@@ -395,6 +457,9 @@ def main():
     ap.add_argument("--eval-pairs", type=int, default=4)
     ap.add_argument("--graph-compare", action="store_true",
                     help="instead: whole runs with eager launches and with HIP-graph replay of each part step")
+    ap.add_argument("--batch-cycle", action="store_true",
+                    help="instead: the plain method against the batch cycle, energy against time (with "
+                         "--many-pairs N: N pairs batched)")
     ap.add_argument("--k-rans", type=int, default=0,
                     help="RANSAC proposer steps per cell and level (Alg. 1; 0 in the workload as specified)")
     args = ap.parse_args()
@@ -413,6 +478,9 @@ def main():
     if args.both_views:
         print(json.dumps({"workload": "450x375 synthetic pair, both views and post-processing",
                           "both_views": run_both_views()}), flush=True)
+        return
+    if args.batch_cycle:
+        print(json.dumps({"batch_cycle": run_batch_cycle(args.workload, args.steps, args.many_pairs)}), flush=True)
         return
     if args.many_pairs:
         m = run_many_pairs(args.many_pairs, args.iterations, loop=not args.no_loop)

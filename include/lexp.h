@@ -119,6 +119,20 @@ typedef struct {
                       the chosen pixel, computed from the labels at the start of each
                       level pass (the first iteration starts from random labels,
                       unlike anything the network is trained on); 0: none */
+  int32_t batch_cycle; /* 1: the "batch cycle" of Alg. 1 (Sec. 3.4): every candidate of a
+                          cell's Alg. 1 is drawn from the labels at the start of its group
+                          step, the costs of all regions of the group for all their
+                          candidates are evaluated in one launch, then the moves are
+                          applied in Alg. 1's order, each an exact expansion on the
+                          current labels; 0: each candidate from the latest labels (the
+                          method as the paper runs it).  The graph option is not used
+                          in this mode. */
+  int32_t tile_cols[4]; /* fused cost kernel, per level: widest column strip of a region's
+                           tiles (0: the widest the kernel's LDS allows) */
+  int32_t tile_fill[4]; /* per level: tiles a group step's launch is filled to with row
+                           strips (0: 256).  Both decide the tiles, and so the rounding of
+                           the costs; a committed table of tuned values keeps labels
+                           independent of any run's timing. */
 } lexp_schedule;
 
 /* Counters of the hot kernel, accumulated while timing is enabled. */

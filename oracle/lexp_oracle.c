@@ -1025,9 +1025,23 @@ void ora_propose_learned(const ora_ctx* c, const float* labels, const float* pla
 
 /* Runs Alg. 1 for every cell of group k of one grid level.  Returns the number
  * of cost evaluations (sum of |R| over the expansions). */
+int64_t ora_run_group_ex(const ora_ctx* c, float* labels, double* costs, uint64_t seed, int iteration, int level,
+                         int cell, int k_prop, int k_rans, int k_rand, double r_d, double r_n, int group,
+                         int batch_cycle, int64_t* dEq);
+
 int64_t ora_run_group(const ora_ctx* c, float* labels, double* costs, uint64_t seed, int iteration, int level,
                       int cell, int k_prop, int k_rans, int k_rand, double r_d, double r_n, int group,
                       int64_t* dEq) {
+  return ora_run_group_ex(c, labels, costs, seed, iteration, level, cell, k_prop, k_rans, k_rand, r_d, r_n, group, 0,
+                          dEq);
+}
+
+/* As ora_run_group; with batch_cycle != 0 every candidate of a cell's Alg. 1
+ * is drawn from the labels as they stand before the cell's first move (the
+ * "batch cycle" of Sec. 3.4), then the moves are made in Alg. 1's order. */
+int64_t ora_run_group_ex(const ora_ctx* c, float* labels, double* costs, uint64_t seed, int iteration, int level,
+                         int cell, int k_prop, int k_rans, int k_rand, double r_d, double r_n, int group,
+                         int batch_cycle, int64_t* dEq) {
   int W = c->W, H = c->H;
   int nci = (W + cell - 1) / cell, ncj = (H + cell - 1) / cell;
   int gi = group % 4, gj = group / 4;
@@ -1041,12 +1055,19 @@ int64_t ora_run_group(const ora_ctx* c, float* labels, double* costs, uint64_t s
     int u0 = (ci - 1) * cell, v0 = (cj - 1) * cell;
     int u1 = (ci + 2) * cell, v1 = (cj + 2) * cell;
     rect_t R = clip_dilate(c, u0, v0, u1, v1, 0);
-    for (int t = 0; t < k_prop + k_rans + k_rand; ++t) {
+    int K = k_prop + k_rans + k_rand;
+    float* batch = batch_cycle ? (float*)malloc(sizeof(float) * 3 * (size_t)(K > 0 ? K : 1)) : NULL;
+    if (batch)
+      for (int t = 0; t < K; ++t)
+        ora_propose(c, labels, seed, iteration, level, cell, ci, cj, t, k_prop, k_rans, r_d, r_n, batch + 3 * t);
+    for (int t = 0; t < K; ++t) {
       float alpha[3];
-      ora_propose(c, labels, seed, iteration, level, cell, ci, cj, t, k_prop, k_rans, r_d, r_n, alpha);
+      if (batch) memcpy(alpha, batch + 3 * t, sizeof(alpha));
+      else ora_propose(c, labels, seed, iteration, level, cell, ci, cj, t, k_prop, k_rans, r_d, r_n, alpha);
       de += ora_expand(c, labels, costs, R.u0, R.v0, R.u1, R.v1, alpha, 0, NULL);
       evals += (int64_t)(R.u1 - R.u0) * (R.v1 - R.v0);
     }
+    free(batch);
   }
   (void)H;
   if (dEq) *dEq += de;
@@ -1057,9 +1078,20 @@ int64_t ora_run_group(const ora_ctx* c, float* labels, double* costs, uint64_t s
  * NULL) receives iterations+1 values: after initialisation and after each
  * iteration.  Returns the number of cost evaluations including the per-pixel
  * initial costs. */
+int64_t ora_optimize_ex(const ora_ctx* c, uint64_t seed, int n_levels, const int* cells, const int* k_prop,
+                        const int* k_rans, const int* k_rand, int iterations, int batch_cycle, float* labels,
+                        double* costs, double* energy);
+
 int64_t ora_optimize(const ora_ctx* c, uint64_t seed, int n_levels, const int* cells, const int* k_prop,
                      const int* k_rans, const int* k_rand, int iterations, float* labels, double* costs,
                      double* energy) {
+  return ora_optimize_ex(c, seed, n_levels, cells, k_prop, k_rans, k_rand, iterations, 0, labels, costs, energy);
+}
+
+/* As ora_optimize, with the batch cycle of ora_run_group_ex as an option. */
+int64_t ora_optimize_ex(const ora_ctx* c, uint64_t seed, int n_levels, const int* cells, const int* k_prop,
+                        const int* k_rans, const int* k_rand, int iterations, int batch_cycle, float* labels,
+                        double* costs, double* energy) {
   ora_init_labels(c, seed, labels);
   ora_pixel_costs(c, labels, NULL, costs);
   int64_t evals = (int64_t)c->W * c->H;
@@ -1068,8 +1100,8 @@ int64_t ora_optimize(const ora_ctx* c, uint64_t seed, int n_levels, const int* c
   for (int it = 0; it < iterations; ++it) {
     for (int h = 0; h < n_levels; ++h)
       for (int k = 0; k < 16; ++k)
-        evals += ora_run_group(c, labels, costs, seed, it, h, cells[h], k_prop[h], k_rans[h], k_rand[h], r_d, r_n, k,
-                               NULL);
+        evals += ora_run_group_ex(c, labels, costs, seed, it, h, cells[h], k_prop[h], k_rans[h], k_rand[h], r_d,
+                                  r_n, k, batch_cycle, NULL);
     r_d *= 0.5;
     r_n *= 0.5;
     if (energy) energy[it + 1] = ora_energy(c, labels, costs, NULL, NULL);

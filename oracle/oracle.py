@@ -84,6 +84,12 @@ def lib():
     L.ora_optimize.restype = C.c_int64
     L.ora_optimize.argtypes = [vp, C.c_uint64, C.c_int, _P(np.int32), _P(np.int32), _P(np.int32),
                                _P(np.int32), C.c_int, f32, f64, vp]
+    L.ora_run_group_ex.restype = C.c_int64
+    L.ora_run_group_ex.argtypes = [vp, f32, f64, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int,
+                                   C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int64)]
+    L.ora_optimize_ex.restype = C.c_int64
+    L.ora_optimize_ex.argtypes = [vp, C.c_uint64, C.c_int, _P(np.int32), _P(np.int32), _P(np.int32),
+                                  _P(np.int32), C.c_int, C.c_int, f32, f64, vp]
     L.ora_postprocess.restype = None
     L.ora_postprocess.argtypes = [vp, f32, f32, f64, _P(np.uint8)]
     L.ora_num_threads.restype = C.c_int
@@ -324,14 +330,18 @@ class Oracle:
         c = (y[..., 2].astype(np.float64) * float(self.p["disp_max"]) - a * u) - b * v
         return np.stack([a, b, c], axis=-1).astype(np.float32)
 
-    def run_group(self, labels, costs, seed, iteration, level, cell, k_prop, k_rand, r_d, r_n, group, k_rans=0):
+    def run_group(self, labels, costs, seed, iteration, level, cell, k_prop, k_rand, r_d, r_n, group, k_rans=0,
+                  batch_cycle=False):
         de = C.c_int64(0)
-        ev = self._L.ora_run_group(self.ctx, labels, costs, C.c_uint64(seed), iteration, level, cell,
-                                   k_prop, k_rans, k_rand, float(r_d), float(r_n), group, C.byref(de))
+        ev = self._L.ora_run_group_ex(self.ctx, labels, costs, C.c_uint64(seed), iteration, level, cell,
+                                      k_prop, k_rans, k_rand, float(r_d), float(r_n), group,
+                                      1 if batch_cycle else 0, C.byref(de))
         return ev, de.value
 
-    def optimize(self, seed, grids, iterations):
-        """grids: (cell, K_prop, K_rand) or (cell, K_prop, K_rand, K_RANS) per level."""
+    def optimize(self, seed, grids, iterations, batch_cycle=False):
+        """grids: (cell, K_prop, K_rand) or (cell, K_prop, K_rand, K_RANS) per level.
+        batch_cycle: every candidate of a cell's Alg. 1 from the labels before
+        the cell's first move (Sec. 3.4's batch cycle)."""
         n = len(grids)
         cells = np.array([g[0] for g in grids], dtype=np.int32)
         kp = np.array([g[1] for g in grids], dtype=np.int32)
@@ -340,8 +350,8 @@ class Oracle:
         labels = np.zeros((self.H, self.W, 3), dtype=np.float32)
         costs = np.zeros((self.H, self.W))
         energy = np.zeros(iterations + 1)
-        ev = self._L.ora_optimize(self.ctx, C.c_uint64(seed), n, cells, kp, ks, kr, iterations, labels, costs,
-                                  energy.ctypes.data)
+        ev = self._L.ora_optimize_ex(self.ctx, C.c_uint64(seed), n, cells, kp, ks, kr, iterations,
+                                     1 if batch_cycle else 0, labels, costs, energy.ctypes.data)
         return labels, costs, energy, ev
 
     @classmethod

@@ -197,6 +197,12 @@ struct lexp_ctx {
     int cut_block = 0, cut_every = 0;  // shape of that launch
   } part[2];
   size_t res_items = 0;  // status slots in the result buffers
+  // batch cycle: one launch per group step for every region and candidate
+  DevBuf<Item> d_bitems;
+  DevBuf<Tile> d_btiles;
+  DevBuf<float> d_bphi;
+  PinBuf<Item> h_bitems;
+  PinBuf<Tile> h_btiles;
   lexp_net* net = nullptr;  // learned proposals for lexp_optimize (not owned)
   hipStream_t capture_stream = nullptr;  // graph mode: work is captured here, replayed on the caller's stream
   double* noalloc_scratch = nullptr;     // this context's device's copy of `scratch`
@@ -285,11 +291,20 @@ int max_tile_width(int r, size_t budget) {
 // its own vertical margin.
 constexpr int kFillTiles = 256;
 
-// Column strips of a region rw wide: the fewest strips of width <= tw_lim,
-// or up to two more when narrower strips need fewer 32-column segments per
-// M row (the raw-cost stage's work per row grows with those segments).
-int column_strips(const lexp_ctx* c, int rw) {
-  const int n0 = (rw + c->tw_lim - 1) / c->tw_lim;
+// A tile plan: the widest column strip (at most the kernel's LDS limit
+// tw_lim) and the tiles a launch is filled to with row strips.
+struct TilePlan {
+  int cols = 0;  // 0: tw_lim
+  int fill = kFillTiles;
+};
+
+// Column strips of a region rw wide: the fewest strips of width <= the
+// plan's widest (and tw_lim), or up to two more when narrower strips need
+// fewer 32-column segments per M row (the raw-cost stage's work per row grows
+// with those segments).
+int column_strips(const lexp_ctx* c, int rw, const TilePlan& plan) {
+  const int lim = plan.cols > 0 ? std::min(plan.cols, c->tw_lim) : c->tw_lim;
+  const int n0 = (rw + lim - 1) / lim;
   auto segs = [&](int n) { return ((rw + n - 1) / n + 4 * c->r + 31) / 32; };
   int best = n0;
   for (int n = n0 + 1; n <= n0 + 2 && n <= rw; ++n)
@@ -298,17 +313,18 @@ int column_strips(const lexp_ctx* c, int rw) {
 }
 constexpr int kMinStripRows = 16;
 
-void plan_tiles(const lexp_ctx* c, const Item* items, int n, std::vector<Tile>& tiles, TileCaps& caps) {
+void plan_tiles(const lexp_ctx* c, const Item* items, int n, std::vector<Tile>& tiles, TileCaps& caps,
+                const TilePlan& plan = TilePlan{}) {
   tiles.clear();
   caps = TileCaps{};
   int64_t col_tiles = 0;
   for (int i = 0; i < n; ++i)
-    if (items[i].rw > 0 && items[i].rh > 0) col_tiles += column_strips(c, items[i].rw);
-  const int fill = col_tiles > 0 ? (int)std::max<int64_t>(1, kFillTiles / col_tiles) : 1;
+    if (items[i].rw > 0 && items[i].rh > 0) col_tiles += column_strips(c, items[i].rw, plan);
+  const int fill = col_tiles > 0 ? (int)std::max<int64_t>(1, plan.fill / col_tiles) : 1;
   for (int i = 0; i < n; ++i) {
     const Item& it = items[i];
     if (it.rw <= 0 || it.rh <= 0) continue;
-    const int ncs = column_strips(c, it.rw);
+    const int ncs = column_strips(c, it.rw, plan);
     const int nrs = std::max((it.rh + kMaxTileRows - 1) / kMaxTileRows,
                              std::min((it.rh + kMinStripRows - 1) / kMinStripRows, fill));
     for (int rs = 0; rs < nrs; ++rs) {
@@ -887,6 +903,7 @@ lexp_status lexp_destroy(lexp_ctx* c) {
   c->d_post.release();
   c->h_items.release(); c->h_tiles.release(); c->h_terms.release(); c->h_x.release(); c->h_flag.release();
   c->h_partial.release(); c->h_labels4.release();
+  c->d_bitems.release(); c->d_btiles.release(); c->d_bphi.release(); c->h_bitems.release(); c->h_btiles.release();
   for (auto& b : c->part) {
     b.d_items.release(); b.d_phi.release(); b.d_terms.release(); b.d_x.release(); b.d_res.release();
     b.h_items.release(); b.h_terms.release(); b.h_x.release(); b.h_res.release();
@@ -1188,6 +1205,8 @@ struct Part {
   int pair_hint = -1;       // the pair of every item, if they share one
   int direct = 0;           // tile i is the only tile of item i
   hipGraphExec_t graph = nullptr;  // captured device sequence of one step of this part (graph mode)
+  float* phi_ext = nullptr;  // batch cycle: the group's costs, evaluated for every step at once (items'
+                             // out_off index it); nullptr: this part's own buffer, evaluated per step
 };
 
 // Per grid level: picks the device max-flow's launch shape by timing each
@@ -1272,15 +1291,22 @@ struct StepArgs {
   RunPair* pairs;
 };
 
-// Alg. 1 candidate of region q of a part for a step, into its item.
-void propose_item(Part& P, const StepArgs& a, int q, int step) {
-  Item& item = P.items[q];
+// Alg. 1 candidate of region q of a part for a step, from its pair's host
+// label mirror as it stands.
+void propose_plane(const Part& P, const StepArgs& a, int q, int step, float al[3]) {
+  const Item& item = P.items[q];
   const RunPair& rp = a.pairs[item.pair];
   const lexp_ctx* c = rp.c;
-  float al[3];
   lexp::propose(c->W, c->H, rp.mirror.data(), 3, rp.seed, a.it, a.level, a.cell, P.ci[q], P.cj[q], step, a.kp,
                 a.kr, c->prm.disp_max / 2.0 * a.scale, a.scale, al,
                 rp.net_planes.empty() ? nullptr : rp.net_planes.data());
+}
+
+// Alg. 1 candidate of region q of a part for a step, into its item.
+void propose_item(Part& P, const StepArgs& a, int q, int step) {
+  float al[3];
+  propose_plane(P, a, q, step, al);
+  Item& item = P.items[q];
   item.a = al[0];
   item.b = al[1];
   item.c = al[2];
@@ -1293,13 +1319,17 @@ lexp_status part_device_work(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const P
                              CutTuner* tuner, hipStream_t s) {
   const int n = (int)P.items.size();
   HIP_TRY(hipMemcpyAsync(B.d_items.p, B.h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
-  lexp_status st = launch_unary<0>(c, d_pairs, B.d_items.p, d_tiles + P.tile_off, (int)P.n_tiles, P.caps, nullptr,
-                                   B.d_phi.p, s, P.bytes, P.n_px, n, P.pair_hint, P.direct);
-  if (st) return st;
+  lexp_status st = LEXP_OK;
+  const float* phi = P.phi_ext ? P.phi_ext : B.d_phi.p;
+  if (!P.phi_ext) {
+    st = launch_unary<0>(c, d_pairs, B.d_items.p, d_tiles + P.tile_off, (int)P.n_tiles, P.caps, nullptr, B.d_phi.p,
+                         s, P.bytes, P.n_px, n, P.pair_hint, P.direct);
+    if (st) return st;
+  }
   if (P.device_cut) {
     int* flag = reinterpret_cast<int*>(B.d_res.p);
     hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, d_pairs, B.d_items.p,
-                       B.d_phi.p, B.d_terms.p + 1, flag);
+                       phi, B.d_terms.p + 1, flag);
     HIP_TRY(hipGetLastError());
     bool timed = false;
     const CutShape shape = tuner ? tuner->pick(c, P.max_px, &timed) : CutShape{};
@@ -1314,7 +1344,7 @@ lexp_status part_device_work(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const P
     HIP_TRY(hipMemcpyAsync(B.h_res.p, B.d_res.p, 4 + 4 * c->res_items + (size_t)P.n_px, hipMemcpyDeviceToHost, s));
   } else {
     hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, d_pairs, B.d_items.p,
-                       B.d_phi.p, B.d_terms.p + 1, B.d_terms.p);
+                       phi, B.d_terms.p + 1, B.d_terms.p);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(B.h_terms.p, B.d_terms.p, sizeof(int) * (1 + 5 * P.n_px), hipMemcpyDeviceToHost, s));
   }
@@ -1444,7 +1474,7 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
     }
   }
   hipLaunchKernelGGL(lexp::k_apply, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, d_pairs, B.d_items.p, d_xs,
-                     B.d_phi.p);
+                     P.phi_ext ? P.phi_ext : B.d_phi.p);
   HIP_TRY(hipGetLastError());
   const auto t3 = std::chrono::steady_clock::now();
   c->stats.expand_calls += 1;
@@ -1486,7 +1516,7 @@ struct GroupPlan {
 // pair, the level and the group only: not on the host threads, not on which
 // part of the run's group step it is put in, not on other pairs batched with
 // it.
-void plan_pair_group(const lexp_ctx* c, int pair, int cell, int k, GroupPlan& g) {
+void plan_pair_group(const lexp_ctx* c, int pair, int cell, int k, const TilePlan& plan, GroupPlan& g) {
   const int nci = (c->W + cell - 1) / cell, ncj = (c->H + cell - 1) / cell;
   std::vector<std::pair<int, int>> cells;
   for (int j = k / 4; j < ncj; j += 4)
@@ -1510,7 +1540,7 @@ void plan_pair_group(const lexp_ctx* c, int pair, int cell, int k, GroupPlan& g)
   }
   std::vector<Tile> t;
   TileCaps unused;
-  plan_tiles(c, mine.data(), (int)mine.size(), t, unused);
+  plan_tiles(c, mine.data(), (int)mine.size(), t, unused, plan);
   const size_t base = g.items.size();
   for (size_t q = 0; q < mine.size(); ++q) {
     g.items.push_back(mine[q]);
@@ -1615,14 +1645,90 @@ void assign_parts(const RunPair* pairs, const GroupPlan& g, double share, Part* 
   P[0].device_cut = share >= 0 && !P[0].items.empty();
 }
 
+// Batch cycle of one group step: the candidates of every step of every
+// region are drawn from the labels at the group's start (cand, per part:
+// region-major, 3 floats per step), and one fused-cost launch evaluates all
+// of them.  Each region keeps its own tiles, so a cost has the rounding it
+// has in a step-by-step run.  Costs of step t, part hp, region q go to
+// d_bphi at t * G + base_hp + (the region's compact offset), G being the
+// group's pixels and base_1 the pixels of part 0.
+lexp_status batch_costs(lexp_ctx* c, RunPair* pairs, Part* const* P, const StepArgs& a, int K,
+                        const PairDev* d_pairs, hipStream_t s) {
+  if (K <= 0) return LEXP_OK;
+  const int64_t G = P[0]->n_px + P[1]->n_px;
+  size_t n_items = 0, n_tiles = 0;
+  for (int hp = 0; hp < 2; ++hp) {
+    n_items += P[hp]->items.size();
+    n_tiles += P[hp]->n_tiles;
+  }
+  if (n_items == 0) return LEXP_OK;
+  HIP_TRY(c->h_bitems.ensure(n_items * K));
+  HIP_TRY(c->h_btiles.ensure(n_tiles * K));
+  HIP_TRY(c->d_bitems.ensure(n_items * K));
+  HIP_TRY(c->d_btiles.ensure(n_tiles * K));
+  HIP_TRY(c->d_bphi.ensure((size_t)G * K));
+  // the staging buffers were last read by the previous group step's launch,
+  // which the host has waited for through that step's parts
+  Item* bi = c->h_bitems.p;
+  Tile* bt = c->h_btiles.p;
+  size_t ii = 0, ti = 0;
+  TileCaps caps;
+  double bytes = 0.0;
+  int hint = -2;
+  for (int hp = 0; hp < 2; ++hp) {
+    Part& Q = *P[hp];
+    const int64_t base = hp == 0 ? 0 : P[0]->n_px;
+    caps.wp = std::max(caps.wp, Q.caps.wp);
+    caps.tw = std::max(caps.tw, Q.caps.tw);
+    caps.ws = std::max(caps.ws, Q.caps.ws);
+    for (const Item& it : Q.items) hint = hint == -2 ? it.pair : (hint == it.pair ? hint : -1);
+    const size_t first = ii;
+    pool_of(c).parallel_for((int)Q.items.size(), [&](int q, int) {
+      for (int t = 0; t < K; ++t) {
+        Item it = Q.items[q];
+        float al[3];
+        propose_plane(Q, a, q, t, al);
+        it.a = al[0];
+        it.b = al[1];
+        it.c = al[2];
+        it.out_off = (long long)t * G + base + Q.items[q].aux_off;
+        bi[first + (size_t)t * Q.items.size() + q] = it;
+      }
+    });
+    for (int t = 0; t < K; ++t)
+      for (size_t j = 0; j < Q.n_tiles; ++j) {
+        Tile tl = c->h_tiles.p[Q.tile_off + j];
+        tl.item += (int)(first + (size_t)t * Q.items.size());
+        bt[ti++] = tl;
+      }
+    ii += Q.items.size() * K;
+    bytes += Q.bytes * K;
+  }
+  HIP_TRY(hipMemcpyAsync(c->d_bitems.p, bi, sizeof(Item) * ii, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->d_btiles.p, bt, sizeof(Tile) * ti, hipMemcpyHostToDevice, s));
+  return launch_unary<0>(c, d_pairs, c->d_bitems.p, c->d_btiles.p, (int)ti, caps, nullptr, c->d_bphi.p, s, bytes,
+                         G * K, (int64_t)ii, hint >= 0 ? hint : -1, 0);
+}
+
+// Items of a part for step t of a batch cycle (the part's items start at
+// `first` in the group's batch table): the candidates drawn at the group's
+// start, their costs' offsets in d_bphi.
+void batch_step_items(const lexp_ctx* c, Part& Q, size_t first, int t) {
+  const size_t n = Q.items.size();
+  for (size_t q = 0; q < n; ++q) Q.items[q] = c->h_bitems.p[first + (size_t)t * n + q];
+  Q.phi_ext = c->d_bphi.p;
+}
+
 // Alg. 2 for the pairs of a run, with one set of launches per group step for
 // all pairs (the scratch, host pool and statistics of pairs[0]'s context).
 lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, double* time_trace, hipStream_t s) {
   if (sch->n_levels < 1 || sch->n_levels > 4 || sch->iterations < 0) return fail(LEXP_EINVAL, "bad schedule");
   for (int h = 0; h < sch->n_levels; ++h)
     if (sch->cell[h] < 1 || sch->k_prop[h] < 0 || sch->k_rand[h] < 0 || sch->k_rans[h] < 0 ||
-        sch->k_prop[h] + sch->k_rans[h] + sch->k_rand[h] > 64)
+        sch->k_prop[h] + sch->k_rans[h] + sch->k_rand[h] > 64 || sch->tile_cols[h] < 0 ||
+        sch->tile_cols[h] > lexp::kMaxTW || sch->tile_fill[h] < 0 || sch->tile_fill[h] > (1 << 20))
       return fail(LEXP_EINVAL, "bad grid level %d", h);
+  if (sch->batch_cycle != 0 && sch->batch_cycle != 1) return fail(LEXP_EINVAL, "batch_cycle must be 0 or 1");
   lexp_ctx* c = pairs[0].c;
   if (sch->learned != 0 && sch->learned != 1) return fail(LEXP_EINVAL, "learned must be 0 or 1");
   if (sch->learned)
@@ -1646,7 +1752,7 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
   // every iteration; otherwise both are cut on the host.
   const bool dev_cut = c->prm.device_cut != 0;
   // kernel timing events are not captured, so a timed run launches eagerly
-  const bool use_graph = c->prm.graph != 0 && !c->timing;
+  const bool use_graph = c->prm.graph != 0 && !c->timing && !sch->batch_cycle;
   std::vector<GroupPlan> groups((size_t)sch->n_levels * 16);
   std::vector<Part> parts((size_t)sch->n_levels * 16 * 2);
   struct GraphGuard {  // frees the captured graphs on every way out
@@ -1663,7 +1769,10 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
   for (int h = 0; h < sch->n_levels; ++h)
     for (int k = 0; k < 16; ++k) {
       GroupPlan& g = groups[(size_t)h * 16 + k];
-      for (int p = 0; p < np; ++p) plan_pair_group(pairs[p].c, p, sch->cell[h], k, g);
+      TilePlan plan;
+      plan.cols = sch->tile_cols[h];
+      if (sch->tile_fill[h] > 0) plan.fill = sch->tile_fill[h];
+      for (int p = 0; p < np; ++p) plan_pair_group(pairs[p].c, p, sch->cell[h], k, plan, g);
       sort_group(g);
       g.tile_off = n_tiles;
       n_tiles += g.n_tiles;
@@ -1750,22 +1859,32 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
         const auto g0 = std::chrono::steady_clock::now();
         if ((st = split_group(h, k))) return st;
         Part* P[2] = {&parts[((size_t)h * 16 + k) * 2], &parts[((size_t)h * 16 + k) * 2 + 1]};
+        if (sch->batch_cycle) {
+          if ((st = batch_costs(c, pairs, P, a, K, d_pairs, s))) return st;
+          for (int hp = 0; hp < 2; ++hp) batch_step_items(c, *P[hp], hp == 0 ? 0 : P[0]->items.size() * K, 0);
+        }
         // Alg. 1 for every cell of the group.  The cells are independent
         // (Lemma 3), so the two parts run staggered: while the host cuts
         // one part, the device evaluates the other part's next candidate.
         for (int hp = 0; hp < 2; ++hp)
           if (!P[hp]->items.empty() && K > 0) {
             Part& Q = *P[hp];
-            pool_of(c).parallel_for((int)Q.items.size(), [&](int q, int) { propose_item(Q, a, q, 0); });
+            if (!sch->batch_cycle)
+              pool_of(c).parallel_for((int)Q.items.size(), [&](int q, int) { propose_item(Q, a, q, 0); });
             if ((st = enqueue_part(c, Q, c->part[hp], d_pairs, c->d_tiles.p, use_graph, &tuners[h], s))) return st;
           }
         for (int step = 0; step < K; ++step)
           for (int hp = 0; hp < 2; ++hp) {
             if (P[hp]->items.empty()) continue;
             const int next = step + 1 < K ? step + 1 : -1;
-            if ((st = finish_part(c, *P[hp], c->part[hp], a, next, d_pairs, &tuners[h], s))) return st;
-            if (next >= 0)
+            // (batch cycle: the candidates were drawn at the group's start)
+            if ((st = finish_part(c, *P[hp], c->part[hp], a, sch->batch_cycle ? -1 : next, d_pairs, &tuners[h], s)))
+              return st;
+            if (next >= 0) {
+              if (sch->batch_cycle)
+                batch_step_items(c, *P[hp], hp == 0 ? 0 : P[0]->items.size() * K, next);
               if ((st = enqueue_part(c, *P[hp], c->part[hp], d_pairs, c->d_tiles.p, use_graph, &tuners[h], s))) return st;
+            }
           }
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - g0).count();
         balance[h].update(ms / (double)std::max<int64_t>(1, groups[(size_t)h * 16 + k].n_px));

@@ -47,7 +47,8 @@ class lexp_rect(C.Structure):
 class lexp_schedule(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("cell", C.c_int32 * 4), ("k_prop", C.c_int32 * 4),
                 ("k_rand", C.c_int32 * 4), ("iterations", C.c_int32), ("k_rans", C.c_int32 * 4),
-                ("learned", C.c_int32)]
+                ("learned", C.c_int32), ("batch_cycle", C.c_int32), ("tile_cols", C.c_int32 * 4),
+                ("tile_fill", C.c_int32 * 4)]
 
 
 class lexp_stats(C.Structure):
@@ -336,25 +337,34 @@ def lexp_init_labels(ctx, seed, labels, stream=None):
     _check(load_library().lexp_init_labels(ctx.handle, C.c_uint64(seed), lp, _stream_ptr(stream)))
 
 
-def make_schedule(grids, iterations, learned=False) -> lexp_schedule:
+def make_schedule(grids, iterations, learned=False, batch_cycle=False, tiles=None) -> lexp_schedule:
+    """grids: (cell, K_prop, K_rand) or (cell, K_prop, K_rand, K_RANS) per level;
+    tiles: None or one (widest column strip, fill) per level (0: default)."""
     s = lexp_schedule()
     if not 1 <= len(grids) <= 4:
         raise ValueError("1 to 4 grid levels")
     s.n_levels = len(grids)
-    for i, g in enumerate(grids):  # (cell, K_prop, K_rand) or (cell, K_prop, K_rand, K_RANS)
+    for i, g in enumerate(grids):
         s.cell[i], s.k_prop[i], s.k_rand[i] = int(g[0]), int(g[1]), int(g[2])
         s.k_rans[i] = int(g[3]) if len(g) > 3 else 0
     s.iterations = int(iterations)
     s.learned = 1 if learned else 0
+    s.batch_cycle = 1 if batch_cycle else 0
+    if tiles is not None:
+        if len(tiles) != len(grids):
+            raise ValueError("one tile plan per grid level")
+        for i, (cols, fill) in enumerate(tiles):
+            s.tile_cols[i], s.tile_fill[i] = int(cols), int(fill)
     return s
 
 
-def lexp_optimize(ctx, grids, iterations, seed, labels, cur_cost, stream=None, learned=False):
+def lexp_optimize(ctx, grids, iterations, seed, labels, cur_cost, stream=None, learned=False, batch_cycle=False,
+                  tiles=None):
     """Alg. 2 on the device + host; returns (energy_trace, time_trace)."""
     torch = _torch()
     lp = _dev(labels, torch.float32, (ctx.height, ctx.width, 4), name="labels")
     cp = _dev(cur_cost, torch.float32, (ctx.height, ctx.width), name="cur_cost")
-    sch = make_schedule(grids, iterations, learned)
+    sch = make_schedule(grids, iterations, learned, batch_cycle, tiles)
     e = np.zeros(iterations + 1)
     t = np.zeros(iterations + 1)
     _check(load_library().lexp_optimize(ctx.handle, C.byref(sch), C.c_uint64(seed), lp, cp, e.ctypes.data,
@@ -362,7 +372,8 @@ def lexp_optimize(ctx, grids, iterations, seed, labels, cur_cost, stream=None, l
     return e, t
 
 
-def lexp_optimize_batch(ctxs, grids, iterations, seeds, labels, cur_costs, stream=None, learned=False):
+def lexp_optimize_batch(ctxs, grids, iterations, seeds, labels, cur_costs, stream=None, learned=False,
+                        batch_cycle=False, tiles=None):
     """Alg. 2 for several pairs at once (one launch per group step for all of
     them); returns (energy traces [n_pairs, iterations+1], time_trace)."""
     torch = _torch()
@@ -375,7 +386,7 @@ def lexp_optimize_batch(ctxs, grids, iterations, seeds, labels, cur_costs, strea
     cp = (C.c_void_p * n)(*[_dev(q, torch.float32, (c.height, c.width), name="cur_cost")
                             for c, q in zip(ctxs, cur_costs)])
     sd = (C.c_uint64 * n)(*[int(x) for x in seeds])
-    sch = make_schedule(grids, iterations, learned)
+    sch = make_schedule(grids, iterations, learned, batch_cycle, tiles)
     e = np.zeros((n, iterations + 1))
     ep = (C.c_void_p * n)(*[e[i].ctypes.data for i in range(n)])
     t = np.zeros(iterations + 1)

@@ -359,3 +359,34 @@ def test_expand_step_equals_one_by_one_and_returns_phi(tiny_oracle):
             at += len(ref)
         assert at == len(phi)
         assert nc.sum() > 0 and np.all(de <= 0)
+
+
+def test_batch_cycle_draws_every_candidate_before_the_cells_first_move(tiny_oracle):
+    # With one candidate per cell the batch cycle is the plain method; with
+    # more, its candidates are those the proposer draws from the labels at the
+    # group's start (each move still exact: the energy never rises), so it
+    # differs from the plain method, whose later candidates see earlier moves.
+    o = tiny_oracle
+    l1, c1, e1, _ = o.optimize(4, [(5, 1, 0)], 2)
+    l2, c2, e2, _ = o.optimize(4, [(5, 1, 0)], 2, batch_cycle=True)
+    assert np.array_equal(l1, l2) and np.array_equal(e1, e2)
+    lb, cb, eb, _ = o.optimize(4, [(5, 1, 3)], 2, batch_cycle=True)
+    lp, cp, ep, _ = o.optimize(4, [(5, 1, 3)], 2)
+    assert np.all(np.diff(eb) < 0) and not np.array_equal(lb, lp)
+    assert np.allclose(cb, o.pixel_costs(lb), atol=1e-10)
+    # group 0 by hand: candidates from the start labels, moves in order
+    lab = o.init_labels(4)
+    cost = o.pixel_costs(lab)
+    la, ca = lab.copy(), cost.copy()
+    o.run_group(la, ca, 4, 0, 0, 5, 1, 3, 8.0, 1.0, 0)  # plain, for contrast
+    lbat, cbat = lab.copy(), cost.copy()
+    cells = [(i, j) for j in range(0, 10, 4) for i in range(0, 13, 4)]
+    cand = {q: [o.propose(lab, 4, 0, 0, 5, i, j, t, 1, 8.0, 1.0) for t in range(4)] for q, (i, j) in enumerate(cells)}
+    for q, (i, j) in enumerate(cells):
+        rect = ((i - 1) * 5, (j - 1) * 5, (i + 2) * 5, (j + 2) * 5)
+        for t in range(4):
+            o.expand(lbat, cbat, rect, cand[q][t])
+    lg, cg = lab.copy(), cost.copy()
+    o.run_group(lg, cg, 4, 0, 0, 5, 1, 3, 8.0, 1.0, 0, batch_cycle=True)
+    assert np.array_equal(lg, lbat) and np.array_equal(cg, cbat)
+    assert np.any(la != lbat)
