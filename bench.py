@@ -83,11 +83,14 @@ def run_gpu(steps: int, warmup: int, seed: int = 0, k_rans: int = 0, name: str =
     cost = torch.zeros((h, w), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
 
+    from paper_1603_08328_amd.autotune import plans_for
+    tiles = plans_for(w, h, prm["gf_radius"], wl["grids"])  # the committed tile plans
+
     def one_step(timing):
         ctx = L.lexp_create(prm, left, right, stream)
         L.lexp_set_timing(ctx, TIME_EVERY if timing else 0)
         grids = [tuple(g) + (k_rans,) for g in wl["grids"]]
-        e, t = L.lexp_optimize(ctx, grids, wl["iterations"], seed, labels, cost, stream)
+        e, t = L.lexp_optimize(ctx, grids, wl["iterations"], seed, labels, cost, stream, tiles=tiles)
         st = L.lexp_get_stats(ctx)
         ctx.close()
         return e, t, st
@@ -306,6 +309,7 @@ def run_batch_cycle(name: str, steps: int, n_pairs: int = 0, seed: int = 0):
     import torch
 
     import paper_1603_08328_amd.lexp as L
+    from paper_1603_08328_amd.autotune import plans_for
     from synth import PAPER_PARAMS, make_pair, make_workload_pair, params_for, workload
     from synth.workloads import many_pair_scenes
 
@@ -330,8 +334,10 @@ def run_batch_cycle(name: str, steps: int, n_pairs: int = 0, seed: int = 0):
         L.lexp_reset_stats(ctxs[0])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        bc = mode == "batch_cycle"
+        tiles = plans_for(scenes[0][0]["width"], scenes[0][0]["height"], 20, wl["grids"], bc) if not n_pairs else None
         es, ts = L.lexp_optimize_batch(ctxs, wl["grids"], wl["iterations"], [seed + i for i in range(len(ctxs))],
-                                       labs, costs, stream, batch_cycle=(mode == "batch_cycle"))
+                                       labs, costs, stream, batch_cycle=bc, tiles=tiles)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         st = L.lexp_get_stats(ctxs[0])

@@ -193,3 +193,23 @@ def test_ransac_proposals_bitwise_equal_to_oracle(tiny_pair, w, h):
                         assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), (args[2:], a, b)
                         n += 1
     assert n > 500
+
+
+def test_tile_plan_table_lookup():
+    """The committed tile plans: one entry per (image size, radius, cell,
+    mode) the tuner measured, each the default rule unless a plan beat it by
+    the tuner's margin; levels the table does not hold take the default."""
+    from paper_1603_08328_amd import autotune as A
+    t = A.load_table()
+    assert "gfx950" in t and len(t["gfx950"]) >= 12
+    for k, e in t["gfx950"].items():
+        default = e["default_kernel_ms_per_group_step"]
+        chosen = e["tried"][f"{e['cols']},{e['fill']}"]
+        assert (e["cols"], e["fill"]) == (0, 256) or chosen < (1 - A.MARGIN) * default, k
+        assert min(e["tried"].values()) == e["tried"][e["fastest"]]
+    grids = [(5, 1, 7), (15, 1, 7), (25, 1, 7)]
+    got = A.plans_for(450, 375, 20, grids, table=t)
+    assert got == [(t["gfx950"][f"450x375/r20/c{c}/plain"]["cols"], t["gfx950"][f"450x375/r20/c{c}/plain"]["fill"])
+                   for c, _, _ in grids]
+    assert A.plans_for(451, 375, 20, grids, table=t) == [(0, 0)] * 3
+    assert A.plans_for(450, 375, 20, [(7, 1, 7)], table=t) == [(0, 0)]
