@@ -364,64 +364,64 @@ def run_batch_cycle(name: str, steps: int, n_pairs: int = 0, seed: int = 0):
                 iterations=wl["iterations"], plain_final_energy=target, **out)
 
 
-def run_cpu_baseline():
-    """The oracle on a bounded sample of the same workload: initial per-pixel
-    costs of the regions of every cell of eight groups (group offsets
-    (i, j) mod 4 with j in {0, 1}) at grid levels 5/15/25 px, and the 8
-    proposer steps of those cells at iteration 0 (the groups one after the
-    other, the cells of a group in parallel on all host threads).  The
-    per-eval times of the two parts are weighted by the full run's counts to
-    give evals/s in the metric's unit."""
+def _oracle_sample(ora, prm, wl, groups, threads, stride=1):
+    """Times the oracle on the regions of the given groups ((i mod 4, j mod 4)
+    offsets of Eq. (15); every `stride`-th cell of each, or fewer skipped to keep
+    four cells per thread) at every grid level:
+    their initial per-pixel costs, then the proposer steps of iteration 0 (the
+    groups one after the other, the cells of a group in parallel on `threads`
+    host threads).  Returns seconds and evaluations of both parts (the
+    expansions per cell size)."""
     from concurrent.futures import ThreadPoolExecutor
 
     from oracle import Oracle
-    from synth import make_workload_pair, params_for, workload
 
-    wl = workload(WORKLOAD)
-    prm = params_for(WORKLOAD)
-    pair = make_workload_pair(WORKLOAD)
-    ora = Oracle(prm, pair.left, pair.right)
-    threads = Oracle.num_threads()
-    h, w = pair.left.shape[:2]
-    labels = ora.init_labels(0)
-    costs = np.zeros((h, w))
-    t_a5 = 0.0
-    n_a5 = 0
-    t_exp = {}
-    n_exp = {}
-    for level, (cell, kp, kr) in enumerate(wl["grids"]):
-        nci = -(-w // cell)
-        ncj = -(-h // cell)
-        groups = [(gi, gj) for gj in (0, 1) for gi in range(4)]
-        cells = [(i, j) for gi, gj in groups for j in range(gj, ncj, 4) for i in range(gi, nci, 4)]
-        rects = [((i - 1) * cell, (j - 1) * cell, (i + 2) * cell, (j + 2) * cell) for i, j in cells]
-        mask = np.zeros((h, w), np.uint8)
-        for u0, v0, u1, v1 in rects:
-            mask[max(v0, 0):v1, max(u0, 0):u1] = 1
-        t0 = time.perf_counter()
-        c = ora.pixel_costs(labels, mask)
-        t_a5 += time.perf_counter() - t0
-        n_a5 += int(mask.sum())
-        m = mask.astype(bool)
-        costs[m] = c[m]
+    Oracle.set_threads(threads)
+    try:
+        w, h = int(prm["width"]), int(prm["height"])
+        labels = ora.init_labels(0)
+        costs = np.zeros((h, w))
+        t_a5, n_a5, t_exp, n_exp = 0.0, 0, {}, {}
+        for level, (cell, kp, kr) in enumerate(wl["grids"]):
+            nci, ncj = -(-w // cell), -(-h // cell)
+            cells = [(i, j) for gi, gj in groups for j in range(gj, ncj, 4) for i in range(gi, nci, 4)]
+            # sub-sample, keeping at least four cells per thread
+            cells = cells[::max(1, min(stride, len(cells) // (4 * threads)))]
+            rects = [((i - 1) * cell, (j - 1) * cell, (i + 2) * cell, (j + 2) * cell) for i, j in cells]
+            mask = np.zeros((h, w), np.uint8)
+            for u0, v0, u1, v1 in rects:
+                mask[max(v0, 0):v1, max(u0, 0):u1] = 1
+            t0 = time.perf_counter()
+            c = ora.pixel_costs(labels, mask)
+            t_a5 += time.perf_counter() - t0
+            n_a5 += int(mask.sum())
+            m = mask.astype(bool)
+            costs[m] = c[m]
 
-        def run_cell(q):
-            i, j = cells[q]
-            for step in range(kp + kr):
-                a = ora.propose(labels, 0, 0, level, cell, i, j, step, kp, prm["disp_max"] / 2, 1.0)
-                ora.expand(labels, costs, rects[q], a)
+            def run_cell(q):
+                i, j = cells[q]
+                for step in range(kp + kr):
+                    a = ora.propose(labels, 0, 0, level, cell, i, j, step, kp, prm["disp_max"] / 2, 1.0)
+                    ora.expand(labels, costs, rects[q], a)
 
-        # one group after the other (Eq. (15)); the cells of a group in parallel (Lemma 3)
-        t0 = time.perf_counter()
-        with ThreadPoolExecutor(max_workers=threads) as ex:
-            for gi, gj in groups:
-                list(ex.map(run_cell, [q for q, (i, j) in enumerate(cells) if i % 4 == gi and j % 4 == gj]))
-        t_exp[cell] = time.perf_counter() - t0
-        n_exp[cell] = sum((min(u1, w) - max(u0, 0)) * (min(v1, h) - max(v0, 0)) for u0, v0, u1, v1 in rects) \
-            * (kp + kr)
-    # full-run counts per level (evaluations of every expansion) and of the init
+            # one group after the other (Eq. (15)); the cells of a group in parallel (Lemma 3)
+            t0 = time.perf_counter()
+            with ThreadPoolExecutor(max_workers=threads) as ex:
+                for gi, gj in groups:
+                    list(ex.map(run_cell, [q for q, (i, j) in enumerate(cells) if i % 4 == gi and j % 4 == gj]))
+            t_exp[cell] = time.perf_counter() - t0
+            n_exp[cell] = sum((min(u1, w) - max(u0, 0)) * (min(v1, h) - max(v0, 0))
+                              for u0, v0, u1, v1 in rects) * (kp + kr)
+    finally:
+        Oracle.set_threads(0)
+    return t_a5, n_a5, t_exp, n_exp
+
+
+def _full_counts(w, h, wl):
+    """Evaluations of a whole run: the initial per-pixel costs and every
+    expansion of every level (per cell size)."""
     full = {}
-    for level, (cell, kp, kr) in enumerate(wl["grids"]):
+    for cell, kp, kr in wl["grids"]:
         nci, ncj = -(-w // cell), -(-h // cell)
         tot = 0
         for j in range(ncj):
@@ -430,13 +430,84 @@ def run_cpu_baseline():
                     min((j + 2) * cell, h)
                 tot += (u1 - u0) * (v1 - v0)
         full[cell] = tot * (kp + kr) * wl["iterations"]
-    full_evals = h * w + sum(full.values())
-    full_time = h * w * (t_a5 / n_a5) + sum(full[c] * t_exp[c] / n_exp[c] for c in full)
-    sample_time = t_a5 + sum(t_exp.values())
-    return dict(value=full_evals / full_time / 1e9, cores=threads, sample_s=sample_time,
+    return h * w, full
+
+
+def _weighted(sample, w, h, wl):
+    """Evals/s of the whole run from a sample's per-eval times."""
+    t_a5, n_a5, t_exp, n_exp = sample
+    n_init, full = _full_counts(w, h, wl)
+    full_evals = n_init + sum(full.values())
+    full_time = n_init * (t_a5 / n_a5) + sum(full[c] * t_exp[c] / n_exp[c] for c in full)
+    return full_evals / full_time / 1e9, full_evals, t_a5 + sum(t_exp.values()), sum(n_exp.values()), n_a5
+
+
+def run_cpu_baseline():
+    """The oracle on bounded samples (per-eval times weighted by a full run's
+    counts, in the metric's unit):
+    - on all host threads, the 450x375 workload: the regions of eight of the
+      16 groups ((i, j) mod 4 with j in {0, 1}) at levels 5/15/25 px, their
+      initial costs and 8 proposer steps (the reported value);
+    - on one thread, the same workload: every 12th region of group (0, 0);
+    - on all threads, the 1500x1000 workload's shape: every 16th region of
+      group (0, 0)."""
+    from oracle import Oracle
+    from synth import make_workload_pair, params_for, workload
+
+    threads = Oracle.num_threads()
+    out = {}
+    for name, groups, thr, stride, key in (
+            (WORKLOAD, [(gi, gj) for gj in (0, 1) for gi in range(4)], threads, 1, "all"),
+            (WORKLOAD, [(0, 0)], 1, 12, "one"),
+            ("highres-1500x1000", [(0, 0)], threads, 16, "highres")):
+        wl = workload(name)
+        prm = params_for(name)
+        pair = make_workload_pair(name)
+        ora = Oracle(prm, pair.left, pair.right)
+        sample = _oracle_sample(ora, prm, wl, groups, thr, stride)
+        out[key] = _weighted(sample, int(prm["width"]), int(prm["height"]), wl)
+        ora.close()
+    v, full_evals, sample_s, n_exp, n_a5 = out["all"]
+    return dict(value=v, cores=threads, sample_s=sample_s + out["one"][2] + out["highres"][2],
                 sample=(f"oracle FP64: initial costs of {n_a5} px and 8 proposer steps of every cell of 8 of the "
-                        f"16 groups at levels 5/15/25 px ({sum(n_exp.values())} evals); per-eval times "
-                        f"weighted by the full run's counts ({full_evals} evals)"))
+                        f"16 groups at levels 5/15/25 px ({n_exp} evals); per-eval times weighted by the full "
+                        f"run's counts ({full_evals} evals)"),
+                one_core_value=out["one"][0],
+                one_core_sample=(f"one thread, every 12th region of group (0, 0) at the three levels "
+                                 f"({out['one'][3]} evals, {out['one'][2]:.1f} s)"),
+                highres_shape_value=out["highres"][0],
+                highres_shape_sample=(f"{threads} threads, 1500x1000 workload, every 16th region of group (0, 0) "
+                                      f"({out['highres'][3]} evals, {out['highres'][2]:.1f} s), "
+                                      f"weighted by that run's counts ({out['highres'][1]} evals)"))
+
+
+def run_oracle_curve(name: str = WORKLOAD, seed: int = 0):
+    """The oracle's whole plain-method run (Alg. 2, FP64, the cells of a group in
+    parallel on all host threads, the paper's CPU scheme): energy after the
+    initialisation and after every iteration, with the wall time at each."""
+    from oracle import Oracle
+    from synth import make_workload_pair, params_for, workload
+
+    wl = workload(name)
+    prm = params_for(name)
+    pair = make_workload_pair(name)
+    ora = Oracle(prm, pair.left, pair.right)
+    t0 = time.perf_counter()
+    labels = ora.init_labels(seed)
+    costs = ora.pixel_costs(labels)
+    energy = [ora.energy(labels, costs)[0]]
+    times = [time.perf_counter() - t0]
+    print(f"oracle curve: init {times[-1]:.1f} s, E {energy[-1]:.1f}", flush=True)
+    scale = 1.0
+    for it in range(wl["iterations"]):
+        for level, (cell, kp, kr) in enumerate(wl["grids"]):
+            for k in range(16):
+                ora.run_group(labels, costs, seed, it, level, cell, kp, kr, prm["disp_max"] / 2 * scale, scale, k)
+        scale *= 0.5
+        energy.append(ora.energy(labels, costs)[0])
+        times.append(time.perf_counter() - t0)
+        print(f"oracle curve: iteration {it} {times[-1]:.1f} s, E {energy[-1]:.1f}", flush=True)
+    return dict(workload=name, threads=Oracle.num_threads(), energy=energy, time_s=times)
 
 
 def main():
@@ -466,6 +537,8 @@ def main():
     ap.add_argument("--batch-cycle", action="store_true",
                     help="instead: the plain method against the batch cycle, energy against time (with "
                          "--many-pairs N: N pairs batched)")
+    ap.add_argument("--oracle-curve", action="store_true",
+                    help="instead: the oracle's whole run on 450x375 on the host cores, energy against time")
     ap.add_argument("--k-rans", type=int, default=0,
                     help="RANSAC proposer steps per cell and level (Alg. 1; 0 in the workload as specified)")
     args = ap.parse_args()
@@ -484,6 +557,9 @@ def main():
     if args.both_views:
         print(json.dumps({"workload": "450x375 synthetic pair, both views and post-processing",
                           "both_views": run_both_views()}), flush=True)
+        return
+    if args.oracle_curve:
+        print(json.dumps({"oracle_curve": run_oracle_curve()}), flush=True)
         return
     if args.batch_cycle:
         print(json.dumps({"batch_cycle": run_batch_cycle(args.workload, args.steps, args.many_pairs)}), flush=True)
@@ -516,7 +592,10 @@ def main():
     if not args.no_cpu_baseline and args.workload == WORKLOAD:
         c = run_cpu_baseline()
         cpu = {"value": c["value"], "unit": "Gpix*labels/s", "cores": c["cores"], "kind": "oracle",
-               "sample": c["sample"], "sample_seconds": round(c["sample_s"], 2)}
+               "sample": c["sample"], "sample_seconds": round(c["sample_s"], 2),
+               "one_core": {"value": c["one_core_value"], "cores": 1, "sample": c["one_core_sample"]},
+               "highres_1500x1000_shape": {"value": c["highres_shape_value"], "cores": c["cores"],
+                                           "sample": c["highres_shape_sample"]}}
     out = {
         "metric": METRIC,
         "value": value,

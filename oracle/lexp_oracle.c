@@ -1217,6 +1217,17 @@ void ora_postprocess(const ora_ctx* c, const float* labL, const float* labR, dou
   free(ok);
 }
 
+/* Threads of the oracle's parallel loops (n <= 0: the default). */
+void ora_set_threads(int n) {
+#ifdef _OPENMP
+  static int dflt = 0;
+  if (!dflt) dflt = omp_get_max_threads();
+  omp_set_num_threads(n > 0 ? n : dflt);
+#else
+  (void)n;
+#endif
+}
+
 int ora_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

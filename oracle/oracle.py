@@ -93,6 +93,8 @@ def lib():
     L.ora_postprocess.restype = None
     L.ora_postprocess.argtypes = [vp, f32, f32, f64, _P(np.uint8)]
     L.ora_num_threads.restype = C.c_int
+    L.ora_set_threads.argtypes = [C.c_int]
+    L.ora_set_threads.restype = None
     _lib = L
     return L
 
@@ -377,3 +379,8 @@ class Oracle:
     @staticmethod
     def num_threads() -> int:
         return lib().ora_num_threads()
+
+    @staticmethod
+    def set_threads(n: int) -> None:
+        """Threads of the oracle's parallel loops (0: the default)."""
+        lib().ora_set_threads(int(n))
