@@ -244,15 +244,19 @@ def run_learned(n_train: int, epochs: int, n_eval: int):
     import paper_1603_08328_amd.lexp as L
     from paper_1603_08328_amd import learned as LP
 
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     t0 = time.perf_counter()
-    samples = LP.make_training_set(range(1000, 1000 + n_train))
+    samples = LP.make_training_set(range(1000, 1000 + n_train), log=log)
     t_data = time.perf_counter() - t0
     net = L.lexp_net_create(450, 375, seed=0)
     t0 = time.perf_counter()
     hist = LP.train(net, samples, epochs=epochs, lr=1e-3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    res = LP.evaluate(net, range(1200, 1200 + n_eval))
+    log(f"trained: losses {hist[0]:.3f} -> {hist[-1]:.3f}")
+    res = LP.evaluate(net, range(1200, 1200 + n_eval), log=log)
     ctx, lab, _ = samples[0]
     f_ms, t_ms, f_tf, t_tf = LP.conv_throughput(net, ctx, lab)
     steps = len(samples) * epochs

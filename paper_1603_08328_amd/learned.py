@@ -33,14 +33,18 @@ def _run(ctx, grids, iterations, seed, learned=False):
     return lab, e, t
 
 
-def make_training_set(seeds, input_iterations=(1, 3), target_iterations=10, solver_seed=0):
+def make_training_set(seeds, input_iterations=(1, 3), target_iterations=10, solver_seed=0, log=None):
     """[(ctx, input labels, target labels)] (device tensors), one entry per
-    seed and input iteration count."""
+    seed and input iteration count.  log (optional) is called with a line of
+    progress every ten scenes."""
     import torch
     from synth import workload
     grids = workload("lowres-450x375")["grids"]
     out = []
-    for sd in seeds:
+    t0 = time.perf_counter()
+    for k, sd in enumerate(seeds):
+        if log and k % 10 == 0:
+            log(f"training set: scene {k} of {len(seeds)}, {time.perf_counter() - t0:.0f} s")
         pair, prm = _scene(sd)
         ctx = L.lexp_create(prm, torch.from_numpy(pair.left).cuda(), torch.from_numpy(pair.right).cuda())
         target, _, _ = _run(ctx, grids, target_iterations, solver_seed)
@@ -69,7 +73,7 @@ def _time_to(e, t, level):
     return None
 
 
-def evaluate(net, seeds, iterations=10, solver_seed=0, tol=0.005):
+def evaluate(net, seeds, iterations=10, solver_seed=0, tol=0.005, log=None):
     """Plain against learned proposals on held-out scenes: per scene, the
     final energies, the energy and time traces, and the wall time each run
     needs to come within tol of the plain run's final energy."""
@@ -85,6 +89,8 @@ def evaluate(net, seeds, iterations=10, solver_seed=0, tol=0.005):
         _, ep, tp = _run(ctx, grids, iterations, solver_seed)
         _, el, tl = _run(ctx, grids, iterations, solver_seed, learned=True)
         level = ep[-1] * (1 + tol)
+        if log:
+            log(f"held-out scene {sd}: plain {ep[-1]:.1f}, learned {el[-1]:.1f}")
         res.append(dict(seed=int(sd), plain_final=float(ep[-1]), learned_final=float(el[-1]),
                         plain_time_to=_time_to(ep, tp, level), learned_time_to=_time_to(el, tl, level),
                         plain_total_s=float(tp[-1]), learned_total_s=float(tl[-1]),
