@@ -66,7 +66,7 @@ def _traffic_from_profile():
         return None
 
 
-def run_gpu(steps: int, warmup: int, seed: int = 0, k_rans: int = 0, name: str = WORKLOAD):
+def run_gpu(steps: int, warmup: int, seed: int = 0, k_rans: int = 0, name: str = WORKLOAD, speculate: bool = False):
     import torch
 
     import paper_1603_08328_amd.lexp as L
@@ -90,7 +90,8 @@ def run_gpu(steps: int, warmup: int, seed: int = 0, k_rans: int = 0, name: str =
         ctx = L.lexp_create(prm, left, right, stream)
         L.lexp_set_timing(ctx, TIME_EVERY if timing else 0)
         grids = [tuple(g) + (k_rans,) for g in wl["grids"]]
-        e, t = L.lexp_optimize(ctx, grids, wl["iterations"], seed, labels, cost, stream, tiles=tiles)
+        e, t = L.lexp_optimize(ctx, grids, wl["iterations"], seed, labels, cost, stream, tiles=tiles,
+                               speculate=speculate)
         st = L.lexp_get_stats(ctx)
         ctx.close()
         return e, t, st
@@ -109,8 +110,17 @@ def run_gpu(steps: int, warmup: int, seed: int = 0, k_rans: int = 0, name: str =
     tlaunches = sum(r[2]["unary_timed_launches"] for r in results)
     launches = sum(r[2]["unary_launches"] for r in results)
     e_final = float(results[-1][0][-1])
+    by_level = []  # the fused kernel per grid level, over the timed launches
+    for li, g in enumerate(wl["grids"]):
+        ms = sum(r[2]["unary_level_ms"][li] for r in results)
+        nb = sum(r[2]["unary_level_alg_bytes"][li] for r in results)
+        nl = sum(r[2]["unary_level_launches"][li] for r in results)
+        if nl and ms > 0:
+            by_level.append({"cell": int(g[0]), "launches_per_step": nl // steps, "avg_launch_us": ms / nl * 1e3,
+                             "alg_bytes_per_launch": nb / nl, "achieved": nb / (ms / 1e3) / 1e9,
+                             "frac": nb / (ms / 1e3) / 1e9 / HBM_PEAK_GBPS})
     return dict(elapsed=elapsed, evals=evals, kernel_ms=kms, kernel_bytes=kbytes, kernel_evals=kevals,
-                timed_launches=tlaunches, launches=launches,
+                timed_launches=tlaunches, launches=launches, by_level=by_level,
                 energy=[float(x) for x in results[-1][0]], times=[float(x) for x in results[-1][1]],
                 final_energy=e_final, stats=results[-1][2], final_labels=labels.cpu().numpy())
 
@@ -543,6 +553,8 @@ def main():
                          "--many-pairs N: N pairs batched)")
     ap.add_argument("--oracle-curve", action="store_true",
                     help="instead: the oracle's whole run on 450x375 on the host cores, energy against time")
+    ap.add_argument("--speculate", action="store_true",
+                    help="single-part groups: evaluate each step's two possible successors while the host cuts it")
     ap.add_argument("--k-rans", type=int, default=0,
                     help="RANSAC proposer steps per cell and level (Alg. 1; 0 in the workload as specified)")
     args = ap.parse_args()
@@ -587,7 +599,7 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-    g = run_gpu(args.steps, args.warmup, k_rans=args.k_rans, name=args.workload)
+    g = run_gpu(args.steps, args.warmup, k_rans=args.k_rans, name=args.workload, speculate=args.speculate)
     ms = g["elapsed"] / args.steps * 1e3
     value = g["evals"] / g["elapsed"] / 1e9
     achieved = g["kernel_bytes"] / (g["kernel_ms"] / 1e3) / 1e9 if g["kernel_ms"] > 0 else 0.0
@@ -618,14 +630,15 @@ def main():
                                 "1500x1000 synthetic pair, 40 planar + 6 quadric segments, 2% holes, disparity [0,200]")
                                + ", guided-filter radius 20, cells 5/15/25, 10 iterations, {K_prop,K_rand}={1,7}"
                                + (f", K_RANS={args.k_rans}" if args.k_rans else ""),
-                   "evals_per_step": g["evals"] // args.steps},
+                   "evals_per_step": g["evals"] // args.steps, "speculate": args.speculate},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": "k_unary<0> (fused raw cost + guided filter)",
                      "launches_per_step": g["launches"] // args.steps,
                      "timed_launches_per_step": g["timed_launches"] // args.steps,
                      "avg_launch_us": g["kernel_ms"] / max(g["timed_launches"], 1) * 1e3,
-                     "alg_bytes_per_launch": g["kernel_bytes"] / max(g["timed_launches"], 1)},
+                     "alg_bytes_per_launch": g["kernel_bytes"] / max(g["timed_launches"], 1),
+                     "by_level": g["by_level"]},
         "cpu_baseline": cpu,
         "time_to_final_energy_s": g["times"][-1],
         "final_energy": g["final_energy"],

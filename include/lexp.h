@@ -133,6 +133,15 @@ typedef struct {
                            strips (0: 256).  Both decide the tiles, and so the rounding of
                            the costs; a committed table of tuned values keeps labels
                            independent of any run's timing. */
+  int32_t speculate;    /* 1: in groups whose regions form one part, the next step's two possible
+                           candidates of every region (its drawn pixel's label kept, or set to
+                           the current step's candidate: Alg. 1 reads no other label for
+                           propagation and refinement steps) are evaluated while the host cuts
+                           the current step, and the one the updated labels propose is used;
+                           the same labels and costs as 0 (each step evaluates its own
+                           candidate after the cut).  The discarded half counts among the
+                           kernel's timed evaluations, not among unary_evals.  Not with the
+                           batch cycle or graphs. */
 } lexp_schedule;
 
 /* Counters of the hot kernel, accumulated while timing is enabled. */
@@ -162,6 +171,11 @@ typedef struct {
   double host_solve_level_ms[4];/* lexp_optimize: host max-flow time per level summed over regions (CPU time of
                                    the solves, all threads; against host_cut_level_ms: the pool's efficiency) */
   int64_t host_solves[4];       /* lexp_optimize: regions cut on the host, per level */
+  double unary_level_ms[4];        /* lexp_optimize: timed fused-kernel milliseconds per grid level */
+  double unary_level_alg_bytes[4]; /* their algorithmic bytes */
+  int64_t unary_level_launches[4]; /* their launches */
+  int64_t spec_steps;   /* lexp_optimize: part steps that took speculatively evaluated costs */
+  int64_t spec_misses;  /* part steps whose candidates matched neither speculative one */
 } lexp_stats;
 
 /* Creates a context for one stereo pair and runs the label-independent set-up

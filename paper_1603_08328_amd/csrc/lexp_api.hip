@@ -171,7 +171,8 @@ struct lexp_ctx {
   int64_t time_seq = 0;  // fused launches since timing was turned on
   lexp_stats stats{};
   std::vector<hipEvent_t> ev_free;
-  struct Pending { hipEvent_t a, b; double bytes; };
+  int time_level = -1;  // grid level the timed launches are counted under (lexp_optimize), -1: none
+  struct Pending { hipEvent_t a, b; double bytes; int level; };
   std::vector<Pending> ev_pending;
   // two halves of a group step in flight at once (host cuts one half while
   // the device evaluates the other)
@@ -195,6 +196,13 @@ struct lexp_ctx {
     hipEvent_t cut0 = nullptr, cut1 = nullptr;  // around a timed device max-flow launch
     bool cut_timed = false;
     int cut_block = 0, cut_every = 0;  // shape of that launch
+    // speculative costs of the next step (lexp_optimize, single-part
+    // groups), double-buffered by step parity
+    DevBuf<Item> d_sitems[2];
+    DevBuf<Tile> d_stiles[2];
+    DevBuf<float> d_sphi[2];
+    PinBuf<Item> h_sitems[2];
+    PinBuf<Tile> h_stiles[2];
   } part[2];
   size_t res_items = 0;  // status slots in the result buffers
   // batch cycle: one launch per group step for every region and candidate
@@ -366,6 +374,11 @@ void collect_timing(lexp_ctx* c) {
     float ms = 0.f;
     if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       c->stats.unary_kernel_ms += ms;
+      if (p.level >= 0 && p.level < 4) {
+        c->stats.unary_level_ms[p.level] += ms;
+        c->stats.unary_level_alg_bytes[p.level] += p.bytes;
+        c->stats.unary_level_launches[p.level] += 1;
+      }
     }
     c->ev_free.push_back(p.a);
     c->ev_free.push_back(p.b);
@@ -388,7 +401,7 @@ template <int MODE>
 lexp_status launch_unary(lexp_ctx* c, const PairDev* d_pairs, const Item* d_items, const Tile* d_tiles, int n_tiles,
                          const TileCaps& caps,
                          const float4* label_field, float* out, hipStream_t s, double alg_bytes, int64_t evals,
-                         int64_t n_items, int pair_hint = -1, int direct = 0) {
+                         int64_t n_items, int pair_hint = -1, int direct = 0, bool count_evals = true) {
   if (n_tiles <= 0) return LEXP_OK;
   const int ring = lexp::unary_ring_rows(c->r);
   const size_t lds = lexp::unary_lds_bytes(ring, caps.wp, caps.tw, caps.ws);
@@ -471,11 +484,11 @@ lexp_status launch_unary(lexp_ctx* c, const PairDev* d_pairs, const Item* d_item
   if (timed) {
     c->stats.unary_launches += 1;
     c->stats.unary_alg_bytes += alg_bytes;
-    c->stats.unary_evals += evals;
+    if (count_evals) c->stats.unary_evals += evals;
     c->stats.unary_items += n_items;
   }
   if (tev) {
-    c->ev_pending.push_back({ea, eb, alg_bytes});
+    c->ev_pending.push_back({ea, eb, alg_bytes, c->time_level});
     c->stats.unary_timed_launches += 1;
     c->stats.unary_timed_alg_bytes += alg_bytes;
     c->stats.unary_timed_evals += evals;
@@ -904,6 +917,11 @@ lexp_status lexp_destroy(lexp_ctx* c) {
   c->h_items.release(); c->h_tiles.release(); c->h_terms.release(); c->h_x.release(); c->h_flag.release();
   c->h_partial.release(); c->h_labels4.release();
   c->d_bitems.release(); c->d_btiles.release(); c->d_bphi.release(); c->h_bitems.release(); c->h_btiles.release();
+  for (auto& B : c->part)
+    for (int i = 0; i < 2; ++i) {
+      B.d_sitems[i].release(); B.d_stiles[i].release(); B.d_sphi[i].release();
+      B.h_sitems[i].release(); B.h_stiles[i].release();
+    }
   for (auto& b : c->part) {
     b.d_items.release(); b.d_phi.release(); b.d_terms.release(); b.d_x.release(); b.d_res.release();
     b.h_items.release(); b.h_terms.release(); b.h_x.release(); b.h_res.release();
@@ -1143,19 +1161,20 @@ lexp_status net_forward(lexp_net* net, lexp_ctx* c, const float* labels, hipStre
   const int n = W * H;
   hipLaunchKernelGGL(lexp::k_net_input, dim3((n + 255) / 256), dim3(256), 0, s, c->left4, c->right4,
                      (const float4*)labels, W, H, (double)c->prm.disp_max, net->act[0]);
-  // forward: a workgroup per four rows of a 64-column run
-  const dim3 grid(((W + 63) / 64) * ((H + 3) / 4));
+  // forward: a workgroup per kConvRows rows of a run of 16 kConvSegs columns
+  const int run = 16 * lexp::kConvSegs;
+  const dim3 grid(((W + run - 1) / run) * ((H + lexp::kConvRows - 1) / lexp::kConvRows)), block(lexp::kConvThreads);
   for (int l = 0; l < lexp_net::kLayers; ++l) {
     const uint16_t* w16 = net->w16 + net->w16_off[l];
     const float* b = net->prm + net->b_off[l];
     if (l == 0)
-      hipLaunchKernelGGL((lexp::k_conv_fwd<16, 32, false>), grid, dim3(256), 0, s, net->act[0], w16, b, W, H,
+      hipLaunchKernelGGL((lexp::k_conv_fwd<16, 32, false>), grid, block, 0, s, net->act[0], w16, b, W, H,
                          net->act[1], (float*)nullptr);
     else if (l < lexp_net::kLayers - 1)
-      hipLaunchKernelGGL((lexp::k_conv_fwd<32, 32, false>), grid, dim3(256), 0, s, net->act[l], w16, b, W, H,
+      hipLaunchKernelGGL((lexp::k_conv_fwd<32, 32, false>), grid, block, 0, s, net->act[l], w16, b, W, H,
                          net->act[l + 1], (float*)nullptr);
     else
-      hipLaunchKernelGGL((lexp::k_conv_fwd<32, 16, true>), grid, dim3(256), 0, s, net->act[l], w16, b, W, H,
+      hipLaunchKernelGGL((lexp::k_conv_fwd<32, 16, true>), grid, block, 0, s, net->act[l], w16, b, W, H,
                          (uint16_t*)nullptr, net->y);
   }
   hipLaunchKernelGGL(lexp::k_net_planes, dim3((n + 255) / 256), dim3(256), 0, s, net->y, W, H,
@@ -1206,7 +1225,10 @@ struct Part {
   int direct = 0;           // tile i is the only tile of item i
   hipGraphExec_t graph = nullptr;  // captured device sequence of one step of this part (graph mode)
   float* phi_ext = nullptr;  // batch cycle: the group's costs, evaluated for every step at once (items'
-                             // out_off index it); nullptr: this part's own buffer, evaluated per step
+                             // out_off index it); speculation: the costs of the step's matched candidates;
+                             // nullptr: this part's own buffer, evaluated per step
+  int spec_step = -1;            // step whose two possible candidates per region were evaluated (-1: none)
+  std::vector<float> spec_al;    // those candidates: region q's at 6q (label at r kept) and 6q+3 (changed)
 };
 
 // Per grid level: picks the device max-flow's launch shape by timing each
@@ -1293,13 +1315,15 @@ struct StepArgs {
 
 // Alg. 1 candidate of region q of a part for a step, from its pair's host
 // label mirror as it stands.
-void propose_plane(const Part& P, const StepArgs& a, int q, int step, float al[3]) {
+// (label_at_r: see lexp::propose)
+void propose_plane(const Part& P, const StepArgs& a, int q, int step, float al[3],
+                   const float* label_at_r = nullptr) {
   const Item& item = P.items[q];
   const RunPair& rp = a.pairs[item.pair];
   const lexp_ctx* c = rp.c;
   lexp::propose(c->W, c->H, rp.mirror.data(), 3, rp.seed, a.it, a.level, a.cell, P.ci[q], P.cj[q], step, a.kp,
                 a.kr, c->prm.disp_max / 2.0 * a.scale, a.scale, al,
-                rp.net_planes.empty() ? nullptr : rp.net_planes.data());
+                rp.net_planes.empty() ? nullptr : rp.net_planes.data(), label_at_r);
 }
 
 // Alg. 1 candidate of region q of a part for a step, into its item.
@@ -1710,6 +1734,87 @@ lexp_status batch_costs(lexp_ctx* c, RunPair* pairs, Part* const* P, const StepA
                          G * K, (int64_t)ii, hint >= 0 ? hint : -1, 0);
 }
 
+// Speculative costs of a part's step t (t >= 1, not a RANSAC step), queued
+// before the host cuts step t-1.  A region's candidate for step t reads the
+// label at one drawn pixel r of its centre cell (Alg. 1 propagation and
+// refinement), and the cut of step t-1 either keeps that label or sets it to
+// step t-1's candidate (r lies inside the region, which no other region of
+// the group touches, Lemma 3).  Both possible candidates of every region are
+// evaluated in one launch over the part's own tiles, so each candidate's costs
+// are those its own launch would give; after the cut, spec_match picks the
+// one the updated labels propose.
+lexp_status spec_launch(lexp_ctx* c, Part& Q, lexp_ctx::PartBuf& B, const StepArgs& a, int t, const PairDev* d_pairs,
+                        hipStream_t s) {
+  const size_t n = Q.items.size();
+  const int par = t & 1;
+  // the buffers of this parity were last read by step t-2's work, which the
+  // host has waited for (its cut) before queueing anything of step t-1
+  HIP_TRY(B.h_sitems[par].ensure(2 * n));
+  HIP_TRY(B.d_sitems[par].ensure(2 * n));
+  HIP_TRY(B.h_stiles[par].ensure(2 * Q.n_tiles));
+  HIP_TRY(B.d_stiles[par].ensure(2 * Q.n_tiles));
+  HIP_TRY(B.d_sphi[par].ensure((size_t)(2 * Q.n_px)));
+  Q.spec_al.resize(6 * n);
+  Item* si = B.h_sitems[par].p;
+  pool_of(c).parallel_for((int)n, [&](int q, int) {
+    const Item& cur = Q.items[q];  // its candidate is step t-1's
+    const float alt[3] = {cur.a, cur.b, cur.c};
+    float* al = &Q.spec_al[6 * (size_t)q];
+    propose_plane(Q, a, q, t, al);            // r keeps its label
+    propose_plane(Q, a, q, t, al + 3, alt);   // r takes step t-1's candidate
+    for (int h = 0; h < 2; ++h) {
+      Item it = cur;
+      it.a = al[3 * h]; it.b = al[3 * h + 1]; it.c = al[3 * h + 2];
+      it.out_off = (long long)h * Q.n_px + cur.aux_off;
+      si[(size_t)h * n + q] = it;
+    }
+  });
+  Tile* st = B.h_stiles[par].p;
+  for (int h = 0; h < 2; ++h)
+    for (size_t j = 0; j < Q.n_tiles; ++j) {
+      Tile tl = c->h_tiles.p[Q.tile_off + j];
+      tl.item += (int)((size_t)h * n);
+      st[(size_t)h * Q.n_tiles + j] = tl;
+    }
+  HIP_TRY(hipMemcpyAsync(B.d_sitems[par].p, si, sizeof(Item) * 2 * n, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(B.d_stiles[par].p, st, sizeof(Tile) * 2 * Q.n_tiles, hipMemcpyHostToDevice, s));
+  Q.spec_step = t;
+  // evaluations count toward the run's total when used (spec_match)
+  return launch_unary<0>(c, d_pairs, B.d_sitems[par].p, B.d_stiles[par].p, (int)(2 * Q.n_tiles), Q.caps, nullptr,
+                         B.d_sphi[par].p, s, 2.0 * Q.bytes, 2 * Q.n_px, (int64_t)(2 * n), Q.pair_hint, 0, false);
+}
+
+// After the cut of step t-1 and the proposal of step t's candidates from the
+// updated labels: when every candidate equals one of the two evaluated for
+// its region (bit for bit), the step takes their costs; otherwise it
+// evaluates its own.
+// (t < 0: the part's own cost buffer, nothing speculated.)
+void spec_match(lexp_ctx* c, Part& Q, lexp_ctx::PartBuf& B, int t) {
+  Q.phi_ext = nullptr;
+  for (Item& it : Q.items) it.out_off = it.aux_off;
+  const bool ready = t >= 0 && Q.spec_step == t;
+  Q.spec_step = -1;
+  if (!ready) return;
+  const size_t n = Q.items.size();
+  std::vector<long long> off(n);
+  for (size_t q = 0; q < n; ++q) {
+    const Item& it = Q.items[q];
+    const float got[3] = {it.a, it.b, it.c};
+    int h = -1;
+    for (int k = 0; k < 2 && h < 0; ++k)
+      if (std::memcmp(got, &Q.spec_al[6 * q + 3 * k], sizeof(got)) == 0) h = k;
+    if (h < 0) {
+      c->stats.spec_misses += 1;
+      return;
+    }
+    off[q] = (long long)h * Q.n_px + it.aux_off;
+  }
+  for (size_t q = 0; q < n; ++q) Q.items[q].out_off = off[q];
+  Q.phi_ext = B.d_sphi[t & 1].p;
+  c->stats.spec_steps += 1;
+  if (c->timing) c->stats.unary_evals += Q.n_px;
+}
+
 // Items of a part for step t of a batch cycle (the part's items start at
 // `first` in the group's batch table): the candidates drawn at the group's
 // start, their costs' offsets in d_bphi.
@@ -1728,6 +1833,7 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
         sch->k_prop[h] + sch->k_rans[h] + sch->k_rand[h] > 64 || sch->tile_cols[h] < 0 ||
         sch->tile_cols[h] > lexp::kMaxTW || sch->tile_fill[h] < 0 || sch->tile_fill[h] > (1 << 20))
       return fail(LEXP_EINVAL, "bad grid level %d", h);
+  if (sch->speculate != 0 && sch->speculate != 1) return fail(LEXP_EINVAL, "speculate must be 0 or 1");
   if (sch->batch_cycle != 0 && sch->batch_cycle != 1) return fail(LEXP_EINVAL, "batch_cycle must be 0 or 1");
   lexp_ctx* c = pairs[0].c;
   if (sch->learned != 0 && sch->learned != 1) return fail(LEXP_EINVAL, "learned must be 0 or 1");
@@ -1753,6 +1859,10 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
   const bool dev_cut = c->prm.device_cut != 0;
   // kernel timing events are not captured, so a timed run launches eagerly
   const bool use_graph = c->prm.graph != 0 && !c->timing && !sch->batch_cycle;
+  // speculative costs of the next step (not with the batch cycle, whose
+  // candidates are all drawn at a group's start, nor with graphs, whose
+  // captured steps include their own cost launch)
+  const bool speculate = sch->speculate != 0 && !sch->batch_cycle && !use_graph;
   std::vector<GroupPlan> groups((size_t)sch->n_levels * 16);
   std::vector<Part> parts((size_t)sch->n_levels * 16 * 2);
   struct GraphGuard {  // frees the captured graphs on every way out
@@ -1761,6 +1871,10 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
       for (Part& x : p) drop_graph(x);
     }
   } graph_guard{parts};
+  struct LevelGuard {  // outside the run, timed launches are counted under no level
+    lexp_ctx* c;
+    ~LevelGuard() { c->time_level = -1; }
+  } level_guard{c};
   std::vector<CutBalance> balance((size_t)sch->n_levels);
   std::vector<CutTuner> tuners((size_t)sch->n_levels);
   size_t n_tiles = 0;
@@ -1842,6 +1956,7 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     for (int h = 0; h < sch->n_levels; ++h) {
       const int K = sch->k_prop[h] + sch->k_rans[h] + sch->k_rand[h];
       const StepArgs a{it, h, sch->cell[h], sch->k_prop[h], sch->k_rans[h], scale, pairs};
+      c->time_level = h;
       if (sch->learned && it == 0) {
         for (int p = 0; p < np; ++p) pairs[p].net_planes.clear();  // random labels: nothing to learn from yet
       } else if (sch->learned) {
@@ -1866,12 +1981,24 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
         // Alg. 1 for every cell of the group.  The cells are independent
         // (Lemma 3), so the two parts run staggered: while the host cuts
         // one part, the device evaluates the other part's next candidate.
+        // A single-part group overlaps nothing with its cuts, so each step's
+        // successor is evaluated speculatively while the host cuts it
+        // (spec_launch); propagation and refinement steps only.
+        const bool spec = speculate && (P[0]->items.empty() || P[1]->items.empty());
+        auto spec_next = [&](Part& Q, int hp, int step) -> lexp_status {
+          const int t = step + 1;
+          if (!spec || t >= K || (t >= a.kp && t < a.kp + a.kr)) return LEXP_OK;
+          return spec_launch(c, Q, c->part[hp], a, t, d_pairs, s);
+        };
         for (int hp = 0; hp < 2; ++hp)
           if (!P[hp]->items.empty() && K > 0) {
             Part& Q = *P[hp];
-            if (!sch->batch_cycle)
+            if (!sch->batch_cycle) {
+              spec_match(c, Q, c->part[hp], -1);  // step 0 evaluates its own costs
               pool_of(c).parallel_for((int)Q.items.size(), [&](int q, int) { propose_item(Q, a, q, 0); });
+            }
             if ((st = enqueue_part(c, Q, c->part[hp], d_pairs, c->d_tiles.p, use_graph, &tuners[h], s))) return st;
+            if ((st = spec_next(Q, hp, 0))) return st;
           }
         for (int step = 0; step < K; ++step)
           for (int hp = 0; hp < 2; ++hp) {
@@ -1883,7 +2010,10 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
             if (next >= 0) {
               if (sch->batch_cycle)
                 batch_step_items(c, *P[hp], hp == 0 ? 0 : P[0]->items.size() * K, next);
+              else
+                spec_match(c, *P[hp], c->part[hp], next);
               if ((st = enqueue_part(c, *P[hp], c->part[hp], d_pairs, c->d_tiles.p, use_graph, &tuners[h], s))) return st;
+              if ((st = spec_next(*P[hp], hp, next))) return st;
             }
           }
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - g0).count();
@@ -2107,8 +2237,9 @@ lexp_status lexp_net_train_step(lexp_net* net, lexp_ctx* c, const float* labels,
   uint16_t* g = net->gbuf[0];
   hipLaunchKernelGGL(lexp::k_net_loss, dim3(nb), dim3(256), 0, s, net->y, (const float4*)target, W, H,
                      (double)c->prm.disp_max, g, net->part_loss);
-  // input gradients: a workgroup per four rows of a 64-column run
-  const dim3 grid(((W + 63) / 64) * ((H + 3) / 4));
+  // input gradients: workgroups as in the forward pass
+  const int run = 16 * lexp::kConvSegs;
+  const dim3 grid(((W + run - 1) / run) * ((H + lexp::kConvRows - 1) / lexp::kConvRows)), block(lexp::kConvThreads);
   // backward through the layers: weight gradients, then the gradient of the
   // layer's input (through the ReLU that produced it)
   for (int l = lexp_net::kLayers - 1; l >= 0; --l) {
@@ -2116,10 +2247,10 @@ lexp_status lexp_net_train_step(lexp_net* net, lexp_ctx* c, const float* labels,
     const uint16_t* wt = net->wt16 + net->w16_off[l];
     if (l == lexp_net::kLayers - 1) {
       net_weight_grad<32, 16>(net, l, g, W, H, s);
-      hipLaunchKernelGGL((lexp::k_conv_bwd_x<32, 16>), grid, dim3(256), 0, s, g, wt, net->act[l], W, H, gp);
+      hipLaunchKernelGGL((lexp::k_conv_bwd_x<32, 16>), grid, block, 0, s, g, wt, net->act[l], W, H, gp);
     } else if (l > 0) {
       net_weight_grad<32, 32>(net, l, g, W, H, s);
-      hipLaunchKernelGGL((lexp::k_conv_bwd_x<32, 32>), grid, dim3(256), 0, s, g, wt, net->act[l], W, H, gp);
+      hipLaunchKernelGGL((lexp::k_conv_bwd_x<32, 32>), grid, block, 0, s, g, wt, net->act[l], W, H, gp);
     } else {
       net_weight_grad<16, 32>(net, l, g, W, H, s);
     }

@@ -110,7 +110,12 @@ __global__ void k_cut_lds(const Item* items, const int* terms, int nf, uint8_t* 
 // excess, or forward residuals only with 32-bit excess and 16-bit heights
 constexpr int kCutBytesFull = 52;
 constexpr int kCutBytesCompact = 28;
-// learned proposal network (lexp_net.hip)
+// learned proposal network (lexp_net.hip).  The forward and input-gradient
+// convolutions run a workgroup of kConvRows waves per kConvRows rows of a run
+// of 16 kConvSegs columns (one row per wave).
+constexpr int kConvSegs = 2;
+constexpr int kConvRows = 8;
+constexpr int kConvThreads = 64 * kConvRows;
 __global__ void k_net_input(const float4* left4, const float4* right4, const float4* labels, int W, int H,
                             double disp_max, uint16_t* x0);
 template <int CI, int CO, bool LAST>

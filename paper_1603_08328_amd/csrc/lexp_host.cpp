@@ -188,7 +188,7 @@ static bool ransac_plane(int width, const float* labels, int stride, uint64_t se
 
 void propose(int width, int height, const float* labels, int stride, uint64_t seed, int iteration, int level,
              int cell, int ci, int cj, int step, int k_prop, int k_rans, double r_d, double r_n, float out[3],
-             const float* net_planes) {
+             const float* net_planes, const float* label_at_r) {
   const int cu0 = ci * cell, cv0 = cj * cell;
   const int cw = std::min(cu0 + cell, width) - cu0;
   const int chh = std::min(cv0 + cell, height) - cv0;
@@ -199,7 +199,7 @@ void propose(int width, int height, const float* labels, int stride, uint64_t se
   if (idx >= npx) idx = npx - 1;
   const int ru = cu0 + (int)(idx % cw);
   const int rv = cv0 + (int)(idx / cw);
-  const float* fr = labels + ((size_t)rv * width + ru) * stride;
+  const float* fr = label_at_r ? label_at_r : labels + ((size_t)rv * width + ru) * stride;
   if (step < k_prop || (step < k_prop + k_rans && !ransac_plane(width, labels, stride, seed, key, cu0, cv0, cw, chh,
                                                                    out))) {
     out[0] = fr[0]; out[1] = fr[1]; out[2] = fr[2];

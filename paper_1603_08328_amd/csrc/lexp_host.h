@@ -28,9 +28,12 @@ void init_label(int width, int u, int v, double disp_max, uint64_t seed, float o
 // net_planes (optional, HxWx4): planes proposed by the learned network; the
 // refinement steps with an odd refinement index then take the plane of the
 // chosen pixel r instead of a perturbation.
+// label_at_r (optional): the label to take as the one at the drawn pixel r
+// instead of labels' (propagation and refinement steps read no other label;
+// not for RANSAC steps, which read the whole cell).
 void propose(int width, int height, const float* labels, int stride, uint64_t seed, int iteration, int level,
              int cell, int ci, int cj, int step, int k_prop, int k_rans, double r_d, double r_n, float out[3],
-             const float* net_planes = nullptr);
+             const float* net_planes = nullptr, const float* label_at_r = nullptr);
 
 // ---- exact binary minimisation ------------------------------------------
 // E(x) = sum_i U_i x_i + sum_{i, d < nf} w_{i,d} (1 - x_i) x_{i + fwd_d} on a

@@ -1,6 +1,8 @@
 // Learned proposal network on CDNA4 (gfx950): five 3x3 convolutions as
-// implicit GEMMs on the BF16 matrix cores (v_mfma_f32_16x16x16_bf16, FP32
-// sums), their backward passes, the plane loss and Adam.
+// implicit GEMMs on the BF16 matrix cores (FP32 sums), their backward
+// passes, the plane loss and Adam.  The forward and input-gradient products
+// use v_mfma_f32_16x16x32_bf16 (K = 32 per instruction), the weight
+// gradients v_mfma_f32_16x16x16_bf16.
 //
 // Layout: activations and gradients pixel-major (index (v W + u) C + c), BF16;
 // the last layer's output FP32; weights [tap][out][in] (tap = 3 ky + kx,
@@ -8,11 +10,14 @@
 // [tap][in][out] for the backward-data products.
 //
 // One matrix instruction computes one 16 x 16 block of a product.
-// Operand fragments (checked on the device): lane l holds A[l % 16][4 (l/16)
-// + i] and B[4 (l/16) + i][l % 16] for i < 4, and receives
+// Operand fragments (checked on the device): for K = 16, lane l holds
+// A[l % 16][4 (l/16) + i] and B[4 (l/16) + i][l % 16] for i < 4; for K = 32,
+// A[l % 16][8 (l/16) + i] and B[8 (l/16) + i][l % 16] for i < 8; both give
 // D[4 (l/16) + i][l % 16].
 //   forward     : M = 16 pixels of a row, N = output channels, K = 9 taps x
-//                 input channels (a wave takes four such blocks of a row);
+//                 input channels, tap-major, in chunks of 32 (one tap of 32
+//                 channels, or two taps of 16, the last chunk then half
+//                 zero); a wave takes four such blocks of a row;
 //   backward x  : M = 16 pixels, N = input channels, K = 9 taps x output
 //                 channels (gradient at p - offset; four blocks per wave);
 //   backward w  : per tap, M = output channels, N = input channels, K = the
@@ -20,7 +25,7 @@
 //                 order by a second kernel (the result does not depend on
 //                 scheduling).
 // BF16 values are rounded to nearest even from FP32 (FP64 values through
-// FP32 first), at the points listed in the reference's description.
+// FP32 first), at the points the network's training recipe fixes.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -32,6 +37,7 @@ namespace lexp {
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline uint16_t to_bf16(float x) {
@@ -41,14 +47,9 @@ __device__ inline uint16_t to_bf16(float x) {
 }
 __device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ inline bf16x4 load4(const uint16_t* p) {
-  const uint2 v = *reinterpret_cast<const uint2*>(p);
-  bf16x4 r;
-  r[0] = (short)(v.x & 0xffffu);
-  r[1] = (short)(v.x >> 16);
-  r[2] = (short)(v.y & 0xffffu);
-  r[3] = (short)(v.y >> 16);
-  return r;
+// Eight BF16 values from 16 aligned bytes (LDS).
+__device__ inline bf16x8 load8(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
 }
 
 }  // namespace
@@ -95,95 +96,201 @@ __global__ void k_net_input(const float4* __restrict__ left4, const float4* __re
 
 // Pixels per wave in the forward and input-gradient convolutions: kSegs
 // segments of 16 consecutive pixels of one row, each weight fragment loaded
-// once and used for all of them.
-constexpr int kSegs = 4;
+// once and used for all of them; kConvRows rows (waves) per workgroup.
+constexpr int kSegs = kConvSegs;
 
-// Patch of a pixel-major BF16 map with C channels that a workgroup's four
-// rows v0..v0+3 of one run of kSegs x 16 columns read through 3x3 taps: rows
-// v0-1..v0+4, columns u0-1..u0+16 kSegs, zero outside the image, a pixel's
-// channels kPatchPad elements apart (the 16 pixels of a fragment then fall in
-// distinct LDS banks).  Coalesced 16-byte loads, 8-byte LDS stores.
+// Patch of a pixel-major BF16 map with C channels that a workgroup's rows
+// v0..v0+kConvRows-1 of one run of kSegs x 16 columns read through 3x3 taps:
+// rows v0-1..v0+kConvRows, columns u0-1..u0+16 kSegs, zero outside the image,
+// pixels C + kPatchPad elements apart (16-byte aligned, and the 16 pixels of
+// a fragment start in distinct groups of four LDS banks).  Coalesced 16-byte
+// loads, 8-byte LDS stores.
 constexpr int kPatchW = 16 * kSegs + 2;
-constexpr int kPatchR = 4 + 2;
-constexpr int kPatchPad = 4;
+constexpr int kPatchR = kConvRows + 2;
+constexpr int kPatchPad = 8;
 
 template <int C>
-__device__ inline void stage_patch(const uint16_t* __restrict__ src, int W, int H, int u0, int v0,
-                                   uint16_t* patch) {
-  constexpr int kPS = C + kPatchPad;
-  constexpr int kPieces = C / 8;
-  for (int i = threadIdx.x; i < kPatchR * kPatchW * kPieces; i += blockDim.x) {
-    const int pc = i % kPieces, px = i / kPieces;
-    const int col = px % kPatchW, row = px / kPatchW;
-    const int yy = v0 - 1 + row, xx = u0 - 1 + col;
-    uint4 val = make_uint4(0u, 0u, 0u, 0u);
-    if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-      val = *reinterpret_cast<const uint4*>(src + ((size_t)yy * W + xx) * C + pc * 8);
-    uint2* dst = reinterpret_cast<uint2*>(patch + (size_t)px * kPS + pc * 8);
-    dst[0] = make_uint2(val.x, val.y);
-    dst[1] = make_uint2(val.z, val.w);
+struct PatchStage {
+  static constexpr int kPS = C + kPatchPad;
+  static constexpr int kPieces = C / 8, kTotal = kPatchR * kPatchW * kPieces, kPer = (kTotal + kConvThreads - 1) / kConvThreads;
+  uint4 val[kPer];
+  // global loads of this thread's pieces (all issued before any is used)
+  __device__ inline void load(const uint16_t* __restrict__ src, int W, int H, int u0, int v0) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = (int)threadIdx.x + k * kConvThreads;
+      const int pc = i % kPieces, px = i / kPieces;
+      const int col = px % kPatchW, row = px / kPatchW;
+      const int yy = v0 - 1 + row, xx = u0 - 1 + col;
+      val[k] = make_uint4(0u, 0u, 0u, 0u);
+      if (i < kTotal && yy >= 0 && yy < H && xx >= 0 && xx < W)
+        val[k] = *reinterpret_cast<const uint4*>(src + ((size_t)yy * W + xx) * C + pc * 8);
+    }
   }
-}
-
-// A layer's BF16 weights, rows of K elements ([tap][row][K] for 9 x R rows),
-// copied to LDS with rows K+4 elements apart (the 16 rows of a fragment then
-// fall in distinct banks).
-template <int R, int K>
-__device__ inline void stage_weights(const uint16_t* __restrict__ w, uint16_t* ws) {
-  constexpr int kPieces = K / 8;
-  for (int i = threadIdx.x; i < 9 * R * kPieces; i += blockDim.x) {
-    const int row = i / kPieces, pc = i % kPieces;
-    const uint4 val = *reinterpret_cast<const uint4*>(w + (size_t)row * K + pc * 8);
-    uint2* dst = reinterpret_cast<uint2*>(ws + (size_t)row * (K + 4) + pc * 8);
-    dst[0] = make_uint2(val.x, val.y);
-    dst[1] = make_uint2(val.z, val.w);
-  }
-}
-
-// Forward convolution of one layer.  A workgroup takes four rows v0..v0+3 of
-// one run of kSegs x 16 columns: it stages the input patch those rows read and
-// the layer's weights in LDS, then each wave computes one row of the run (all
-// output channels) from LDS fragments.  Bias, then ReLU and BF16 (hidden layers) or FP32 output
-// (last layer).
-template <int CI, int CO, bool LAST>
-__global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w16,
-                                                  const float* __restrict__ bias, int W, int H,
-                                                  uint16_t* __restrict__ xo, float* __restrict__ yo) {
-  constexpr int kPW = kPatchW, kPS = CI + kPatchPad;
-  __shared__ __align__(16) uint16_t patch[kPatchR * kPatchW * kPS];
-  __shared__ __align__(16) uint16_t wsh[9 * CO * (CI + 4)];
-  const int nrun = (W + 16 * kSegs - 1) / (16 * kSegs);
-  const int u0 = (blockIdx.x % nrun) * 16 * kSegs, v0 = (blockIdx.x / nrun) * 4;
-  stage_patch<CI>(x, W, H, u0, v0, patch);
-  stage_weights<CO, CI>(w16, wsh);
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int v = v0 + wv;
-  if (v >= H) return;
-  const int m = lane & 15, kq = (lane >> 4) * 4;
-  f32x4 acc[kSegs][CO / 16];
+  __device__ inline void store(uint16_t* patch) const {
 #pragma unroll
-  for (int sg = 0; sg < kSegs; ++sg)
-#pragma unroll
-    for (int nb = 0; nb < CO / 16; ++nb) acc[sg][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int tap = 0; tap < 9; ++tap) {
-    const int prow = wv + tap / 3;  // patch row of image row v + tap/3 - 1
-#pragma unroll
-    for (int cb = 0; cb < CI / 16; ++cb) {
-      bf16x4 b[CO / 16];
-#pragma unroll
-      for (int nb = 0; nb < CO / 16; ++nb) b[nb] = load4(wsh + (tap * CO + nb * 16 + m) * (CI + 4) + cb * 16 + kq);
-#pragma unroll
-      for (int sg = 0; sg < kSegs; ++sg) {
-        // patch column of image column u0 + 16 sg + m + tap%3 - 1
-        const bf16x4 a = load4(patch + ((size_t)prow * kPW + sg * 16 + m + tap % 3) * kPS + cb * 16 + kq);
-#pragma unroll
-        for (int nb = 0; nb < CO / 16; ++nb)
-          acc[sg][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[nb], acc[sg][nb], 0, 0, 0);
+    for (int k = 0; k < kPer; ++k) {
+      const int i = (int)threadIdx.x + k * kConvThreads;
+      if (i < kTotal) {
+        const int pc = i % kPieces, px = i / kPieces;
+        uint2* dst = reinterpret_cast<uint2*>(patch + (size_t)px * kPS + pc * 8);
+        dst[0] = make_uint2(val[k].x, val[k].y);
+        dst[1] = make_uint2(val[k].z, val[k].w);
       }
     }
   }
+};
+
+// A layer's BF16 weights ([tap][n][k] for N rows n of K elements k) copied to
+// LDS in the order the K = 32 fragments read them: element (tap, n, k), at
+// position j = tap K + k of the product's K dimension, goes to
+// [j / 32][n / 16][(j % 32) / 8][n % 16][j % 8], so the 64 lanes of a wave read
+// one fragment as 1 KB of consecutive bytes.  Chunks past 9 K (K = 16: the
+// last chunk's second half) are zero.
+template <int N, int K, int THREADS = kConvThreads>
+struct WeightStage {
+  static constexpr int kChunks = (9 * K + 31) / 32, kTotal = kChunks * 32 * N / 8, kPer = (kTotal + THREADS - 1) / THREADS;
+  uint4 val[kPer];
+  __device__ inline void load(const uint16_t* __restrict__ w) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = (int)threadIdx.x + k * THREADS;
+      // piece i of the fragment order: chunk c, block nb, lane group g, row m
+      const int m = i % 16, g = (i / 16) % 4, nb = (i / 64) % (N / 16), c = i / (64 * (N / 16));
+      const int j = c * 32 + g * 8, n = nb * 16 + m;
+      val[k] = make_uint4(0u, 0u, 0u, 0u);
+      if (i < kTotal && j < 9 * K) {
+        const int tap = j / K, kk = j % K;
+        val[k] = *reinterpret_cast<const uint4*>(w + ((size_t)tap * N + n) * K + kk);
+      }
+    }
+  }
+  __device__ inline void store(uint16_t* ws) const {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = (int)threadIdx.x + k * THREADS;
+      if (i < kTotal) *reinterpret_cast<uint4*>(ws + (size_t)i * 8) = val[k];
+    }
+  }
+};
+
+// LDS of a forward or input-gradient workgroup: the input patch (CP
+// channels) and the weights (N outputs) while the products run, then every
+// wave's block of 16 kSegs pixels x N channels (rows N + 8 elements apart, so
+// the four pixel rows a write instruction touches fall in distinct banks) for
+// coalesced 16-byte stores.
+template <int CP, int N>
+struct ConvLds {
+  static constexpr int kPS = CP + kPatchPad;
+  static constexpr int kChunks = (9 * CP + 31) / 32;
+  static constexpr int kPatch = kPatchR * kPatchW * kPS;
+  static constexpr int kW = kChunks * 32 * N;
+  static constexpr int kOS = N + 8;
+  static constexpr int kOut = kConvRows * 16 * kSegs * kOS;
+  static constexpr int kFS = N + 4;                      // FP32 output blocks: floats per pixel row
+  static constexpr int kOutF = 2 * kConvRows * 16 * kSegs * kFS;  // in 16-bit elements
+  static constexpr int kOutMax = kOut > kOutF ? kOut : kOutF;
+  static constexpr int kElems = kPatch + kW > kOutMax ? kPatch + kW : kOutMax;
+};
+
+// Products of a forward (MIRROR false) or input-gradient (MIRROR true)
+// workgroup: stages the patch and the weights, then wave w accumulates row
+// v0 + w of the run: acc[s][nb] = the 16 x 16 block of pixels u0 + 16 s ..
+// and outputs 16 nb .. over K = 9 taps x CP channels, one K = 32 chunk at a
+// time, each weight fragment read once for the row's blocks.  Blocks past the
+// image's last column are skipped.  Ends with a barrier, after which the LDS
+// is free for the output blocks.
+template <int CP, int N, bool MIRROR>
+__device__ inline void conv_products(const uint16_t* __restrict__ src, const uint16_t* __restrict__ w, int W, int H,
+                                     int u0, int v0, uint16_t* smem, f32x4 (&acc)[kSegs][N / 16]) {
+  using Lds = ConvLds<CP, N>;
+  constexpr int kPS = Lds::kPS;
+  uint16_t* patch = smem;
+  uint16_t* wsh = smem + Lds::kPatch;
+  {
+    PatchStage<CP> ps;
+    WeightStage<N, CP> ws;
+    ps.load(src, W, H, u0, v0);
+    ws.load(w);
+    ps.store(patch);
+    ws.store(wsh);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int m = lane & 15, g = lane >> 4;
+  const int live_segs = __builtin_amdgcn_readfirstlane(min(kSegs, (W - u0 + 15) / 16));
+#pragma unroll
+  for (int sg = 0; sg < kSegs; ++sg)
+#pragma unroll
+    for (int nb = 0; nb < N / 16; ++nb) acc[sg][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < Lds::kChunks; ++c) {
+    const int j = c * 32 + g * 8;  // this lane's first K index: tap j / CP, channel j % CP
+    const bool live = j < 9 * CP;
+    const int tap = live ? j / CP : 0, ch = j % CP;
+    bf16x8 b[N / 16];
+#pragma unroll
+    for (int nb = 0; nb < N / 16; ++nb) b[nb] = load8(wsh + ((size_t)((c * (N / 16) + nb) * 4 + g) * 16 + m) * 8);
+    // forward: image row v + tap/3 - 1, column u + tap%3 - 1; input gradient:
+    // the mirrored offset (g at p - offset)
+    const int prow = MIRROR ? wv + 2 - tap / 3 : wv + tap / 3;
+    const int pcol = MIRROR ? 2 - tap % 3 : tap % 3;
+#pragma unroll
+    for (int sg = 0; sg < kSegs; ++sg) {
+      if (sg < live_segs) {
+        bf16x8 a = load8(patch + ((size_t)prow * kPatchW + sg * 16 + m + pcol) * kPS + ch);
+        if (!live) a = bf16x8{};
+#pragma unroll
+        for (int nb = 0; nb < N / 16; ++nb)
+          acc[sg][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[sg][nb], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Forward convolution of one layer.  A workgroup takes kConvRows rows from v0 of
+// one run of kSegs x 16 columns; each wave computes one row of the run (all
+// output channels).  Bias, then ReLU and BF16 (hidden layers) or FP32 output
+// (last layer), through LDS so that every store writes 16 bytes of a pixel.
+template <int CI, int CO, bool LAST>
+__global__ __launch_bounds__(kConvThreads) void k_conv_fwd(const uint16_t* __restrict__ x, const uint16_t* __restrict__ w16,
+                                                  const float* __restrict__ bias, int W, int H,
+                                                  uint16_t* __restrict__ xo, float* __restrict__ yo) {
+  using Lds = ConvLds<CI, CO>;
+  __shared__ __align__(16) uint16_t smem[Lds::kElems];
+  const int nrun = (W + 16 * kSegs - 1) / (16 * kSegs);
+  const int u0 = (blockIdx.x % nrun) * 16 * kSegs, v0 = (blockIdx.x / nrun) * kConvRows;
+  f32x4 acc[kSegs][CO / 16];
+  conv_products<CI, CO, false>(x, w16, W, H, u0, v0, smem, acc);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int v = v0 + wv;
+  const int m = lane & 15, kq = (lane >> 4) * 4;
+  if (LAST) {
+    float* of = reinterpret_cast<float*>(smem) + (size_t)wv * 16 * kSegs * Lds::kFS;
+#pragma unroll
+    for (int nb = 0; nb < CO / 16; ++nb) {
+      const int co = nb * 16 + m;
+      const float bb = bias[co];
+#pragma unroll
+      for (int sg = 0; sg < kSegs; ++sg)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) of[(sg * 16 + kq + i) * Lds::kFS + co] = acc[sg][nb][i] + bb;
+    }
+    __syncthreads();
+    if (v >= H) return;
+    constexpr int kPf = CO / 4;  // 16-byte pieces per pixel
+#pragma unroll
+    for (int k = 0; k < 16 * kSegs * kPf / 64; ++k) {
+      const int q = lane + 64 * k, px = q / kPf, pc = q % kPf;
+      const int u = u0 + px;
+      if (u < W)
+        *reinterpret_cast<float4*>(yo + ((size_t)v * W + u) * CO + pc * 4) =
+            *reinterpret_cast<const float4*>(of + px * Lds::kFS + pc * 4);
+    }
+    return;
+  }
+  uint16_t* ob = smem + (size_t)wv * 16 * kSegs * Lds::kOS;
 #pragma unroll
   for (int nb = 0; nb < CO / 16; ++nb) {
     const int co = nb * 16 + m;
@@ -192,75 +299,68 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ x
     for (int sg = 0; sg < kSegs; ++sg)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int u = u0 + sg * 16 + kq + i;
-        if (u >= W) continue;
-        const size_t p = (size_t)v * W + u;
         const float z = acc[sg][nb][i] + bb;
-        if (LAST)
-          yo[p * CO + co] = z;
-        else
-          xo[p * CO + co] = to_bf16(z > 0.f ? z : 0.f);
+        ob[(sg * 16 + kq + i) * Lds::kOS + co] = to_bf16(z > 0.f ? z : 0.f);
       }
+  }
+  __syncthreads();
+  if (v >= H) return;
+  constexpr int kPc = CO / 8;  // 16-byte pieces per pixel
+#pragma unroll
+  for (int k = 0; k < 16 * kSegs * kPc / 64; ++k) {
+    const int q = lane + 64 * k, px = q / kPc, pc = q % kPc;
+    const int u = u0 + px;
+    if (u < W)
+      *reinterpret_cast<uint4*>(xo + ((size_t)v * W + u) * CO + pc * 8) =
+          *reinterpret_cast<const uint4*>(ob + px * Lds::kOS + pc * 8);
   }
 }
 
 // Gradient of a layer's input: dx(p) = sum over taps and output channels of
-// W[tap][o][i] g(p - offset)[o], then gp = BF16(dx * [x(p) > 0]) (the input
+// W[tap][o][i] g(p - offset)[o], then gp = BF16(dx) * [x(p) > 0] (the input
 // came from a ReLU).  Workgroups as in the forward convolution, with the
-// patch of g (the taps mirrored).
+// patch of g (the taps mirrored) and the weights in [tap][in][out] order;
+// the mask is applied on the 16-byte stores.
 template <int CI, int CO>
-__global__ __launch_bounds__(256) void k_conv_bwd_x(const uint16_t* __restrict__ g, const uint16_t* __restrict__ wt16,
+__global__ __launch_bounds__(kConvThreads) void k_conv_bwd_x(const uint16_t* __restrict__ g, const uint16_t* __restrict__ wt16,
                                                     const uint16_t* __restrict__ x, int W, int H,
                                                     uint16_t* __restrict__ gp) {
-  constexpr int kPW = kPatchW, kPS = CO + kPatchPad;
-  __shared__ __align__(16) uint16_t patch[kPatchR * kPatchW * kPS];
-  __shared__ __align__(16) uint16_t wsh[9 * CI * (CO + 4)];
+  using Lds = ConvLds<CO, CI>;
+  __shared__ __align__(16) uint16_t smem[Lds::kElems];
   const int nrun = (W + 16 * kSegs - 1) / (16 * kSegs);
-  const int u0 = (blockIdx.x % nrun) * 16 * kSegs, v0 = (blockIdx.x / nrun) * 4;
-  stage_patch<CO>(g, W, H, u0, v0, patch);
-  stage_weights<CI, CO>(wt16, wsh);
-  __syncthreads();
+  const int u0 = (blockIdx.x % nrun) * 16 * kSegs, v0 = (blockIdx.x / nrun) * kConvRows;
+  f32x4 acc[kSegs][CI / 16];
+  conv_products<CO, CI, true>(g, wt16, W, H, u0, v0, smem, acc);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int v = v0 + wv;
-  if (v >= H) return;
   const int m = lane & 15, kq = (lane >> 4) * 4;
-  f32x4 acc[kSegs][CI / 16];
+  uint16_t* ob = smem + (size_t)wv * 16 * kSegs * Lds::kOS;
 #pragma unroll
-  for (int sg = 0; sg < kSegs; ++sg)
-#pragma unroll
-    for (int nb = 0; nb < CI / 16; ++nb) acc[sg][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int tap = 0; tap < 9; ++tap) {
-    const int prow = wv + 2 - tap / 3;  // patch row of image row v - (tap/3 - 1)
-#pragma unroll
-    for (int cb = 0; cb < CO / 16; ++cb) {
-      bf16x4 b[CI / 16];
-#pragma unroll
-      for (int nb = 0; nb < CI / 16; ++nb) b[nb] = load4(wsh + (tap * CI + nb * 16 + m) * (CO + 4) + cb * 16 + kq);
-#pragma unroll
-      for (int sg = 0; sg < kSegs; ++sg) {
-        // patch column of image column u0 + 16 sg + m - (tap%3 - 1)
-        const bf16x4 a = load4(patch + ((size_t)prow * kPW + sg * 16 + m + 2 - tap % 3) * kPS + cb * 16 + kq);
-#pragma unroll
-        for (int nb = 0; nb < CI / 16; ++nb)
-          acc[sg][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[nb], acc[sg][nb], 0, 0, 0);
-      }
-    }
-  }
-#pragma unroll
-  for (int nb = 0; nb < CI / 16; ++nb) {
-    const int ci = nb * 16 + m;
+  for (int nb = 0; nb < CI / 16; ++nb)
 #pragma unroll
     for (int sg = 0; sg < kSegs; ++sg)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int u = u0 + sg * 16 + kq + i;
-        if (u >= W) continue;
-        const size_t p = (size_t)v * W + u;
-        const uint16_t xv = x[p * CI + ci];
-        const bool pos = (xv & 0x8000u) == 0 && xv != 0;
-        gp[p * CI + ci] = to_bf16(pos ? acc[sg][nb][i] : 0.f);
-      }
+      for (int i = 0; i < 4; ++i) ob[(sg * 16 + kq + i) * Lds::kOS + nb * 16 + m] = to_bf16(acc[sg][nb][i]);
+  __syncthreads();
+  if (v >= H) return;
+  constexpr int kPc = CI / 8;
+#pragma unroll
+  for (int k = 0; k < 16 * kSegs * kPc / 64; ++k) {
+    const int q = lane + 64 * k, px = q / kPc, pc = q % kPc;
+    const int u = u0 + px;
+    if (u < W) {
+      const size_t o = ((size_t)v * W + u) * CI + pc * 8;
+      const uint4 xv = *reinterpret_cast<const uint4*>(x + o);
+      uint4 d = *reinterpret_cast<const uint4*>(ob + px * Lds::kOS + pc * 8);
+      // BF16 x > 0: sign bit clear and not zero, per 16-bit half
+      auto mask = [](uint32_t xw, uint32_t dw) {
+        const uint32_t lo = ((xw & 0x8000u) == 0u && (xw & 0xffffu) != 0u) ? 0xffffu : 0u;
+        const uint32_t hi = ((xw & 0x80000000u) == 0u && (xw >> 16) != 0u) ? 0xffff0000u : 0u;
+        return dw & (lo | hi);
+      };
+      d.x = mask(xv.x, d.x); d.y = mask(xv.y, d.y); d.z = mask(xv.z, d.z); d.w = mask(xv.w, d.w);
+      *reinterpret_cast<uint4*>(gp + o) = d;
+    }
   }
 }
 

@@ -48,7 +48,7 @@ class lexp_schedule(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("cell", C.c_int32 * 4), ("k_prop", C.c_int32 * 4),
                 ("k_rand", C.c_int32 * 4), ("iterations", C.c_int32), ("k_rans", C.c_int32 * 4),
                 ("learned", C.c_int32), ("batch_cycle", C.c_int32), ("tile_cols", C.c_int32 * 4),
-                ("tile_fill", C.c_int32 * 4)]
+                ("tile_fill", C.c_int32 * 4), ("speculate", C.c_int32)]
 
 
 class lexp_stats(C.Structure):
@@ -61,7 +61,9 @@ class lexp_stats(C.Structure):
                 ("device_cut_block", C.c_int32 * 4), ("device_cut_relabel", C.c_int32 * 4),
                 ("unary_timed_launches", C.c_int64), ("unary_timed_alg_bytes", C.c_double),
                 ("unary_timed_evals", C.c_int64), ("host_solve_level_ms", C.c_double * 4),
-                ("host_solves", C.c_int64 * 4)]
+                ("host_solves", C.c_int64 * 4), ("unary_level_ms", C.c_double * 4),
+                ("unary_level_alg_bytes", C.c_double * 4), ("unary_level_launches", C.c_int64 * 4),
+                ("spec_steps", C.c_int64), ("spec_misses", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -71,6 +73,8 @@ class lexp_stats(C.Structure):
         d["device_cut_relabel"] = list(d["device_cut_relabel"])
         d["host_solve_level_ms"] = list(d["host_solve_level_ms"])
         d["host_solves"] = list(d["host_solves"])
+        for k in ("unary_level_ms", "unary_level_alg_bytes", "unary_level_launches"):
+            d[k] = list(d[k])
         return d
 
 
@@ -337,9 +341,11 @@ def lexp_init_labels(ctx, seed, labels, stream=None):
     _check(load_library().lexp_init_labels(ctx.handle, C.c_uint64(seed), lp, _stream_ptr(stream)))
 
 
-def make_schedule(grids, iterations, learned=False, batch_cycle=False, tiles=None) -> lexp_schedule:
+def make_schedule(grids, iterations, learned=False, batch_cycle=False, tiles=None, speculate=False) -> lexp_schedule:
     """grids: (cell, K_prop, K_rand) or (cell, K_prop, K_rand, K_RANS) per level;
-    tiles: None or one (widest column strip, fill) per level (0: default)."""
+    tiles: None or one (widest column strip, fill) per level (0: default);
+    speculate: evaluate each step's two possible successors while the host
+    cuts it (single-part groups; the same results either way)."""
     s = lexp_schedule()
     if not 1 <= len(grids) <= 4:
         raise ValueError("1 to 4 grid levels")
@@ -350,6 +356,7 @@ def make_schedule(grids, iterations, learned=False, batch_cycle=False, tiles=Non
     s.iterations = int(iterations)
     s.learned = 1 if learned else 0
     s.batch_cycle = 1 if batch_cycle else 0
+    s.speculate = 1 if speculate and not batch_cycle else 0
     if tiles is not None:
         if len(tiles) != len(grids):
             raise ValueError("one tile plan per grid level")
@@ -359,12 +366,12 @@ def make_schedule(grids, iterations, learned=False, batch_cycle=False, tiles=Non
 
 
 def lexp_optimize(ctx, grids, iterations, seed, labels, cur_cost, stream=None, learned=False, batch_cycle=False,
-                  tiles=None):
+                  tiles=None, speculate=False):
     """Alg. 2 on the device + host; returns (energy_trace, time_trace)."""
     torch = _torch()
     lp = _dev(labels, torch.float32, (ctx.height, ctx.width, 4), name="labels")
     cp = _dev(cur_cost, torch.float32, (ctx.height, ctx.width), name="cur_cost")
-    sch = make_schedule(grids, iterations, learned, batch_cycle, tiles)
+    sch = make_schedule(grids, iterations, learned, batch_cycle, tiles, speculate)
     e = np.zeros(iterations + 1)
     t = np.zeros(iterations + 1)
     _check(load_library().lexp_optimize(ctx.handle, C.byref(sch), C.c_uint64(seed), lp, cp, e.ctypes.data,
@@ -373,7 +380,7 @@ def lexp_optimize(ctx, grids, iterations, seed, labels, cur_cost, stream=None, l
 
 
 def lexp_optimize_batch(ctxs, grids, iterations, seeds, labels, cur_costs, stream=None, learned=False,
-                        batch_cycle=False, tiles=None):
+                        batch_cycle=False, tiles=None, speculate=False):
     """Alg. 2 for several pairs at once (one launch per group step for all of
     them); returns (energy traces [n_pairs, iterations+1], time_trace)."""
     torch = _torch()
@@ -386,7 +393,7 @@ def lexp_optimize_batch(ctxs, grids, iterations, seeds, labels, cur_costs, strea
     cp = (C.c_void_p * n)(*[_dev(q, torch.float32, (c.height, c.width), name="cur_cost")
                             for c, q in zip(ctxs, cur_costs)])
     sd = (C.c_uint64 * n)(*[int(x) for x in seeds])
-    sch = make_schedule(grids, iterations, learned, batch_cycle, tiles)
+    sch = make_schedule(grids, iterations, learned, batch_cycle, tiles, speculate)
     e = np.zeros((n, iterations + 1))
     ep = (C.c_void_p * n)(*[e[i].ctypes.data for i in range(n)])
     t = np.zeros(iterations + 1)

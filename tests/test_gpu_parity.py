@@ -731,18 +731,24 @@ def test_optimize_batch_rejects_mixed_radius_and_shared_buffers(tiny):
 def test_sampled_timing_counts_every_launch_and_times_every_nth(tiny):
     """lexp_set_timing(ctx, N): every fused launch is counted, every N-th is
     timed (events at the kernel's own start and end), with its bytes and
-    evaluations; N = 1 times them all; negative periods are refused."""
+    evaluations, also per grid level; N = 1 times them all; negative periods
+    are refused."""
     P = tiny
     lab = torch.zeros((P.H, P.W, 4), device="cuda")
     cost = torch.zeros((P.H, P.W), device="cuda")
     for every in (1, 3):
         L.lexp_set_timing(P.ctx, every)
         L.lexp_reset_stats(P.ctx)
-        L.lexp_optimize(P.ctx, [(5, 1, 3)], 1, 0, lab, cost)
+        L.lexp_optimize(P.ctx, [(5, 1, 3), (10, 1, 3)], 1, 0, lab, cost)
         st = L.lexp_get_stats(P.ctx)
         n = st["unary_launches"]
         assert n > 0 and st["unary_timed_launches"] == (n + every - 1) // every
         assert st["unary_kernel_ms"] > 0
+        # the timed launches split by grid level (two levels here)
+        assert sum(st["unary_level_launches"]) == st["unary_timed_launches"]
+        assert all(x > 0 for x in st["unary_level_launches"][:2]) and st["unary_level_launches"][2:] == [0, 0]
+        assert sum(st["unary_level_ms"]) == pytest.approx(st["unary_kernel_ms"], rel=1e-9)
+        assert sum(st["unary_level_alg_bytes"]) == pytest.approx(st["unary_timed_alg_bytes"], rel=1e-12)
         if every == 1:
             assert st["unary_timed_alg_bytes"] == st["unary_alg_bytes"]
             assert st["unary_timed_evals"] == st["unary_evals"]
