@@ -66,14 +66,15 @@ def _traffic_from_profile():
         return None
 
 
-def run_gpu(steps: int, warmup: int, seed: int = 0, k_rans: int = 0, name: str = WORKLOAD, speculate: bool = False):
+def run_gpu(steps: int, warmup: int, seed: int = 0, k_rans: int = 0, name: str = WORKLOAD, speculate: bool = False,
+            host_threads: int = 0):
     import torch
 
     import paper_1603_08328_amd.lexp as L
     from synth import make_workload_pair, params_for, workload
 
     wl = workload(name)
-    prm = params_for(name)
+    prm = dict(params_for(name), host_threads=host_threads)  # 0: one per CPU the process may run on
     pair = make_workload_pair(name)
     dev = torch.device("cuda:0")
     left = torch.from_numpy(pair.left).to(dev)
@@ -555,6 +556,8 @@ def main():
                     help="instead: the oracle's whole run on 450x375 on the host cores, energy against time")
     ap.add_argument("--speculate", action="store_true",
                     help="single-part groups: evaluate each step's two possible successors while the host cuts it")
+    ap.add_argument("--host-threads", type=int, default=0,
+                    help="host max-flow threads (0: one per CPU the process may run on)")
     ap.add_argument("--k-rans", type=int, default=0,
                     help="RANSAC proposer steps per cell and level (Alg. 1; 0 in the workload as specified)")
     args = ap.parse_args()
@@ -599,7 +602,8 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-    g = run_gpu(args.steps, args.warmup, k_rans=args.k_rans, name=args.workload, speculate=args.speculate)
+    g = run_gpu(args.steps, args.warmup, k_rans=args.k_rans, name=args.workload, speculate=args.speculate,
+                host_threads=args.host_threads)
     ms = g["elapsed"] / args.steps * 1e3
     value = g["evals"] / g["elapsed"] / 1e9
     achieved = g["kernel_bytes"] / (g["kernel_ms"] / 1e3) / 1e9 if g["kernel_ms"] > 0 else 0.0
@@ -645,7 +649,7 @@ def main():
         "energy_trace": [round(x, 3) for x in g["energy"]],
         "time_trace_s": [round(x, 4) for x in g["times"]],
         "kernel_evals_per_s": (g["kernel_evals"] / (g["kernel_ms"] / 1e3) / 1e9) if g["kernel_ms"] > 0 else None,
-        "host_threads": len(os.sched_getaffinity(0)), "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+        "host_threads": args.host_threads or len(os.sched_getaffinity(0)), "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
         "host_cut_ms_per_step": g["stats"]["host_cut_ms"],
         "host_wait_ms_per_step": g["stats"]["host_wait_ms"],
         "host_enqueue_ms_per_step": g["stats"]["host_enqueue_ms"],
