@@ -251,10 +251,11 @@ lexp_status lexp_pairwise(lexp_ctx* ctx, int32_t pu, int32_t pv, int32_t qu, int
 lexp_status lexp_energy(lexp_ctx* ctx, const float* labels, const float* cur_cost, double* total,
                         double* unary, double* pairwise, void* hip_stream);
 
-/* lexp_energy for callers that cannot allocate memory (code under HIP graph
- * capture, tight serving loops, harnesses that forbid hipMalloc): the same
- * arguments, the same values bit for bit (the same per-block partial sums,
- * added in the same order), and no allocation of any kind.  The partial sums
+/* lexp_energy for callers that cannot allocate memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments, the same values bit
+ * for bit (the same per-block partial sums, added in the same order), and no
+ * allocation of any kind.  (It copies the totals to the host and waits for
+ * them, so it is not for a stream under HIP graph capture.)  The partial sums
  * and totals live in a fixed device array of the library, one per GPU, held
  * from the first lexp_create on that GPU until the process ends (about
  * 128 KB).  Images of at most LEXP_NOALLOC_MAX_PIXELS pixels (LEXP_EINVAL
