@@ -96,17 +96,22 @@ struct DevBuf {
   }
 };
 
-// grow-only pinned host buffer
+// grow-only pinned host buffer; `coherent` ones are read and written by
+// kernels in place (fine-grained: the device caches none of it, so host
+// stores made before a launch are what the kernel reads, and the kernel's
+// stores are what the host reads after waiting for it)
 template <class T>
 struct PinBuf {
   T* p = nullptr;
   size_t cap = 0;
+  bool coherent = false;
   hipError_t ensure(size_t n) {
     if (n <= cap) return hipSuccess;
     if (p) (void)hipHostFree(p);
     p = nullptr;
     cap = 0;
-    hipError_t e = hipHostMalloc((void**)&p, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault);
+    const unsigned flags = coherent ? (hipHostMallocMapped | hipHostMallocCoherent) : hipHostMallocDefault;
+    hipError_t e = hipHostMalloc((void**)&p, std::max<size_t>(n, 1) * sizeof(T), flags);
     if (e == hipSuccess) cap = n;
     return e;
   }
@@ -1367,10 +1372,11 @@ lexp_status part_device_work(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const P
     B.cut_every = shape.every;
     HIP_TRY(hipMemcpyAsync(B.h_res.p, B.d_res.p, 4 + 4 * c->res_items + (size_t)P.n_px, hipMemcpyDeviceToHost, s));
   } else {
+    // the terms go straight to the host's pinned buffer (the kernel writes
+    // through PCIe; no copy of its own), flag first
     hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, d_pairs, B.d_items.p,
-                       phi, B.d_terms.p + 1, B.d_terms.p);
+                       phi, B.h_terms.p + 1, B.h_terms.p);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(B.h_terms.p, B.d_terms.p, sizeof(int) * (1 + 5 * P.n_px), hipMemcpyDeviceToHost, s));
   }
   return LEXP_OK;
 }
@@ -1444,7 +1450,8 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
   const int nf = c->dp.nf;
   const int* terms = B.h_terms.p + 1;
   uint8_t* xs = dev ? B.h_res.p + 4 + 4 * c->res_items : B.h_x.p;
-  uint8_t* d_xs = dev ? B.d_res.p + 4 + 4 * c->res_items : B.d_x.p;
+  // (host cuts: the label update reads the cut from the host's pinned buffer)
+  uint8_t* d_xs = dev ? B.d_res.p + 4 + 4 * c->res_items : B.h_x.p;
   std::vector<int> host_cut;  // device path: regions the kernel left to the host
   if (dev) {
     const int* status = reinterpret_cast<const int*>(B.h_res.p) + 1;
@@ -1489,9 +1496,7 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
     if (next_step >= 0) propose_item(P, a, i, next_step);
   });
   const auto t2 = std::chrono::steady_clock::now();
-  if (!dev) {
-    HIP_TRY(hipMemcpyAsync(B.d_x.p, B.h_x.p, (size_t)P.n_px, hipMemcpyHostToDevice, s));
-  } else {
+  if (dev) {
     for (int i : host_cut) {
       const Item& it = P.items[i];
       HIP_TRY(hipMemcpyAsync(d_xs + it.aux_off, xs + it.aux_off, (size_t)it.rw * it.rh, hipMemcpyHostToDevice, s));
@@ -1927,6 +1932,8 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     HIP_TRY(B.d_x.ensure((size_t)max_px));
     HIP_TRY(B.d_res.ensure(4 + 4 * max_items + (size_t)max_px));
     HIP_TRY(B.h_items.ensure(max_items));
+    B.h_terms.coherent = true;  // written by k_graph_terms in place (host cuts)
+    B.h_x.coherent = true;      // read by k_apply in place (host cuts)
     HIP_TRY(B.h_terms.ensure(1 + (size_t)max_px * 5));
     HIP_TRY(B.h_x.ensure((size_t)max_px));
     HIP_TRY(B.h_res.ensure(4 + 4 * max_items + (size_t)max_px));
@@ -1936,6 +1943,7 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     B.cut_timed = false;
     HIP_TRY(hipMemsetAsync(B.d_terms.p, 0, sizeof(int), s));  // overflow flags
     HIP_TRY(hipMemsetAsync(B.d_res.p, 0, sizeof(int), s));
+    B.h_terms.p[0] = 0;  // (the host path's flag, written by the device in place)
   }
 
   // Alg. 2, initialisation: random labels and their per-pixel costs.
