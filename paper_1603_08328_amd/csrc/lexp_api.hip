@@ -1356,21 +1356,22 @@ lexp_status part_device_work(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const P
     if (st) return st;
   }
   if (P.device_cut) {
-    int* flag = reinterpret_cast<int*>(B.d_res.p);
+    // the flag, the regions' status and their cuts go straight to the host's
+    // pinned result buffer (no copy of their own)
+    int* flag = reinterpret_cast<int*>(B.h_res.p);
     hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, d_pairs, B.d_items.p,
                        phi, B.d_terms.p + 1, flag);
     HIP_TRY(hipGetLastError());
     bool timed = false;
     const CutShape shape = tuner ? tuner->pick(c, P.max_px, &timed) : CutShape{};
     if (timed) HIP_TRY(hipEventRecord(B.cut0, s));
-    if ((st = launch_cut(c, B.d_items.p, n, B.d_terms.p + 1, B.d_res.p + 4 + 4 * c->res_items, flag + 1, P.max_px, s,
+    if ((st = launch_cut(c, B.d_items.p, n, B.d_terms.p + 1, B.h_res.p + 4 + 4 * c->res_items, flag + 1, P.max_px, s,
                          shape)))
       return st;
     if (timed) HIP_TRY(hipEventRecord(B.cut1, s));
     B.cut_timed = timed;
     B.cut_block = shape.block;
     B.cut_every = shape.every;
-    HIP_TRY(hipMemcpyAsync(B.h_res.p, B.d_res.p, 4 + 4 * c->res_items + (size_t)P.n_px, hipMemcpyDeviceToHost, s));
   } else {
     // the terms go straight to the host's pinned buffer (the kernel writes
     // through PCIe; no copy of its own), flag first
@@ -1449,9 +1450,8 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
   if (flag) return fail(LEXP_EINVAL, "binary-problem term exceeds 2^30 quanta (parameters too large)");
   const int nf = c->dp.nf;
   const int* terms = B.h_terms.p + 1;
+  // the cut, in the host's pinned buffer, which the label update reads in place
   uint8_t* xs = dev ? B.h_res.p + 4 + 4 * c->res_items : B.h_x.p;
-  // (host cuts: the label update reads the cut from the host's pinned buffer)
-  uint8_t* d_xs = dev ? B.d_res.p + 4 + 4 * c->res_items : B.h_x.p;
   std::vector<int> host_cut;  // device path: regions the kernel left to the host
   if (dev) {
     const int* status = reinterpret_cast<const int*>(B.h_res.p) + 1;
@@ -1496,13 +1496,7 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
     if (next_step >= 0) propose_item(P, a, i, next_step);
   });
   const auto t2 = std::chrono::steady_clock::now();
-  if (dev) {
-    for (int i : host_cut) {
-      const Item& it = P.items[i];
-      HIP_TRY(hipMemcpyAsync(d_xs + it.aux_off, xs + it.aux_off, (size_t)it.rw * it.rh, hipMemcpyHostToDevice, s));
-    }
-  }
-  hipLaunchKernelGGL(lexp::k_apply, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, d_pairs, B.d_items.p, d_xs,
+  hipLaunchKernelGGL(lexp::k_apply, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, d_pairs, B.d_items.p, xs,
                      P.phi_ext ? P.phi_ext : B.d_phi.p);
   HIP_TRY(hipGetLastError());
   const auto t3 = std::chrono::steady_clock::now();
@@ -1934,6 +1928,7 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     HIP_TRY(B.h_items.ensure(max_items));
     B.h_terms.coherent = true;  // written by k_graph_terms in place (host cuts)
     B.h_x.coherent = true;      // read by k_apply in place (host cuts)
+    B.h_res.coherent = true;    // written by k_graph_terms and the device max-flow, read by k_apply, in place
     HIP_TRY(B.h_terms.ensure(1 + (size_t)max_px * 5));
     HIP_TRY(B.h_x.ensure((size_t)max_px));
     HIP_TRY(B.h_res.ensure(4 + 4 * max_items + (size_t)max_px));
@@ -1943,7 +1938,8 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     B.cut_timed = false;
     HIP_TRY(hipMemsetAsync(B.d_terms.p, 0, sizeof(int), s));  // overflow flags
     HIP_TRY(hipMemsetAsync(B.d_res.p, 0, sizeof(int), s));
-    B.h_terms.p[0] = 0;  // (the host path's flag, written by the device in place)
+    B.h_terms.p[0] = 0;  // (the flags of both paths, written by the device in place)
+    reinterpret_cast<int*>(B.h_res.p)[0] = 0;
   }
 
   // Alg. 2, initialisation: random labels and their per-pixel costs.
