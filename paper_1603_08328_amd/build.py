@@ -3,7 +3,7 @@ the host-only pieces (random numbers, proposers, max-flow, thread pool) with
 g++.  Every call compiles from scratch.
 
 Device code: -O3, -ffp-contract=off (fused multiply-adds only where fmaf() is
-written), packed FP32 instructions disabled.  Host code: -O2 -ffp-contract=off
+written), packed FP32 instructions disabled.  Host code: -O3 -ffp-contract=off
 so the double-precision proposer arithmetic is rounded as written.
 """
 from __future__ import annotations
@@ -42,7 +42,7 @@ def build(verbose: bool = False, csrc: str = CSRC, out: str = LIB) -> str:
     tmp = tempfile.mkdtemp(prefix="lexp_build_")
     try:
         host_obj = os.path.join(tmp, "lexp_host.o")
-        _run(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+        _run(["g++", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
               "-I", INCLUDE, "-c", os.path.join(csrc, "lexp_host.cpp"), "-o", host_obj], verbose)
         objs = [host_obj]
         for src in ("lexp_kernels.hip", "lexp_cut.hip", "lexp_post.hip", "lexp_net.hip", "lexp_api.hip"):
