@@ -183,16 +183,16 @@ struct lexp_ctx {
   // the device evaluates the other)
   // Buffers of one part of a group in flight in lexp_optimize.  terms[0] is
   // the overflow flag of the graph terms (cleared once per run, never reset by
-  // a step), the terms of the part follow from terms[1].  With the device cut
-  // the result buffer holds the flag, a status per region and the cut
-  // (x, one byte per pixel), and one copy brings them to the host; on the host
-  // path one copy brings the flag and the terms.
+  // a step), the terms of the part follow from terms[1].  On the host path
+  // k_graph_terms writes the flag and the terms straight into h_terms, and
+  // k_apply reads the host's cut from h_x; with the device cut the terms stay
+  // in d_terms and the device writes the flag, a status per region and the
+  // cut (x, one byte per pixel) straight into h_res, which k_apply reads.
+  // Those three host buffers are coherent pinned memory (no copies).
   struct PartBuf {
     DevBuf<Item> d_items;
     DevBuf<float> d_phi;
     DevBuf<int> d_terms;
-    DevBuf<uint8_t> d_x;
-    DevBuf<unsigned char> d_res;
     PinBuf<Item> h_items;
     PinBuf<int> h_terms;
     PinBuf<uint8_t> h_x;
@@ -928,7 +928,7 @@ lexp_status lexp_destroy(lexp_ctx* c) {
       B.h_sitems[i].release(); B.h_stiles[i].release();
     }
   for (auto& b : c->part) {
-    b.d_items.release(); b.d_phi.release(); b.d_terms.release(); b.d_x.release(); b.d_res.release();
+    b.d_items.release(); b.d_phi.release(); b.d_terms.release();
     b.h_items.release(); b.h_terms.release(); b.h_x.release(); b.h_res.release();
     if (b.ready) (void)hipEventDestroy(b.ready);
     if (b.cut0) (void)hipEventDestroy(b.cut0);
@@ -1341,9 +1341,9 @@ void propose_item(Part& P, const StepArgs& a, int q, int step) {
   item.c = al[2];
 }
 
-// A part's items (with their candidates already proposed), cost kernel, graph
-// terms and the copy of the terms (or of the device cut) to the host, all
-// queued on the stream.
+// A part's items (with their candidates already proposed), cost kernel and
+// graph terms (and the device cut), all queued on the stream; the terms (or
+// the device's cuts) land in the host's pinned buffers.
 lexp_status part_device_work(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairDev* d_pairs, const Tile* d_tiles,
                              CutTuner* tuner, hipStream_t s) {
   const int n = (int)P.items.size();
@@ -1385,8 +1385,8 @@ lexp_status part_device_work(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const P
 // Queues one step of a part: its items (candidates already proposed) go to
 // the pinned staging buffer, then the device work.  In graph mode the device
 // work of the part's current split is captured once into a HIP graph (the
-// items copy from the same pinned buffer, the kernels, the copy back) and
-// replayed for every candidate step.
+// items copy from the same pinned buffer and the kernels) and replayed for
+// every candidate step.
 lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairDev* d_pairs, const Tile* d_tiles,
                          bool use_graph, CutTuner* tuner, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -1923,8 +1923,6 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     HIP_TRY(B.d_items.ensure(max_items));
     HIP_TRY(B.d_phi.ensure((size_t)max_px));
     HIP_TRY(B.d_terms.ensure(1 + (size_t)max_px * 5));
-    HIP_TRY(B.d_x.ensure((size_t)max_px));
-    HIP_TRY(B.d_res.ensure(4 + 4 * max_items + (size_t)max_px));
     HIP_TRY(B.h_items.ensure(max_items));
     B.h_terms.coherent = true;  // written by k_graph_terms in place (host cuts)
     B.h_x.coherent = true;      // read by k_apply in place (host cuts)
@@ -1936,9 +1934,7 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     if (!B.cut0) HIP_TRY(hipEventCreate(&B.cut0));
     if (!B.cut1) HIP_TRY(hipEventCreate(&B.cut1));
     B.cut_timed = false;
-    HIP_TRY(hipMemsetAsync(B.d_terms.p, 0, sizeof(int), s));  // overflow flags
-    HIP_TRY(hipMemsetAsync(B.d_res.p, 0, sizeof(int), s));
-    B.h_terms.p[0] = 0;  // (the flags of both paths, written by the device in place)
+    B.h_terms.p[0] = 0;  // the overflow flags of both paths, written by the device in place
     reinterpret_cast<int*>(B.h_res.p)[0] = 0;
   }
 
