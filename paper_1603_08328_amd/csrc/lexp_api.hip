@@ -227,7 +227,11 @@ struct lexp_ctx {
 struct lexp_net {
   static constexpr int kLayers = 5;
   static constexpr int kCh[kLayers + 1] = {16, 32, 32, 32, 32, 16};
-  static constexpr int kChunk = 4096;  // pixels per weight-gradient partial sum
+  // weight-gradient partial sums (one per chunk of kWgRows rows x kWgTiles
+  // tiles of 32 columns) of an image
+  static int grad_chunks(int W, int H) {
+    return ((H + lexp::kWgRows - 1) / lexp::kWgRows) * (((W + 31) / 32 + lexp::kWgTiles - 1) / lexp::kWgTiles);
+  }
   int max_w = 0, max_h = 0;
   size_t w_off[kLayers] = {}, b_off[kLayers] = {}, n_prm = 0;  // parameter layout: per layer [w][b]
   size_t w16_off[kLayers] = {}, n_w16 = 0;
@@ -1191,12 +1195,12 @@ lexp_status net_forward(lexp_net* net, lexp_ctx* c, const float* labels, hipStre
 // Weight and bias gradients of layer l from the gradient g of its output.
 template <int CI, int CO>
 void net_weight_grad(lexp_net* net, int l, const uint16_t* g, int W, int H, hipStream_t s) {
-  const int n = W * H, chunks = (n + lexp_net::kChunk - 1) / lexp_net::kChunk;
-  hipLaunchKernelGGL((lexp::k_conv_bwd_w<CI, CO>), dim3(chunks, 9), dim3(256), 0, s, g, net->act[l], W, H,
-                     lexp_net::kChunk, net->part_w, net->part_b);
-  hipLaunchKernelGGL(lexp::k_sum_chunks, dim3((9 * CO * CI + 255) / 256), dim3(256), 0, s, net->part_w, chunks,
+  const int chunks = lexp_net::grad_chunks(W, H);
+  hipLaunchKernelGGL((lexp::k_conv_bwd_w<CI, CO>), dim3(chunks), dim3(256), 0, s, g, net->act[l], W, H,
+                     net->part_w, net->part_b);
+  hipLaunchKernelGGL(lexp::k_sum_chunks, dim3((9 * CO * CI + 63) / 64), dim3(256), 0, s, net->part_w, chunks,
                      9 * CO * CI, net->grad + net->w_off[l]);
-  hipLaunchKernelGGL(lexp::k_sum_chunks, dim3(1), dim3(256), 0, s, net->part_b, chunks, CO,
+  hipLaunchKernelGGL(lexp::k_sum_chunks, dim3((CO + 63) / 64), dim3(256), 0, s, net->part_b, chunks, CO,
                      net->grad + net->b_off[l]);
 }
 
@@ -2168,7 +2172,7 @@ lexp_status net_init(lexp_net* net, int32_t max_width, int32_t max_height, uint6
   net->n_prm = off;
   net->n_w16 = off16;
   const size_t n = (size_t)max_width * max_height;
-  const size_t chunks = (n + lexp_net::kChunk - 1) / lexp_net::kChunk;
+  const size_t chunks = (size_t)lexp_net::grad_chunks(max_width, max_height);
   HIP_TRY(hipMalloc((void**)&net->prm, sizeof(float) * off));
   HIP_TRY(hipMalloc((void**)&net->grad, sizeof(float) * off));
   HIP_TRY(hipMalloc((void**)&net->mom1, sizeof(float) * off));

@@ -116,6 +116,10 @@ constexpr int kCutBytesCompact = 28;
 constexpr int kConvSegs = 2;
 constexpr int kConvRows = 8;
 constexpr int kConvThreads = 64 * kConvRows;
+// The weight gradients take a layer's pixels in chunks of kWgRows rows by
+// kWgTiles tiles of 32 columns (one partial sum per chunk).
+constexpr int kWgRows = 4;
+constexpr int kWgTiles = 8;
 __global__ void k_net_input(const float4* left4, const float4* right4, const float4* labels, int W, int H,
                             double disp_max, uint16_t* x0);
 template <int CI, int CO, bool LAST>
@@ -125,8 +129,7 @@ template <int CI, int CO>
 __global__ void k_conv_bwd_x(const uint16_t* g, const uint16_t* wt16, const uint16_t* x, int W, int H,
                              uint16_t* gp);
 template <int CI, int CO>
-__global__ void k_conv_bwd_w(const uint16_t* g, const uint16_t* x, int W, int H, int chunk_px, float* part_w,
-                             float* part_b);
+__global__ void k_conv_bwd_w(const uint16_t* g, const uint16_t* x, int W, int H, float* part_w, float* part_b);
 __global__ void k_sum_chunks(const float* part, int n_chunks, int n, float* out);
 __global__ void k_net_loss(const float* y, const float4* target, int W, int H, double disp_max, uint16_t* g,
                            double* part);

@@ -1,8 +1,8 @@
 // Learned proposal network on CDNA4 (gfx950): five 3x3 convolutions as
 // implicit GEMMs on the BF16 matrix cores (FP32 sums), their backward
 // passes, the plane loss and Adam.  The forward and input-gradient products
-// use v_mfma_f32_16x16x32_bf16 (K = 32 per instruction), the weight
-// gradients v_mfma_f32_16x16x16_bf16.
+// and weight-gradient products use v_mfma_f32_16x16x32_bf16 (K = 32 per
+// instruction).
 //
 // Layout: activations and gradients pixel-major (index (v W + u) C + c), BF16;
 // the last layer's output FP32; weights [tap][out][in] (tap = 3 ky + kx,
@@ -10,10 +10,9 @@
 // [tap][in][out] for the backward-data products.
 //
 // One matrix instruction computes one 16 x 16 block of a product.
-// Operand fragments (checked on the device): for K = 16, lane l holds
-// A[l % 16][4 (l/16) + i] and B[4 (l/16) + i][l % 16] for i < 4; for K = 32,
-// A[l % 16][8 (l/16) + i] and B[8 (l/16) + i][l % 16] for i < 8; both give
-// D[4 (l/16) + i][l % 16].
+// Operand fragments (checked on the device): lane l holds
+// A[l % 16][8 (l/16) + i] and B[8 (l/16) + i][l % 16] for i < 8 and gets
+// D[4 (l/16) + i][l % 16] for i < 4.
 //   forward     : M = 16 pixels of a row, N = output channels, K = 9 taps x
 //                 input channels, tap-major, in chunks of 32 (one tap of 32
 //                 channels, or two taps of 16, the last chunk then half
@@ -21,9 +20,9 @@
 //   backward x  : M = 16 pixels, N = input channels, K = 9 taps x output
 //                 channels (gradient at p - offset; four blocks per wave);
 //   backward w  : per tap, M = output channels, N = input channels, K = the
-//                 pixels of a chunk; chunk partial sums are added in chunk
-//                 order by a second kernel (the result does not depend on
-//                 scheduling).
+//                 pixels of a chunk, 32 columns of one row at a time; chunk
+//                 partial sums are added in chunk order by a second kernel
+//                 (the result does not depend on scheduling).
 // BF16 values are rounded to nearest even from FP32 (FP64 values through
 // FP32 first), at the points the network's training recipe fixes.
 #include <hip/hip_runtime.h>
@@ -36,7 +35,6 @@ namespace lexp {
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -45,7 +43,6 @@ __device__ inline uint16_t to_bf16(float x) {
   u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (finite values)
   return (uint16_t)(u >> 16);
 }
-__device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // Eight BF16 values from 16 aligned bytes (LDS).
 __device__ inline bf16x8 load8(const uint16_t* p) {
@@ -364,125 +361,203 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_bwd_x(const uint16_t* __r
   }
 }
 
-// Weight and bias gradients of one layer, partial sums per pixel chunk:
+// Weight and bias gradients of one layer, partial sums per chunk:
 // part_w[chunk][tap][o][i] = sum over the chunk's pixels p of g(p)[o]
-// x(p + offset(tap))[i]; part_b[chunk][o] (tap-0 workgroups) = sum of g(p)[o].
-// Grid (chunks, 9 taps).  The chunk goes through LDS in tiles of kTile
-// pixels (g and the shifted x, pixel-major, coalesced 16-byte loads, the next
-// tile's loads in flight during this tile's products); wave w takes the
-// 16-pixel blocks w, w+4, ... of the chunk, in order.
+// x(p + offset(tap))[i] (x zero outside the image); part_b[chunk][o] = sum of
+// g(p)[o].  A chunk is kWgRows image rows by kWgTiles tiles of 32 columns;
+// one workgroup (4 waves) per chunk, all nine taps.
+//
+// Products: per tap, M = output channels, N = input channels, K = 32 pixels
+// of one tile row (v_mfma_f32_16x16x32_bf16).  Both operands take 8
+// consecutive pixels of one channel per lane, so the tile goes to LDS
+// channel-major: g as gT[o][row][col], x as three copies xT[dx][i][row][col]
+// (rows from one above the tile to one below it, copy dx shifted by dx
+// columns), so that every fragment is one aligned 16-byte read.  Channel
+// strides of 68 and 100 words put the 16 channels of a fragment read in
+// distinct LDS banks.  Wave w takes input block nb = w % (CI/16) and the
+// taps tg, tg + TG, ... (tg = w / (CI/16), TG = 64 / CI), for every output
+// block; wave 0 also adds up g for the bias.  The next tile's global loads
+// are in flight while the current tile's products run.
 template <int CI, int CO>
 __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__ g, const uint16_t* __restrict__ x,
-                                                    int W, int H, int chunk_px, float* __restrict__ part_w,
+                                                    int W, int H, float* __restrict__ part_w,
                                                     float* __restrict__ part_b) {
-  constexpr int kTile = 256;
-  constexpr int kGS = CO + 8, kXS = CI + 8;  // LDS elements per pixel (16-byte aligned rows)
-  constexpr int kGP = kTile * CO / 8 / 256, kXP = kTile * CI / 8 / 256;  // 16-byte pieces per thread
-  __shared__ __align__(16) uint16_t gs[kTile * kGS];
-  __shared__ __align__(16) uint16_t xs[kTile * kXS];
-  __shared__ float red[4][CO * CI];
-  __shared__ float redb[4][CO];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int chunk = blockIdx.x, tap = blockIdx.y;
-  const int P = W * H;
-  const int p0 = chunk * chunk_px, p1 = min(p0 + chunk_px, P);
-  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-  const int m = lane & 15, kq = (lane >> 4) * 4;
-  uint4 gv[kGP], xv[kXP];
-  auto fetch = [&](int t0) {
+  constexpr int kR = kWgRows;
+  constexpr int kSG = kR * 32 + 8, kSX = (kR + 2) * 32 + 8;  // channel strides (elements)
+  constexpr int kNB = CI / 16, kMB = CO / 16, kTG = 4 / kNB, kTaps = (9 + kTG - 1) / kTG;
+  // staging pieces: a pair of adjacent pixels x 8 channels
+  constexpr int kGItems = kR * 16 * (CO / 8), kXItems = 3 * (kR + 2) * 16 * (CI / 8);
+  constexpr int kGPer = (kGItems + 255) / 256, kXPer = (kXItems + 255) / 256;
+  __shared__ __align__(16) uint16_t gT[CO * kSG];
+  __shared__ __align__(16) uint16_t xT[3 * CI * kSX];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int m = lane & 15, grp = lane >> 4;
+  const int nb = wv % kNB, tg = wv / kNB;
+  const int n_tiles = (W + 31) / 32, n_groups = (n_tiles + kWgTiles - 1) / kWgTiles;
+  const int chunk = blockIdx.x;
+  const int v0 = (chunk / n_groups) * kR;
+  const int t_begin = (chunk % n_groups) * kWgTiles, t_end = min(t_begin + kWgTiles, n_tiles);
+  // two tiles' staging registers: a tile's loads are issued two tiles ahead
+  struct Stage {
+    uint4 gv[kGPer][2], xv[kXPer][2];
+  };
+  Stage st[2];
+  auto fetch = [&](Stage& S, int u0) {
 #pragma unroll
-    for (int k = 0; k < kGP; ++k) {
-      const int piece = threadIdx.x + k * 256;
-      const int p = t0 + piece / (CO / 8), c8 = piece % (CO / 8);
-      gv[k] = p < p1 ? *reinterpret_cast<const uint4*>(g + (size_t)p * CO + c8 * 8) : make_uint4(0u, 0u, 0u, 0u);
+    for (int k = 0; k < kGPer; ++k) {
+      const int it = (int)threadIdx.x + k * 256;
+      const int pp = it % 16, c8 = (it / 16) % (CO / 8), r = it / (16 * (CO / 8));
+      const int v = v0 + r;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int u = u0 + 2 * pp + e;
+        S.gv[k][e] = make_uint4(0u, 0u, 0u, 0u);
+        if (it < kGItems && u < W && v < H)
+          S.gv[k][e] = *reinterpret_cast<const uint4*>(g + ((size_t)v * W + u) * CO + c8 * 8);
+      }
     }
 #pragma unroll
-    for (int k = 0; k < kXP; ++k) {
-      const int piece = threadIdx.x + k * 256;
-      const int p = t0 + piece / (CI / 8), c8 = piece % (CI / 8);
-      const int u = p % W, v = p / W;
-      const int xx = u + dx, yy = v + dy;
-      const bool in = p < p1 && xx >= 0 && xx < W && yy >= 0 && yy < H;
-      xv[k] = in ? *reinterpret_cast<const uint4*>(x + ((size_t)yy * W + xx) * CI + c8 * 8)
-                 : make_uint4(0u, 0u, 0u, 0u);
+    for (int k = 0; k < kXPer; ++k) {
+      const int it = (int)threadIdx.x + k * 256;
+      const int pp = it % 16, c8 = (it / 16) % (CI / 8), rest = it / (16 * (CI / 8));
+      const int r = rest % (kR + 2), d = rest / (kR + 2);
+      const int v = v0 - 1 + r;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int u = u0 + 2 * pp + e + d - 1;
+        S.xv[k][e] = make_uint4(0u, 0u, 0u, 0u);
+        if (it < kXItems && u >= 0 && u < W && v >= 0 && v < H)
+          S.xv[k][e] = *reinterpret_cast<const uint4*>(x + ((size_t)v * W + u) * CI + c8 * 8);
+      }
     }
   };
-  f32x4 acc[CO / 16][CI / 16];
+  // a pixel pair's 8 channels as 8 words (channel j of both pixels), channel-major
+  auto put = [](uint16_t* base, int stride, const uint4 (&pv)[2]) {
+    const uint32_t a[4] = {pv[0].x, pv[0].y, pv[0].z, pv[0].w}, b[4] = {pv[1].x, pv[1].y, pv[1].z, pv[1].w};
 #pragma unroll
-  for (int mb = 0; mb < CO / 16; ++mb)
+    for (int q = 0; q < 4; ++q) {
+      *reinterpret_cast<uint32_t*>(base + (2 * q) * stride) = (a[q] & 0xffffu) | (b[q] << 16);
+      *reinterpret_cast<uint32_t*>(base + (2 * q + 1) * stride) = (a[q] >> 16) | (b[q] & 0xffff0000u);
+    }
+  };
+  // the staged tile into LDS, between barriers (the previous tile's fragments are read first)
+  auto stage = [&](const Stage& S) {
+    __syncthreads();
 #pragma unroll
-    for (int nb = 0; nb < CI / 16; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float bsum[CO / 16];
-#pragma unroll
-  for (int mb = 0; mb < CO / 16; ++mb) bsum[mb] = 0.f;
-  fetch(p0);
-  for (int t0 = p0; t0 < p1; t0 += kTile) {
-    __syncthreads();  // the previous tile's fragments are read
-#pragma unroll
-    for (int k = 0; k < kGP; ++k) {
-      const int piece = threadIdx.x + k * 256;
-      *reinterpret_cast<uint4*>(gs + (piece / (CO / 8)) * kGS + (piece % (CO / 8)) * 8) = gv[k];
+    for (int k = 0; k < kGPer; ++k) {
+      const int it = (int)threadIdx.x + k * 256;
+      if (it < kGItems) {
+        const int pp = it % 16, c8 = (it / 16) % (CO / 8), r = it / (16 * (CO / 8));
+        put(gT + (size_t)(c8 * 8) * kSG + r * 32 + 2 * pp, kSG, S.gv[k]);
+      }
     }
 #pragma unroll
-    for (int k = 0; k < kXP; ++k) {
-      const int piece = threadIdx.x + k * 256;
-      *reinterpret_cast<uint4*>(xs + (piece / (CI / 8)) * kXS + (piece % (CI / 8)) * 8) = xv[k];
+    for (int k = 0; k < kXPer; ++k) {
+      const int it = (int)threadIdx.x + k * 256;
+      if (it < kXItems) {
+        const int pp = it % 16, c8 = (it / 16) % (CI / 8), rest = it / (16 * (CI / 8));
+        const int r = rest % (kR + 2), d = rest / (kR + 2);
+        put(xT + (size_t)(d * CI + c8 * 8) * kSX + r * 32 + 2 * pp, kSX, S.xv[k]);
+      }
     }
     __syncthreads();
-    if (t0 + kTile < p1) fetch(t0 + kTile);
-    for (int bl = wave; bl < kTile / 16 && t0 + bl * 16 < p1; bl += 4) {
-      // this lane's four pixels of the block (zero past the chunk)
-      bf16x4 a[CO / 16], b[CI / 16];
+  };
+  f32x4 acc[kTaps][kMB];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int px = bl * 16 + kq + i;
+  for (int q = 0; q < kTaps; ++q)
 #pragma unroll
-        for (int mb = 0; mb < CO / 16; ++mb) {
-          const uint16_t gq = gs[px * kGS + mb * 16 + m];
-          a[mb][i] = (short)gq;
-          if (tap == 0) bsum[mb] += from_bf16(gq);
-        }
+    for (int mb = 0; mb < kMB; ++mb) acc[q][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum[kMB];
 #pragma unroll
-        for (int nb = 0; nb < CI / 16; ++nb) b[nb][i] = (short)xs[px * kXS + nb * 16 + m];
+  for (int mb = 0; mb < kMB; ++mb) bsum[mb] = 0.f;
+  auto products = [&]() {
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      bf16x8 a[kMB];
+#pragma unroll
+      for (int mb = 0; mb < kMB; ++mb) a[mb] = load8(gT + (size_t)(mb * 16 + m) * kSG + r * 32 + grp * 8);
+      if (wv == 0) {
+#pragma unroll
+        for (int mb = 0; mb < kMB; ++mb)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) bsum[mb] += (float)a[mb][j];
       }
-      // A[o][pixel] and B[pixel][i]: lane m is the row of A and the column of B
 #pragma unroll
-      for (int mb = 0; mb < CO / 16; ++mb)
+      for (int q = 0; q < kTaps; ++q) {
+        const int tap = tg + q * kTG;
+        if (tap < 9) {
+          const int dy = tap / 3 - 1, d = tap % 3;
+          const bf16x8 b = load8(xT + (size_t)(d * CI + nb * 16 + m) * kSX + (r + 1 + dy) * 32 + grp * 8);
 #pragma unroll
-        for (int nb = 0; nb < CI / 16; ++nb)
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+          for (int mb = 0; mb < kMB; ++mb)
+            acc[q][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b, acc[q][mb], 0, 0, 0);
+        }
+      }
+    }
+  };
+  const int nt = t_end - t_begin;
+  if (nt > 0) fetch(st[0], t_begin * 32);
+  if (nt > 1) fetch(st[1], (t_begin + 1) * 32);
+  for (int q = 0; q < nt; q += 2) {
+    stage(st[0]);
+    if (q + 2 < nt) fetch(st[0], (t_begin + q + 2) * 32);
+    products();
+    if (q + 1 < nt) {
+      stage(st[1]);
+      if (q + 3 < nt) fetch(st[1], (t_begin + q + 3) * 32);
+      products();
     }
   }
+  // D[4 grp + i][m] of block (mb, nb): output channel mb 16 + 4 grp + i, input nb 16 + m
 #pragma unroll
-  for (int mb = 0; mb < CO / 16; ++mb)
+  for (int q = 0; q < kTaps; ++q) {
+    const int tap = tg + q * kTG;
+    if (tap < 9) {
 #pragma unroll
-    for (int nb = 0; nb < CI / 16; ++nb)
+      for (int mb = 0; mb < kMB; ++mb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) red[wave][(mb * 16 + kq + i) * CI + nb * 16 + m] = acc[mb][nb][i];
-  if (tap == 0) {
+        for (int i = 0; i < 4; ++i)
+          part_w[(((size_t)chunk * 9 + tap) * CO + mb * 16 + grp * 4 + i) * CI + nb * 16 + m] = acc[q][mb][i];
+    }
+  }
+  if (wv == 0) {
 #pragma unroll
-    for (int mb = 0; mb < CO / 16; ++mb) {
+    for (int mb = 0; mb < kMB; ++mb) {
       float s = bsum[mb];
       s += __shfl_xor(s, 16);
       s += __shfl_xor(s, 32);
-      if (lane < 16) redb[wave][mb * 16 + lane] = s;
+      if (lane < 16) part_b[(size_t)chunk * CO + mb * 16 + lane] = s;
     }
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < CO * CI; e += 256)
-    part_w[((size_t)chunk * 9 + tap) * CO * CI + e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
-  if (tap == 0)
-    for (int e = threadIdx.x; e < CO; e += 256)
-      part_b[(size_t)chunk * CO + e] = ((redb[0][e] + redb[1][e]) + redb[2][e]) + redb[3][e];
 }
 
-// Sum of the chunk partials in chunk order: out[e] = sum_c part[c * n + e].
-__global__ void k_sum_chunks(const float* __restrict__ part, int n_chunks, int n, float* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  float s = 0.f;
-  for (int c = 0; c < n_chunks; ++c) s += part[(size_t)c * n + e];
-  out[e] = s;
+// Sum of the chunk partials: out[e] = sum over chunks c of part[c n + e].
+// Wave s of a workgroup adds the chunks c = s mod 4 in order (loads in
+// batches of 16, one memory round trip per batch), then the four sums are
+// added in wave order: a fixed order, so the result does not depend on
+// scheduling.  64 elements per workgroup of 256 threads.
+__global__ __launch_bounds__(256) void k_sum_chunks(const float* __restrict__ part, int n_chunks, int n,
+                                                    float* __restrict__ out) {
+  constexpr int kBatch = 16;
+  __shared__ float red[4][64];
+  const int s = threadIdx.x >> 6, e = blockIdx.x * 64 + (threadIdx.x & 63);
+  float acc = 0.f;
+  if (e < n) {
+    for (int c0 = s; c0 < n_chunks; c0 += 4 * kBatch) {
+      float v[kBatch];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int c = c0 + 4 * k;
+        v[k] = c < n_chunks ? part[(size_t)c * n + e] : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k)
+        if (c0 + 4 * k < n_chunks) acc += v[k];
+    }
+  }
+  red[s][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (s == 0 && e < n) out[e] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
 }
 
 // Plane loss of the output and its gradient (FP64): for every pixel p the
@@ -587,8 +662,8 @@ template __global__ void k_conv_bwd_x<32, 32>(const uint16_t*, const uint16_t*, 
                                               uint16_t*);
 template __global__ void k_conv_bwd_x<32, 16>(const uint16_t*, const uint16_t*, const uint16_t*, int, int,
                                               uint16_t*);
-template __global__ void k_conv_bwd_w<16, 32>(const uint16_t*, const uint16_t*, int, int, int, float*, float*);
-template __global__ void k_conv_bwd_w<32, 32>(const uint16_t*, const uint16_t*, int, int, int, float*, float*);
-template __global__ void k_conv_bwd_w<32, 16>(const uint16_t*, const uint16_t*, int, int, int, float*, float*);
+template __global__ void k_conv_bwd_w<16, 32>(const uint16_t*, const uint16_t*, int, int, float*, float*);
+template __global__ void k_conv_bwd_w<32, 32>(const uint16_t*, const uint16_t*, int, int, float*, float*);
+template __global__ void k_conv_bwd_w<32, 16>(const uint16_t*, const uint16_t*, int, int, float*, float*);
 
 }  // namespace lexp
