@@ -21,7 +21,7 @@
 //                 channels (gradient at p - offset; four blocks per wave);
 //   backward w  : per tap, M = output channels, N = input channels, K = the
 //                 pixels of a chunk, 32 columns of one row at a time; chunk
-//                 partial sums are added in chunk order by a second kernel
+//                 partial sums are added in a fixed order by a second kernel
 //                 (the result does not depend on scheduling).
 // BF16 values are rounded to nearest even from FP32 (FP64 values through
 // FP32 first), at the points the network's training recipe fixes.
