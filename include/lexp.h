@@ -81,7 +81,7 @@ typedef struct {
  *                              lexp_create are (left, right) for both views.
  *   graph                    : lexp_optimize: 1 = the device work of each step of a
  *                              part (items copy, cost kernel, graph terms, device
- *                              max-flow, copy back) is captured once per split of
+ *                              max-flow) is captured once per split of
  *                              its group into a HIP graph and replayed for every
  *                              candidate step (the device/host split of each level
  *                              is tuned in the first iteration only, then kept, so
@@ -154,7 +154,7 @@ typedef struct {
   int64_t expand_calls;     /* group steps (one batch of disjoint expansions) */
   double host_cut_ms;       /* host max-flow time, or with the device cut the host time after
                                the cut (label mirror, candidates), wall, summed over steps */
-  double host_wait_ms;      /* time the host waited for device terms */
+  double host_wait_ms;      /* time the host waited for the device's terms or cuts */
   double host_enqueue_ms;   /* lexp_optimize: host time queueing device work (copies, launches) */
   double host_update_ms;    /* lexp_optimize: host time queueing label updates after the cuts */
   double host_cut_level_ms[4]; /* lexp_optimize: host_cut_ms by grid level */
