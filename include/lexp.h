@@ -154,7 +154,8 @@ typedef struct {
   int64_t expand_calls;     /* group steps (one batch of disjoint expansions) */
   double host_cut_ms;       /* host max-flow time, or with the device cut the host time after
                                the cut (label mirror, candidates), wall, summed over steps */
-  double host_wait_ms;      /* time the host waited for the device's terms or cuts */
+  double host_wait_ms;      /* time the host waited for the device's terms or cuts (terms in two
+                               launches: the wait for the first, plus a worker's for the second) */
   double host_enqueue_ms;   /* lexp_optimize: host time queueing device work (copies, launches) */
   double host_update_ms;    /* lexp_optimize: host time queueing label updates after the cuts */
   double host_cut_level_ms[4]; /* lexp_optimize: host_cut_ms by grid level */

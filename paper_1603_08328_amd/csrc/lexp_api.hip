@@ -198,6 +198,11 @@ struct lexp_ctx {
     PinBuf<uint8_t> h_x;
     PinBuf<unsigned char> h_res;
     hipEvent_t ready = nullptr;
+    // host path: the terms of the first `split` regions (the larger ones) come
+    // from a launch of their own, followed by `half`, so the host pool starts
+    // on them while the rest are written (0: one launch)
+    hipEvent_t half = nullptr;
+    int split = 0;
     hipEvent_t cut0 = nullptr, cut1 = nullptr;  // around a timed device max-flow launch
     bool cut_timed = false;
     int cut_block = 0, cut_every = 0;  // shape of that launch
@@ -935,6 +940,7 @@ lexp_status lexp_destroy(lexp_ctx* c) {
     b.d_items.release(); b.d_phi.release(); b.d_terms.release();
     b.h_items.release(); b.h_terms.release(); b.h_x.release(); b.h_res.release();
     if (b.ready) (void)hipEventDestroy(b.ready);
+    if (b.half) (void)hipEventDestroy(b.half);
     if (b.cut0) (void)hipEventDestroy(b.cut0);
     if (b.cut1) (void)hipEventDestroy(b.cut1);
   }
@@ -1349,7 +1355,7 @@ void propose_item(Part& P, const StepArgs& a, int q, int step) {
 // graph terms (and the device cut), all queued on the stream; the terms (or
 // the device's cuts) land in the host's pinned buffers.
 lexp_status part_device_work(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairDev* d_pairs, const Tile* d_tiles,
-                             CutTuner* tuner, hipStream_t s) {
+                             CutTuner* tuner, bool capture, hipStream_t s) {
   const int n = (int)P.items.size();
   HIP_TRY(hipMemcpyAsync(B.d_items.p, B.h_items.p, sizeof(Item) * n, hipMemcpyHostToDevice, s));
   lexp_status st = LEXP_OK;
@@ -1359,6 +1365,7 @@ lexp_status part_device_work(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const P
                          s, P.bytes, P.n_px, n, P.pair_hint, P.direct);
     if (st) return st;
   }
+  B.split = 0;
   if (P.device_cut) {
     // the flag, the regions' status and their cuts go straight to the host's
     // pinned result buffer (no copy of their own)
@@ -1378,10 +1385,22 @@ lexp_status part_device_work(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const P
     B.cut_every = shape.every;
   } else {
     // the terms go straight to the host's pinned buffer (the kernel writes
-    // through PCIe; no copy of its own), flag first
-    hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, d_pairs, B.d_items.p,
+    // through PCIe; no copy of its own), flag first; outside graph capture
+    // in two launches, the first half of the regions' terms ready on their own
+    // (the writes are bound by the PCIe link, so the host cuts the larger
+    // regions while the rest are in flight)
+    const int split = !capture && n >= 8 ? n / 2 : 0;
+    const int n1 = split ? split : n;
+    hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n1), dim3(256), 0, s, d_pairs, B.d_items.p,
                        phi, B.h_terms.p + 1, B.h_terms.p);
     HIP_TRY(hipGetLastError());
+    if (split) {
+      HIP_TRY(hipEventRecord(B.half, s));
+      hipLaunchKernelGGL(lexp::k_graph_terms, dim3((P.max_px + 255) / 256, n - split), dim3(256), 0, s, d_pairs,
+                         B.d_items.p + split, phi, B.h_terms.p + 1, B.h_terms.p);
+      HIP_TRY(hipGetLastError());
+    }
+    B.split = split;
   }
   return LEXP_OK;
 }
@@ -1403,7 +1422,7 @@ lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairD
       if (!c->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
       const hipStream_t cs = c->capture_stream;
       HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      lexp_status st = part_device_work(c, P, B, d_pairs, d_tiles, nullptr, cs);
+      lexp_status st = part_device_work(c, P, B, d_pairs, d_tiles, nullptr, true, cs);
       hipGraph_t g = nullptr;
       const hipError_t e = hipStreamEndCapture(cs, &g);
       if (st) {
@@ -1420,8 +1439,9 @@ lexp_status enqueue_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const PairD
       c->stats.graphs_captured += 1;
     }
     HIP_TRY(hipGraphLaunch(P.graph, s));
+    B.split = 0;
   } else {
-    lexp_status st = part_device_work(c, P, B, d_pairs, d_tiles, tuner, s);
+    lexp_status st = part_device_work(c, P, B, d_pairs, d_tiles, tuner, false, s);
     if (st) return st;
   }
   HIP_TRY(hipEventRecord(B.ready, s));
@@ -1440,9 +1460,12 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
                         const PairDev* d_pairs, CutTuner* tuner, hipStream_t s) {
   const int n = (int)P.items.size();
   const bool dev = P.device_cut;
+  // host path in two launches: regions [0, split) are ready with B.half, the
+  // rest with B.ready (the first worker to reach one of them waits for it)
+  const int split = dev ? 0 : B.split;
   lexp::ThreadPool& pool = pool_of(c);
   const auto t0 = std::chrono::steady_clock::now();
-  HIP_TRY(hipEventSynchronize(B.ready));
+  HIP_TRY(hipEventSynchronize(split ? B.half : B.ready));
   const auto t1 = std::chrono::steady_clock::now();
   if (B.cut_timed && tuner) {
     float ms = 0.f;
@@ -1450,8 +1473,8 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
     tuner->report(B.cut_block, B.cut_every, ms);
     B.cut_timed = false;
   }
-  const int flag = dev ? reinterpret_cast<const int*>(B.h_res.p)[0] : B.h_terms.p[0];
-  if (flag) return fail(LEXP_EINVAL, "binary-problem term exceeds 2^30 quanta (parameters too large)");
+  const char* overflow = "binary-problem term exceeds 2^30 quanta (parameters too large)";
+  if (dev ? reinterpret_cast<const int*>(B.h_res.p)[0] : B.h_terms.p[0]) return fail(LEXP_EINVAL, "%s", overflow);
   const int nf = c->dp.nf;
   const int* terms = B.h_terms.p + 1;
   // the cut, in the host's pinned buffer, which the label update reads in place
@@ -1472,6 +1495,24 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
   // per-worker CPU time of the solves (summed into the statistics below)
   double solve_ms[lexp::kMaxPoolThreads] = {};
   int64_t solves[lexp::kMaxPoolThreads] = {};
+  // the second launch's regions: 0 not yet waited for, 1 a worker waits, 2
+  // ready, 3 failed (device error or overflow: every later region is skipped)
+  std::atomic<int> rest{0};
+  hipError_t rest_err = hipSuccess;
+  double rest_wait_ms = 0.0;
+  auto wait_rest = [&]() -> bool {
+    int st = rest.load(std::memory_order_acquire);
+    if (st == 0 && rest.compare_exchange_strong(st, 1, std::memory_order_acq_rel)) {
+      const auto w0 = std::chrono::steady_clock::now();
+      rest_err = hipEventSynchronize(B.ready);
+      rest_wait_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
+      st = rest_err == hipSuccess && B.h_terms.p[0] == 0 ? 2 : 3;
+      rest.store(st, std::memory_order_release);
+      return st == 2;
+    }
+    while ((st = rest.load(std::memory_order_acquire)) == 1) std::this_thread::yield();
+    return st == 2;
+  };
   auto host_solve = [&](int i, int worker) {
     const auto s0 = std::chrono::steady_clock::now();
     const Item& it = P.items[i];
@@ -1485,6 +1526,7 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
   if (dev && !host_cut.empty())
     pool.parallel_for((int)host_cut.size(), [&](int q, int worker) { host_solve(host_cut[q], worker); });
   pool.parallel_for(n, [&](int i, int worker) {
+    if (split && i >= split && !wait_rest()) return;
     const Item& it = P.items[i];
     if (it.rw > 0 && it.rh > 0) {
       if (!dev) host_solve(i, worker);
@@ -1499,13 +1541,18 @@ lexp_status finish_part(lexp_ctx* c, Part& P, lexp_ctx::PartBuf& B, const StepAr
     }
     if (next_step >= 0) propose_item(P, a, i, next_step);
   });
+  if (split) {
+    if (rest.load() == 0) wait_rest();  // (no worker reached the second launch's regions)
+    if (rest_err != hipSuccess) return fail(LEXP_EDEVICE, "%s", hipGetErrorString(rest_err));
+    if (B.h_terms.p[0]) return fail(LEXP_EINVAL, "%s", overflow);
+  }
   const auto t2 = std::chrono::steady_clock::now();
   hipLaunchKernelGGL(lexp::k_apply, dim3((P.max_px + 255) / 256, n), dim3(256), 0, s, d_pairs, B.d_items.p, xs,
                      P.phi_ext ? P.phi_ext : B.d_phi.p);
   HIP_TRY(hipGetLastError());
   const auto t3 = std::chrono::steady_clock::now();
   c->stats.expand_calls += 1;
-  c->stats.host_wait_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+  c->stats.host_wait_ms += std::chrono::duration<double, std::milli>(t1 - t0).count() + rest_wait_ms;
   c->stats.host_cut_ms += std::chrono::duration<double, std::milli>(t2 - t1).count();
   c->stats.host_cut_level_ms[a.level] += std::chrono::duration<double, std::milli>(t2 - t1).count();
   for (int w = 0; w < pool.size(); ++w) {
@@ -1935,6 +1982,8 @@ lexp_status optimize_run(RunPair* pairs, int np, const lexp_schedule* sch, doubl
     HIP_TRY(B.h_x.ensure((size_t)max_px));
     HIP_TRY(B.h_res.ensure(4 + 4 * max_items + (size_t)max_px));
     if (!B.ready) HIP_TRY(hipEventCreateWithFlags(&B.ready, hipEventDisableTiming));
+    if (!B.half) HIP_TRY(hipEventCreateWithFlags(&B.half, hipEventDisableTiming));
+    B.split = 0;
     if (!B.cut0) HIP_TRY(hipEventCreate(&B.cut0));
     if (!B.cut1) HIP_TRY(hipEventCreate(&B.cut1));
     B.cut_timed = false;
