@@ -56,7 +56,11 @@ typedef struct {
 /* Parameters of the energy (Sec. 3.2) and of the guided filter.
  *   alpha, tau_col, tau_grad : raw cost weights and truncations, Eq. (9)
  *   gf_radius                : radius r of the regression window W'_k of
- *                              Eq. (7), (2r+1)^2 pixels; 1 <= r <= 32
+ *                              Eq. (7), (2r+1)^2 pixels; 1 <= r, and r <= 28 on
+ *                              MI355X: a tile of the fused cost kernel holds its
+ *                              rings and rows of M (1 + 4r columns and more) in
+ *                              one workgroup's 160 KB of LDS; lexp_create rejects
+ *                              a larger r (LEXP_EINVAL)
  *   gf_eps                   : e of Eq. (7) (0.01^2 in the paper)
  *   lambda, tau_dis, w_floor,
  *   gamma                    : smoothness weight, truncation, lower bound

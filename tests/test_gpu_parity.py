@@ -243,6 +243,33 @@ def test_unary_small_image_windows_larger_than_image(r):
         assert_cost_close(g, P.ora.unary_region(rc, lab).reshape(-1), P.rho_max, f"r={r} {rc}")
 
 
+def test_unary_maximum_radius():
+    """r = 28, the largest window the fused kernel takes on MI355X (57 x 57
+    windows, M = R dilated by 56; a tile's rings and M rows in one workgroup's
+    160 KB of LDS leave strips of two columns): costs of interior,
+    border-clipped, ragged and 1x1 regions against the oracle, and r = 29
+    rejected when the context is created.  The right image is the left one
+    shifted by 5 px, so the label d = 5 matches (low costs) and the others mix
+    matched, partly out-of-view and fully out-of-view samples."""
+    rng = np.random.default_rng(28)
+    h, w = 150, 190
+    left = texture(rng, h, w)
+    right = texture(rng, h, w)
+    right[:, :w - 5] = left[:, 5:]
+    with pytest.raises(L.LexpError):
+        L.lexp_create(base_params(w, h, 29), _cuda(left), _cuda(right))
+    P = Pair(params=base_params(w, h, 28), left=left, right=right)
+    rects = [(60, 50, 105, 95), (0, 0, 45, 45), (150, 110, 190, 150), (95, 70, 96, 71), (20, 100, 95, 150),
+             (0, 0, w, h)]
+    labs = [[0, 0, 5.0], [0.02, -0.01, 5.5], [0, 0, 5.0], [0.1, 0.05, 3.0], [0, 0, 1e4], [-0.05, 0.02, 8.0]]
+    got = _unary(P, rects, labs)
+    for rc, lab, g in zip(rects, labs, got):
+        ref = P.ora.unary_region(rc, lab).reshape(-1)
+        assert_cost_close(g, ref, P.rho_max, f"r=28 {rc}")
+    # the matching label costs well below rho_max inside the view
+    assert float(np.median(got[0])) < 0.5 * P.rho_max
+
+
 def test_guided_coeffs(lowres):
     """Coefficients (a_k, b_k) of Eq. (7) over R+, against the oracle's.
 
