@@ -484,6 +484,35 @@ def test_optimize_tiny_bit_identical_to_oracle(tiny):
     assert torch.equal(lab, lab2) and torch.equal(cost, cost2)
 
 
+def test_optimize_rejects_bad_schedules_and_leaves_state(tiny):
+    """Schedules outside the ranges the header states are refused before any
+    work is queued: the labels and costs keep their values."""
+    import ctypes
+    P = tiny
+    lab = torch.full((P.H, P.W, 4), 7.0, device="cuda")
+    cost = torch.full((P.H, P.W), 3.0, device="cuda")
+    lib = L.load_library()
+    e, t = np.zeros(3), np.zeros(3)
+
+    def run(field, value, index=None):
+        s = L.make_schedule([(5, 1, 3)], 2)
+        if index is None:
+            setattr(s, field, value)
+        else:
+            getattr(s, field)[index] = value
+        return lib.lexp_optimize(P.ctx.handle, ctypes.byref(s), ctypes.c_uint64(0), ctypes.c_void_p(lab.data_ptr()),
+                                 ctypes.c_void_p(cost.data_ptr()), e.ctypes.data, t.ctypes.data, None)
+
+    bad = [("n_levels", 0, None), ("n_levels", 5, None), ("iterations", -1, None), ("cell", 0, 0),
+           ("k_prop", -1, 0), ("k_rand", 64, 0), ("k_rans", -1, 0), ("tile_cols", 129, 0), ("tile_fill", -1, 0),
+           ("speculate", 2, None), ("batch_cycle", 2, None), ("learned", 2, None)]
+    for field, value, index in bad:
+        assert run(field, value, index) == L.LEXP_EINVAL, (field, value)
+    assert run("learned", 1, None) == L.LEXP_ESTATE  # no network set on the context
+    torch.cuda.synchronize()
+    assert bool(torch.all(lab == 7.0)) and bool(torch.all(cost == 3.0))
+
+
 def test_optimize_tiny_with_ransac_bit_identical_to_oracle(tiny):
     """Alg. 1 with the RANSAC proposer enabled (one propagation, one RANSAC
     and two refinement steps per cell): labels bit-identical to the oracle's
