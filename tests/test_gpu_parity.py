@@ -229,6 +229,12 @@ def test_invalid_arguments_raise(tiny):
     bad = dict(P.p, gf_radius=0)
     with pytest.raises(L.LexpError):
         L.lexp_create(bad, _cuda(P.left), _cuda(P.right))
+    # every parameter range the header states
+    for change in (dict(gf_radius=33), dict(neighbours=6), dict(gf_eps=0.0), dict(gamma=0.0), dict(alpha=1.5),
+                   dict(lam=-1.0), dict(tau_dis=65.0, lam=1.0), dict(tau_col=2e4), dict(disp_max=float("inf")),
+                   dict(host_threads=65), dict(device_cut=2), dict(view=2), dict(graph=2)):
+        with pytest.raises(L.LexpError):
+            L.lexp_create(dict(P.p, **change), _cuda(P.left), _cuda(P.right))
 
 
 @pytest.mark.parametrize("r", [1, 2, 5, 9])
