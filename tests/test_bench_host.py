@@ -64,3 +64,29 @@ def test_weighted_rate_of_a_uniform_sample():
               {c: 300 * (k + 1) for k, (c, _, _) in enumerate(wl["grids"])})
     rate = bench._weighted(sample, 450, 375, wl)[0]
     assert rate == pytest.approx(1.0 / per / 1e9, rel=1e-12)
+
+
+def test_committed_profiles_name_the_current_kernel_sources():
+    """Every committed profile summary that records the hash of the kernel
+    source it was taken on names the source as it stands (a profile of an
+    older kernel would describe code that is no longer built)."""
+    import glob
+    import hashlib
+    import re
+
+    def h16(rel):
+        with open(os.path.join(ROOT, "paper_1603_08328_amd", "csrc", rel), "rb") as fh:
+            return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+    fused, cut = h16("lexp_kernels.hip"), h16("lexp_cut.hip")
+    seen = 0
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*"))):
+        with open(path) as fh:
+            text = fh.read()
+        for m in re.finditer(r"Kernel source( \(lexp_cut\.hip\))? sha256\[:16\] ([0-9a-f]{16})", text):
+            assert m.group(2) == (cut if m.group(1) else fused), os.path.basename(path)
+            seen += 1
+        for m in re.finditer(r"kernel_source_sha256_16: ([0-9a-f]{16})", text):
+            assert m.group(1) == fused, os.path.basename(path)
+            seen += 1
+    assert seen >= 5
