@@ -490,6 +490,25 @@ def test_optimize_tiny_bit_identical_to_oracle(tiny):
     assert torch.equal(lab, lab2) and torch.equal(cost, cost2)
 
 
+@pytest.mark.parametrize("device_cut", [0, 1])
+def test_optimize_four_neighbourhood_bit_identical_to_oracle(device_cut):
+    """The 4-neighbourhood (forward neighbours (1,0) and (0,1) only): a whole
+    run at 64x48, every cut on the host or part of them on the device, gives
+    the oracle's labels bit for bit."""
+    pair = make_workload_pair("tiny-64x48")
+    P = Pair(params=dict(params_for("tiny-64x48"), neighbours=4, device_cut=device_cut), left=pair.left,
+             right=pair.right)
+    lab = torch.zeros((P.H, P.W, 4), device="cuda")
+    cost = torch.zeros((P.H, P.W), device="cuda")
+    e, _ = L.lexp_optimize(P.ctx, [(5, 1, 3)], 2, 0, lab, cost)
+    olab, ocost, oe, _ = P.ora.optimize(0, [(5, 1, 3)], 2)
+    g3 = lab.cpu().numpy()[..., :3]
+    assert np.array_equal(g3.view(np.uint32), olab.view(np.uint32)), \
+        f"{np.any(g3 != olab, axis=-1).sum()} pixels differ"
+    assert np.allclose(e, oe, rtol=1e-5)
+    assert_cost_close(cost.cpu().numpy(), ocost, P.rho_max, "final costs")
+
+
 def test_optimize_rejects_bad_schedules_and_leaves_state(tiny):
     """Schedules outside the ranges the header states are refused before any
     work is queued: the labels and costs keep their values."""
