@@ -509,6 +509,30 @@ def test_optimize_four_neighbourhood_bit_identical_to_oracle(device_cut):
     assert_cost_close(cost.cpu().numpy(), ocost, P.rho_max, "final costs")
 
 
+@pytest.mark.parametrize("device_cut", [0, 1])
+def test_optimize_paper_radius_two_levels_bit_identical_to_oracle(device_cut):
+    """The paper's filter radius r = 20 (41 x 41 windows) with two grid levels
+    (5- and 15-px cells, the second with 45 x 45 regions split into strips),
+    a whole 2-iteration run on a 120x90 scene: the oracle's labels bit for
+    bit, every cut on the host or part of them on the device."""
+    from synth.scenes import make_pair
+    from synth import PAPER_PARAMS
+    pair = make_pair(width=120, height=90, n_planar=5, n_quadric=1, disp_max=24.0, c_range=(3.0, 21.0),
+                     hole_frac=0.02, seed=5)
+    prm = dict(PAPER_PARAMS, width=120, height=90, disp_max=24.0, gf_radius=20, device_cut=device_cut)
+    P = Pair(params=prm, left=pair.left, right=pair.right)
+    grids = [(5, 1, 3), (15, 1, 3)]
+    lab = torch.zeros((P.H, P.W, 4), device="cuda")
+    cost = torch.zeros((P.H, P.W), device="cuda")
+    e, _ = L.lexp_optimize(P.ctx, grids, 2, 0, lab, cost)
+    olab, ocost, oe, _ = P.ora.optimize(0, grids, 2)
+    g3 = lab.cpu().numpy()[..., :3]
+    assert np.array_equal(g3.view(np.uint32), olab.view(np.uint32)), \
+        f"{np.any(g3 != olab, axis=-1).sum()} pixels differ"
+    assert np.allclose(e, oe, rtol=1e-5)
+    assert_cost_close(cost.cpu().numpy(), ocost, P.rho_max, "final costs")
+
+
 def test_optimize_rejects_bad_schedules_and_leaves_state(tiny):
     """Schedules outside the ranges the header states are refused before any
     work is queued: the labels and costs keep their values."""
