@@ -533,6 +533,31 @@ def test_optimize_paper_radius_two_levels_bit_identical_to_oracle(device_cut):
     assert_cost_close(cost.cpu().numpy(), ocost, P.rho_max, "final costs")
 
 
+@pytest.mark.parametrize("device_cut", [0, 1])
+def test_optimize_three_levels_bit_identical_to_oracle(device_cut):
+    """The 450x375 workload's three grid levels (5-, 15- and 25-px cells, r =
+    20) on a 200x150 scene, one iteration from the random labels: the oracle's
+    labels bit for bit, every cut on the host or (one host thread, so that the
+    larger groups are split) part of them on the device."""
+    from synth.scenes import make_pair
+    from synth import PAPER_PARAMS
+    pair = make_pair(width=200, height=150, n_planar=6, n_quadric=1, disp_max=30.0, c_range=(4.0, 26.0),
+                     hole_frac=0.02, seed=6)
+    prm = dict(PAPER_PARAMS, width=200, height=150, disp_max=30.0, gf_radius=20, device_cut=device_cut,
+               host_threads=1 if device_cut else 0)
+    P = Pair(params=prm, left=pair.left, right=pair.right)
+    grids = [(5, 1, 3), (15, 1, 3), (25, 1, 3)]
+    lab = torch.zeros((P.H, P.W, 4), device="cuda")
+    cost = torch.zeros((P.H, P.W), device="cuda")
+    e, _ = L.lexp_optimize(P.ctx, grids, 1, 0, lab, cost)
+    olab, ocost, oe, _ = P.ora.optimize(0, grids, 1)
+    g3 = lab.cpu().numpy()[..., :3]
+    assert np.array_equal(g3.view(np.uint32), olab.view(np.uint32)), \
+        f"{np.any(g3 != olab, axis=-1).sum()} pixels differ"
+    assert np.allclose(e, oe, rtol=1e-5)
+    assert_cost_close(cost.cpu().numpy(), ocost, P.rho_max, "final costs")
+
+
 def test_optimize_rejects_bad_schedules_and_leaves_state(tiny):
     """Schedules outside the ranges the header states are refused before any
     work is queued: the labels and costs keep their values."""
