@@ -51,6 +51,29 @@ def test_batch_cycle_tiny_bit_identical_to_oracle(tiny):
     assert not np.array_equal(plain, olab)
 
 
+def test_batch_cycle_three_levels_bit_identical_to_oracle():
+    """The batch cycle with the 450x375 workload's three grid levels (5-, 15-
+    and 25-px cells, r = 20; the regions of the larger cells cut into strips in
+    the one launch per group step) on a 200x150 scene, one iteration from the
+    random labels: the oracle's batch cycle, bit for bit."""
+    from oracle import Oracle
+    from synth import PAPER_PARAMS
+    from synth.scenes import make_pair
+    pair = make_pair(width=200, height=150, n_planar=6, n_quadric=1, disp_max=30.0, c_range=(4.0, 26.0),
+                     hole_frac=0.02, seed=6)
+    prm = dict(PAPER_PARAMS, width=200, height=150, disp_max=30.0, gf_radius=20)
+    grids = [(5, 1, 3), (15, 1, 3), (25, 1, 3)]
+    ctx = L.lexp_create(prm, _cuda(pair.left), _cuda(pair.right))
+    lab, cost, e = _run(ctx, prm, grids, 1, 0, batch_cycle=True)
+    ctx.close()
+    ora = Oracle(prm, pair.left, pair.right)
+    olab, ocost, oe, _ = ora.optimize(0, grids, 1, batch_cycle=True)
+    g3 = lab[..., :3]
+    assert np.array_equal(g3.view(np.uint32), olab.view(np.uint32)), f"{np.any(g3 != olab, axis=-1).sum()} differ"
+    assert np.allclose(e, oe, rtol=1e-5)
+    assert np.all(np.abs(cost - ocost) <= 1e-4 * np.maximum(np.abs(ocost), ora.rho_max))
+
+
 def test_batch_cycle_lowres_device_and_host_cuts_and_pairs_identical():
     """450x375, one iteration of the batch cycle: every cut on the host, the
     device max-flow at every level (one host thread), and the pair batched
