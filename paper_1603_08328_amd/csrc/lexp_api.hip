@@ -1202,7 +1202,7 @@ lexp_status net_forward(lexp_net* net, lexp_ctx* c, const float* labels, hipStre
 template <int CI, int CO>
 void net_weight_grad(lexp_net* net, int l, const uint16_t* g, int W, int H, hipStream_t s) {
   const int chunks = lexp_net::grad_chunks(W, H);
-  hipLaunchKernelGGL((lexp::k_conv_bwd_w<CI, CO>), dim3(chunks), dim3(256), 0, s, g, net->act[l], W, H,
+  hipLaunchKernelGGL((lexp::k_conv_bwd_w<CI, CO>), dim3(chunks), dim3(lexp::kWgThreads), 0, s, g, net->act[l], W, H,
                      net->part_w, net->part_b);
   hipLaunchKernelGGL(lexp::k_sum_chunks, dim3((9 * CO * CI + 63) / 64), dim3(256), 0, s, net->part_w, chunks,
                      9 * CO * CI, net->grad + net->w_off[l]);

@@ -120,6 +120,7 @@ constexpr int kConvThreads = 64 * kConvRows;
 // kWgTiles tiles of 32 columns (one partial sum per chunk).
 constexpr int kWgRows = 4;
 constexpr int kWgTiles = 8;
+constexpr int kWgThreads = 1024;  // 16 waves: the staging of a tile spread over more lanes
 __global__ void k_net_input(const float4* left4, const float4* right4, const float4* labels, int W, int H,
                             double disp_max, uint16_t* x0);
 template <int CI, int CO, bool LAST>

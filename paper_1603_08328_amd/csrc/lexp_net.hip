@@ -365,7 +365,7 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_bwd_x(const uint16_t* __r
 // part_w[chunk][tap][o][i] = sum over the chunk's pixels p of g(p)[o]
 // x(p + offset(tap))[i] (x zero outside the image); part_b[chunk][o] = sum of
 // g(p)[o].  A chunk is kWgRows image rows by kWgTiles tiles of 32 columns;
-// one workgroup (4 waves) per chunk, all nine taps.
+// one workgroup (kWgThreads / 64 waves) per chunk, all nine taps.
 //
 // Products: per tap, M = output channels, N = input channels, K = 32 pixels
 // of one tile row (v_mfma_f32_16x16x32_bf16).  Both operands take 8
@@ -375,19 +375,20 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_bwd_x(const uint16_t* __r
 // columns), so that every fragment is one aligned 16-byte read.  Channel
 // strides of 68 and 100 words put the 16 channels of a fragment read in
 // distinct LDS banks.  Wave w takes input block nb = w % (CI/16) and the
-// taps tg, tg + TG, ... (tg = w / (CI/16), TG = 64 / CI), for every output
-// block; wave 0 also adds up g for the bias.  The next tile's global loads
+// taps tg, tg + TG, ... (tg = w / (CI/16), TG = waves / (CI/16); waves with
+// tg >= 9 only stage), for every output block; wave 0 also adds up g for the
+// bias.  The next tile's global loads
 // are in flight while the current tile's products run.
 template <int CI, int CO>
-__global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__ g, const uint16_t* __restrict__ x,
+__global__ __launch_bounds__(kWgThreads) void k_conv_bwd_w(const uint16_t* __restrict__ g, const uint16_t* __restrict__ x,
                                                     int W, int H, float* __restrict__ part_w,
                                                     float* __restrict__ part_b) {
   constexpr int kR = kWgRows;
   constexpr int kSG = kR * 32 + 8, kSX = (kR + 2) * 32 + 8;  // channel strides (elements)
-  constexpr int kNB = CI / 16, kMB = CO / 16, kTG = 4 / kNB, kTaps = (9 + kTG - 1) / kTG;
+  constexpr int kNB = CI / 16, kMB = CO / 16, kTG = kWgThreads / 64 / kNB, kTaps = (9 + kTG - 1) / kTG;
   // staging pieces: a pair of adjacent pixels x 8 channels
   constexpr int kGItems = kR * 16 * (CO / 8), kXItems = 3 * (kR + 2) * 16 * (CI / 8);
-  constexpr int kGPer = (kGItems + 255) / 256, kXPer = (kXItems + 255) / 256;
+  constexpr int kGPer = (kGItems + kWgThreads - 1) / kWgThreads, kXPer = (kXItems + kWgThreads - 1) / kWgThreads;
   __shared__ __align__(16) uint16_t gT[CO * kSG];
   __shared__ __align__(16) uint16_t xT[3 * CI * kSX];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -405,7 +406,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
   auto fetch = [&](Stage& S, int u0) {
 #pragma unroll
     for (int k = 0; k < kGPer; ++k) {
-      const int it = (int)threadIdx.x + k * 256;
+      const int it = (int)threadIdx.x + k * kWgThreads;
       const int pp = it % 16, c8 = (it / 16) % (CO / 8), r = it / (16 * (CO / 8));
       const int v = v0 + r;
 #pragma unroll
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
     }
 #pragma unroll
     for (int k = 0; k < kXPer; ++k) {
-      const int it = (int)threadIdx.x + k * 256;
+      const int it = (int)threadIdx.x + k * kWgThreads;
       const int pp = it % 16, c8 = (it / 16) % (CI / 8), rest = it / (16 * (CI / 8));
       const int r = rest % (kR + 2), d = rest / (kR + 2);
       const int v = v0 - 1 + r;
@@ -445,7 +446,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kGPer; ++k) {
-      const int it = (int)threadIdx.x + k * 256;
+      const int it = (int)threadIdx.x + k * kWgThreads;
       if (it < kGItems) {
         const int pp = it % 16, c8 = (it / 16) % (CO / 8), r = it / (16 * (CO / 8));
         put(gT + (size_t)(c8 * 8) * kSG + r * 32 + 2 * pp, kSG, S.gv[k]);
@@ -453,7 +454,7 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(const uint16_t* __restrict__
     }
 #pragma unroll
     for (int k = 0; k < kXPer; ++k) {
-      const int it = (int)threadIdx.x + k * 256;
+      const int it = (int)threadIdx.x + k * kWgThreads;
       if (it < kXItems) {
         const int pp = it % 16, c8 = (it / 16) % (CI / 8), rest = it / (16 * (CI / 8));
         const int r = rest % (kR + 2), d = rest / (kR + 2);
